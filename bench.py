@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput of the Spectral Ewald k-space evaluation on one MI355X.
+
+One step = one full pass of the hot path on the device-resident inputs:
+bin/sort, spread (eq. 4.5), forward FFT, scaling + k-space energy (eq. 4.6),
+inverse FFT, gather of phi and F (eqs. 4.9, 4.12).  Workload: synthetic
+3-site water at liquid density, L = 100 A (100,200 atoms), xi = 0.3 A^-1,
+M = 96, P = 8 (relative rms force error of the method ~1e-5).  The headline
+value is FP32; the FP64 form at the same parameters is reported beside it.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SE k-space E+F atom-evals/s at rms force err 1e-5, FP32 vs FP64; %HBM peak"
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_work(stage, N, M, P, rs):
+    """Algorithmic work of one launch of a stage: (kind, amount).
+    Bytes for the grid passes and binning, flops for spread and gather."""
+    K = M // 2 + 1
+    grid, spec = M ** 3 * rs, M * M * K * 2 * rs
+    if stage == "bin_count":
+        return "bytes", N * 4 * rs + N * 8 + grid            # x, q in; keys out; grid zeroed
+    if stage == "bin_scatter":
+        return "bytes", N * 4 * rs + N * 8 + N * (4 * rs + 8)  # x, q, keys in; sorted out
+    if stage == "spread":
+        return "flops", N * 2 * P ** 3                     # a multiply and an add per point
+    if stage == "gather":
+        return "flops", N * 4 * P ** 3                     # two multiply-adds per point
+    if stage == "fft_x":
+        return "bytes", grid + spec
+    if stage == "ifft_x":
+        return "bytes", spec + grid
+    return "bytes", 2 * spec                               # fft_y, fft_z_scale, ifft_y
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    from paper_1712_04718_amd import SEPlan, _lib
+    from workloads import make_system
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    x, q, spec = make_system(args.workload)
+    N, L, xi, M, P = len(q), spec.L, spec.xi, spec.M, args.P
+    log(f"workload {args.workload}: N={N} L={L} xi={xi} M={M} P={P}")
+    lib = _lib.load()
+
+    out = {}
+    for dtype, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+        plan = SEPlan(M, P, L, xi, dtype=dtype, n_max=N, device=dev)
+        xt = torch.tensor(x, dtype=dtype, device=dev)
+        qt = torch.tensor(q, dtype=dtype, device=dev)
+        E = torch.empty((), dtype=torch.float64, device=dev)
+        phi = torch.empty(N, dtype=dtype, device=dev)
+        F = torch.empty(N, 3, dtype=dtype, device=dev)
+        ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (xt, qt, E, phi, F)]
+
+        def step():
+            s = torch.cuda.current_stream().cuda_stream
+            _lib.check(lib.se_plan_set_stream(plan._plan, ctypes.c_void_p(s)))
+            _lib.check(lib.se_kspace(plan._plan, N, *ptrs))
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_eager = e0.elapsed_time(e1) / args.steps
+
+        # the same step captured once in a HIP graph and replayed
+        g = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cap):
+            step()  # warm the capture stream
+        torch.cuda.current_stream().wait_stream(cap)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_graph = e0.elapsed_time(e1) / args.steps
+        log(f"{tag}: eager {ms_eager * 1e3:.1f} us/step, graph {ms_graph * 1e3:.1f} us/step")
+
+        # accuracy of this precision against the FP64 oracle (sampled particles)
+        from oracle import se_oracle as O
+        xo, qo = xt.double().cpu().numpy(), qt.double().cpu().numpy()
+        eta = O.se_eta(L, xi, M, P)
+        G = O.se_spread(xo, qo, L, M, P, xi, eta)
+        Eo, Phi = O.scale_and_energy(G, O.se_influence(L, xi, M, eta), L)
+        idx = np.random.default_rng(0).choice(N, size=2000, replace=False)
+        phio, Fo = O.se_gather(xo[idx], qo[idx], L, M, P, xi, eta, Phi)
+        Fg = F.double().cpu().numpy()[idx]
+        err_F = O.rel_rms(Fg, Fo)
+        err_E = abs(E.item() - Eo) / abs(Eo)
+
+        # per-kernel durations from the library's own events (separate plan)
+        tplan = SEPlan(M, P, L, xi, dtype=dtype, n_max=N, device=dev, timing=True)
+        tplan.kspace(xt, qt)
+        acc = {}
+        nrep = max(5, min(args.steps, 50))
+        for _ in range(nrep):
+            tplan.kspace(xt, qt)
+            for k, v in tplan.stage_times().items():
+                acc[k] = acc.get(k, 0.0) + v / nrep
+        out[tag] = dict(ms_eager=ms_eager, ms_graph=ms_graph, err_F=err_F, err_E=err_E,
+                        stages_ms=acc)
+        for t in (plan, tplan):
+            t.close()
+
+    # CPU baseline: the oracle as it stands, full workload, FP64
+    cpu = None
+    if not args.no_cpu:
+        from oracle import se_oracle as O
+        reps = args.cpu_reps
+        O.se_kspace(x[:100], q[:100], L, xi, M, P)  # load the library
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            O.se_kspace(x, q, L, xi, M, P)
+        dt = (time.perf_counter() - t0) / reps
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": N / dt, "unit": "atom-evals/s", "cores": cores, "kind": "oracle",
+               "sample": f"{reps} full FP64 evaluations of the same {N}-atom workload "
+                         f"(spread and FFT on one thread, gather on {cores} OpenMP threads)"}
+        log(f"oracle: {dt:.3f} s per evaluation")
+
+    f32 = out["f32"]
+    ms = f32["ms_graph"]
+    value = N / (ms * 1e-3)
+    stages = f32["stages_ms"]
+    dom = max(stages, key=stages.get)
+    kind, amount = kernel_work(dom, N, M, P, 4)
+    dur_s = stages[dom] * 1e-3
+    if kind == "bytes":
+        achieved = amount / dur_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        achieved = amount / dur_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS["f32"],
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["kernel_us"] = stages[dom] * 1e3
+
+    grid_passes = {}
+    for st in ("fft_x", "fft_y", "fft_z_scale", "ifft_y", "ifft_x"):
+        if st in stages:
+            _, b = kernel_work(st, N, M, P, 4)
+            grid_passes[st] = round(b / (stages[st] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+    f64 = out["f64"]
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "atom-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: 3-site water, {N} atoms, L={L} A, "
+                               f"xi={xi}, M={M}, P={P}, SE Gaussian window",
+                   "N": N, "L": L, "xi": xi, "M": M, "P": P, "mode": "hip-graph replay"},
+        "rms_force_err_vs_fp64_oracle": f32["err_F"],
+        "energy_rel_err_vs_fp64_oracle": f32["err_E"],
+        "eager": {"ms_per_step": f32["ms_eager"], "value": N / (f32["ms_eager"] * 1e-3)},
+        "fp64": {"value": N / (f64["ms_graph"] * 1e-3), "ms_per_step": f64["ms_graph"],
+                 "eager_ms_per_step": f64["ms_eager"],
+                 "rms_force_err_vs_fp64_oracle": f64["err_F"],
+                 "stages_us": {k: round(v * 1e3, 2) for k, v in f64["stages_ms"].items()}},
+        "fp32_over_fp64": f64["ms_graph"] / ms,
+        "stages_us": {k: round(v * 1e3, 2) for k, v in stages.items()},
+        "grid_pass_hbm_frac": grid_passes,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="water_L100")
+    ap.add_argument("--P", type=int, default=8)
+    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "slab decomposition is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

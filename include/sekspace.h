@@ -1,0 +1,167 @@
+/*
+ * sekspace.h — C ABI of the MI355X (gfx950) Spectral Ewald k-space library.
+ *
+ * Problem (paper section 1, eqs. 1.1-1.3): N point charges q_n at x_n in the
+ * periodic cube [0,L)^3.  The library evaluates the Fourier-space
+ * (long-range) parts of the Ewald sums, eqs. (1.5)-(1.7):
+ *     E   = (2 pi / L^3) sum_{k != 0} e^{-k^2/4xi^2} / k^2 |S(k)|^2,
+ *     phi = dE/dq,   F = -dE/dx,
+ * approximated by the Spectral Ewald method (section 4, Algorithm 1, Table 2):
+ *   1. sort particles into tiles of the M^3 grid,
+ *   2. spread truncated Gaussians (eq. 4.5) with P^3 support,
+ *   3. forward 3D FFT,
+ *   4. scale by e^{-(1-eta) k^2 / 4 xi^2} / k^2 (eq. 4.6) and reduce E,
+ *   5. inverse 3D FFT,
+ *   6. gather phi (eq. 4.9) and F (eq. 4.12 read as F = -dE/dx).
+ * The SPME window (section 6, eqs. 6.1-6.3: cardinal B-splines of order p,
+ * influence function B(k) e^{-k^2/4xi^2}/k^2) is the second window behind the
+ * same calls.
+ *
+ * Units: Coulomb constant 1; multiply E, phi, F by e.g. 138.935 kJ mol^-1 nm
+ * e^-2 (section 5 remark) or 332.0637 kcal mol^-1 A e^-2 as needed.
+ *
+ * Conventions shared by every call
+ *   - All functions return se_status and never throw or abort.  Arguments are
+ *     checked on the host, synchronously, before anything is enqueued; on an
+ *     error nothing is enqueued and outputs are untouched.
+ *     se_last_error() returns a message for the last failing call on the
+ *     calling thread.
+ *   - Device pointers are HIP device memory on the plan's device.  Arrays are
+ *     contiguous and row-major: x[N][3] (AoS), q[N], phi[N], F[N][3], all of
+ *     the plan's dtype (float for SE_FP32, double for SE_FP64).  E is always
+ *     one double in device memory.
+ *   - The library never frees or retains caller memory beyond a call.
+ *   - Work is enqueued asynchronously on the plan's stream; calls return
+ *     without synchronising.  Calls on one plan must not overlap in time from
+ *     different host threads.
+ *   - Positions may lie outside [0,L): they are wrapped periodically
+ *     (section 1: the box is periodic).
+ *   - The k = 0 mode is always dropped (section 1); a non-neutral charge set
+ *     is accepted and no neutralising-background term is added, so that
+ *     dE/dq = phi holds for any q.
+ *   - NaN or Inf inputs are not detected; they propagate into the outputs.
+ */
+#ifndef SEKSPACE_H
+#define SEKSPACE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SE_OK = 0,
+    SE_ERR_ARG = 1,          /* bad scalar argument, null pointer, N > n_max */
+    SE_ERR_GRID = 2,         /* M not even, not 2^a 3^b 5^c, out of range, or M < P */
+    SE_ERR_ETA = 3,          /* Gaussian shape eta outside (0,1) (section 4) */
+    SE_ERR_UNSUPPORTED = 4,  /* window/precision/P combination not built */
+    SE_ERR_WORKSPACE = 5,    /* device allocation failed */
+    SE_ERR_HIP = 6,          /* HIP runtime error while enqueueing */
+    SE_ERR_STATE = 7         /* se_gather/se_backward before any se_forward */
+} se_status;
+
+typedef enum { SE_WINDOW_GAUSSIAN = 0, SE_WINDOW_BSPLINE = 1 } se_window;
+typedef enum { SE_FP32 = 0, SE_FP64 = 1 } se_dtype;
+
+/* se_params.flags */
+#define SE_FLAG_ADD_SELF 1u  /* add the self terms of eqs. (1.5)-(1.6):
+                                phi += -2 xi q / sqrt(pi), E += -(xi/sqrt(pi)) sum q^2 */
+#define SE_FLAG_TIMING 2u    /* record a HIP event pair around every kernel launch
+                                (on the plan's stream) for se_plan_stage_times    */
+
+/* Kernel stages of one evaluation, in launch order (se_plan_stage_times). */
+enum {
+    SE_STAGE_BIN_COUNT = 0,  /* zero grid, tile histogram, tile offsets       */
+    SE_STAGE_BIN_SCATTER,    /* write particles in tile order                */
+    SE_STAGE_SPREAD,         /* step 2                                        */
+    SE_STAGE_FFT_X,          /* step 3, real-to-complex along x              */
+    SE_STAGE_FFT_Y,          /* step 3, along y                              */
+    SE_STAGE_FFT_Z_SCALE,    /* steps 3-5 along z: FFT, scale + energy, IFFT */
+    SE_STAGE_IFFT_Y,         /* step 5, along y                              */
+    SE_STAGE_IFFT_X,         /* step 5, complex-to-real along x              */
+    SE_STAGE_GATHER,         /* step 6 (se_gather or se_backward)            */
+    SE_NUM_STAGES
+};
+
+typedef struct {
+    int M;          /* grid points per side; even, 2^a 3^b 5^c, 8 <= M <= 512 */
+    int P;          /* SE: Gaussian support points per side, even, 4..16;
+                       SPME: B-spline order p, 3..8.  P <= M.              */
+    double L;       /* box side, > 0                                         */
+    double xi;      /* Ewald splitting parameter, > 0                        */
+    double c;       /* SE shape constant of eq. (5.2); <= 0 selects 0.95     */
+    int window;     /* se_window                                             */
+    int dtype;      /* se_dtype: precision of inputs, outputs and arithmetic */
+    unsigned flags; /* SE_FLAG_*                                             */
+} se_params;
+
+typedef struct se_plan se_plan;
+
+/* Human-readable name of a status code (static storage). */
+const char *se_status_string(se_status s);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *se_last_error(void);
+
+/* Host only, no GPU needed.  Gaussian shape parameter of section 4 and
+ * eq. (5.2): eta = (2 w xi / m)^2 with w = P h / 2, h = L / M, m = c sqrt(pi P),
+ * i.e. eta = P L^2 xi^2 / (c^2 pi M^2).  Validates *prm like se_plan_create
+ * (except device checks); for the B-spline window *eta is set to 0. */
+se_status se_params_check(const se_params *prm, double *eta);
+
+/* Host only, no GPU needed.  Device bytes a plan for up to n_max particles
+ * allocates (grids, spectra, sorted particles, tables). */
+se_status se_plan_workspace_size(const se_params *prm, int n_max, size_t *bytes);
+
+/* Create a plan on the current HIP device for up to n_max particles.
+ * hip_stream is a hipStream_t (NULL = the default stream).  The plan owns
+ * its device workspace (allocated here, freed by se_plan_destroy). */
+se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream,
+                         se_plan **out);
+
+/* Change the stream later calls enqueue on. */
+se_status se_plan_set_stream(se_plan *plan, void *hip_stream);
+
+/* Read back the derived eta (0 for the B-spline window). */
+se_status se_plan_eta(const se_plan *plan, double *eta);
+
+/* Plans created with SE_FLAG_TIMING: wait for the last recorded launches
+ * and write the duration in milliseconds of each stage's most recent launch
+ * to ms[0..n-1] (stage order above; -1 for a stage not launched since the
+ * plan was created).  SE_ERR_STATE for plans without the flag. */
+se_status se_plan_stage_times(se_plan *plan, double *ms, int n);
+
+/* Release the plan and its workspace (synchronises its stream first). */
+se_status se_plan_destroy(se_plan *plan);
+
+/* Steps 1-5 of Algorithm 1: sort, spread, FFT, scale, energy, inverse FFT.
+ * x: device [N][3], q: device [N] (plan dtype); E_dev: device double, set to
+ * the k-space energy (plus the self energy with SE_FLAG_ADD_SELF).
+ * 0 <= N <= n_max (N = 0 gives E = 0).  The scaled grid and the sorted
+ * particles stay in the plan until the next se_forward on it; x and q are
+ * not referenced after the call's work completes. */
+se_status se_forward(se_plan *plan, int N, const void *x, const void *q,
+                     double *E_dev);
+
+/* Step 6 for the particles of the last se_forward: phi (device [N]) and F
+ * (device [N][3]) in the caller's particle order; either may be NULL. */
+se_status se_gather(se_plan *plan, void *phi, void *F);
+
+/* se_forward followed by se_gather. */
+se_status se_kspace(se_plan *plan, int N, const void *x, const void *q,
+                    double *E_dev, void *phi, void *F);
+
+/* Adjoint of se_forward for reverse-mode differentiation, reusing the stored
+ * scaled grid (no re-spreading, no FFT):
+ *     grad_x = gE * dE/dx = -gE * F,   grad_q = gE * dE/dq = gE * phi,
+ * with gE read from device memory (one double).  grad_x device [N][3],
+ * grad_q device [N]; either may be NULL. */
+se_status se_backward(se_plan *plan, const double *gE_dev, void *grad_x,
+                      void *grad_q);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEKSPACE_H */

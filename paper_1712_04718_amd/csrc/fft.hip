@@ -1,0 +1,411 @@
+// Steps 3-5 of Algorithm 1: forward 3D FFT of the real grid, multiplication
+// by the influence function with the k-space energy, inverse 3D FFT.
+//
+// Five passes over a half spectrum C[z][y][kx], kx = 0..M/2 (row length
+// K = M/2 + 1), all built on one batched Stockham FFT held in LDS:
+//   x_r2c : pairs of real rows packed as one complex row, FFT, split into two
+//           half spectra;
+//   y_fwd : FFT along y of B adjacent kx columns of one z-plane;
+//   z     : FFT along z of B adjacent (y,kx) pencils, scale by the
+//           influence function w(k) (eq. 4.6 for SE, eq. 6.2 for SPME)
+//           times 4 pi / L^3, accumulate the energy
+//             E = 1/2 sum_k mu(kx) w(k) |G^(k)|^2   (FP64),
+//           mu = 1 on kx = 0 and kx = M/2 and 2 elsewhere (Hermitian half),
+//           then the inverse FFT along z; the last block adds the partial
+//           energies in a fixed order;
+//   y_inv : inverse FFT along y;
+//   x_c2r : two half spectra rebuilt into one Hermitian-packed complex row,
+//           inverse FFT, real and imaginary parts are the two real rows.
+// Forward transforms use e^{-i k.x}, inverse ones e^{+i k.x}, both
+// unnormalised; the inverse is conj(FFT(conj(.))).
+//
+// In LDS a batch of B pencils of length M is stored element-major
+// (element k of pencil b at k*B + b) so that the B threads working on the
+// same butterfly index of different pencils touch consecutive addresses.
+#include "se_common.hpp"
+
+namespace sek {
+namespace {
+
+extern __shared__ __align__(16) unsigned char f_smem[];
+
+template <typename C> __device__ inline C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename C> __device__ inline C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C> __device__ inline C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename C> __device__ inline C cconj(C a) { a.y = -a.y; return a; }
+// multiply by -i
+template <typename C> __device__ inline C cmul_mi(C a) { C r; r.x = a.y; r.y = -a.x; return r; }
+
+// Forward DFTs of small prime-power sizes (X_k = sum_n x_n e^{-2 pi i nk/R}).
+template <typename R, typename C> __device__ inline void dft2(C *v) {
+  const C a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+template <typename R, typename C> __device__ inline void dft3(C *v) {
+  const R s3 = static_cast<R>(0.86602540378443864676);  // sin(2 pi / 3)
+  const C t1 = cadd(v[1], v[2]);
+  C t2;
+  t2.x = v[0].x - R(0.5) * t1.x;
+  t2.y = v[0].y - R(0.5) * t1.y;
+  const C d = csub(v[1], v[2]);
+  C t3;  // -i sin(2pi/3) (v1 - v2)
+  t3.x = s3 * d.y;
+  t3.y = -s3 * d.x;
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(t2, t3);
+  v[2] = csub(t2, t3);
+}
+template <typename R, typename C> __device__ inline void dft4(C *v) {
+  const C a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  const C c = cadd(v[1], v[3]), d = cmul_mi(csub(v[1], v[3]));
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, d);
+  v[3] = csub(b, d);
+}
+template <typename R, typename C> __device__ inline void dft5(C *v) {
+  const R c1 = static_cast<R>(0.30901699437494742410);   // cos(2 pi/5)
+  const R c2 = static_cast<R>(-0.80901699437494742410);  // cos(4 pi/5)
+  const R s1 = static_cast<R>(0.95105651629515357212);   // sin(2 pi/5)
+  const R s2 = static_cast<R>(0.58778525229247312917);   // sin(4 pi/5)
+  const C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+  const C t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+  C a1, a2, b1, b2;
+  a1.x = v[0].x + c1 * t1.x + c2 * t2.x;  a1.y = v[0].y + c1 * t1.y + c2 * t2.y;
+  a2.x = v[0].x + c2 * t1.x + c1 * t2.x;  a2.y = v[0].y + c2 * t1.y + c1 * t2.y;
+  b1.x = s1 * t3.x + s2 * t4.x;           b1.y = s1 * t3.y + s2 * t4.y;
+  b2.x = s2 * t3.x - s1 * t4.x;           b2.y = s2 * t3.y - s1 * t4.y;
+  v[0] = cadd(v[0], cadd(t1, t2));
+  const C mb1 = cmul_mi(b1), mb2 = cmul_mi(b2);
+  v[1] = cadd(a1, mb1);
+  v[4] = csub(a1, mb1);
+  v[2] = cadd(a2, mb2);
+  v[3] = csub(a2, mb2);
+}
+template <typename R, typename C> __device__ inline void dft8(C *v) {
+  const R r2 = static_cast<R>(0.70710678118654752440);
+  // two radix-4 halves on even/odd samples, then combine
+  C e[4] = {v[0], v[2], v[4], v[6]};
+  C o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<R, C>(e);
+  dft4<R, C>(o);
+  // twiddles e^{-2 pi i k / 8}, k = 0..3
+  C w1; w1.x = r2 * (o[1].x + o[1].y); w1.y = r2 * (o[1].y - o[1].x);
+  const C w2 = cmul_mi(o[2]);
+  C w3; w3.x = r2 * (o[3].y - o[3].x); w3.y = -r2 * (o[3].x + o[3].y);
+  v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], w1);   v[5] = csub(e[1], w1);
+  v[2] = cadd(e[2], w2);   v[6] = csub(e[2], w2);
+  v[3] = cadd(e[3], w3);   v[7] = csub(e[3], w3);
+}
+
+// One radix stage of the Stockham autosort FFT on B pencils:
+//   in[(j + r M/R) B + b] -> twiddle by w^{r k}, k = j mod Ns, w = e^{-2pi i/(Ns R)}
+//   -> R-point DFT -> out[((j/Ns) Ns R + k + r Ns) B + b].
+template <typename R, int RAD>
+__device__ inline void stockham_stage(const cplx_t<R> *in, cplx_t<R> *out, int M, int B,
+                                      int Ns, const cplx_t<R> *__restrict__ tw) {
+  using C = cplx_t<R>;
+  const int nb = M / RAD;
+  const int total = nb * B;
+  const int tstep = M / (Ns * RAD);
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int b = t % B, j = t / B;
+    const int k = j % Ns;
+    C v[RAD];
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[r] = in[(j + r * nb) * B + b];
+    if (k != 0) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) v[r] = cmul(v[r], tw[r * k * tstep]);
+    }
+    if constexpr (RAD == 2) dft2<R, C>(v);
+    if constexpr (RAD == 3) dft3<R, C>(v);
+    if constexpr (RAD == 4) dft4<R, C>(v);
+    if constexpr (RAD == 5) dft5<R, C>(v);
+    if constexpr (RAD == 8) dft8<R, C>(v);
+    const int dst = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) out[(dst + r * Ns) * B + b] = v[r];
+  }
+}
+
+// Forward FFT of B pencils held in buf0; returns the buffer with the result.
+template <typename R>
+__device__ cplx_t<R> *fft_batch(cplx_t<R> *buf0, cplx_t<R> *buf1, int B, const FftPlan &pl,
+                                const cplx_t<R> *__restrict__ tw) {
+  cplx_t<R> *in = buf0, *out = buf1;
+  int Ns = 1;
+  for (int s = 0; s < pl.nstages; ++s) {
+    const int rad = pl.radix[s];
+    switch (rad) {
+      case 2: stockham_stage<R, 2>(in, out, pl.M, B, Ns, tw); break;
+      case 3: stockham_stage<R, 3>(in, out, pl.M, B, Ns, tw); break;
+      case 4: stockham_stage<R, 4>(in, out, pl.M, B, Ns, tw); break;
+      case 5: stockham_stage<R, 5>(in, out, pl.M, B, Ns, tw); break;
+      default: stockham_stage<R, 8>(in, out, pl.M, B, Ns, tw); break;
+    }
+    __syncthreads();
+    cplx_t<R> *t = in; in = out; out = t;
+    Ns *= rad;
+  }
+  return in;
+}
+
+// ---------------------------------------------------------------- x passes
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl, int B,
+            const cplx_t<R> *__restrict__ tw) {
+  using C = cplx_t<R>;
+  const int M = pl.M, K = M / 2 + 1;
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  const long long nrows = static_cast<long long>(M) * M;
+  const long long row0 = static_cast<long long>(blockIdx.x) * 2 * B;
+  // row r of the batch goes to pencil r/2, real part for even r, imag for odd
+  for (int i = threadIdx.x; i < 2 * B * M; i += blockDim.x) {
+    const int r = i / M, xk = i - r * M;
+    const long long gr = row0 + r;
+    const R v = gr < nrows ? grid[gr * M + xk] : R(0);
+    R *slot = reinterpret_cast<R *>(&b0[xk * B + (r >> 1)]);
+    slot[r & 1] = v;
+  }
+  __syncthreads();
+  const C *Z = fft_batch<R>(b0, b1, B, pl, tw);
+  // Z = FFT(r1 + i r2): R1[k] = (Z[k] + conj Z[M-k]) / 2, R2[k] = (Z[k] - conj Z[M-k]) / 2i
+  for (int i = threadIdx.x; i < B * K; i += blockDim.x) {
+    const int b = i / K, k = i - b * K;
+    const long long gr = row0 + 2 * b;
+    if (gr >= nrows) continue;
+    const C zk = Z[k * B + b];
+    const C zm = Z[((M - k) % M) * B + b];
+    C r1, r2;
+    r1.x = R(0.5) * (zk.x + zm.x);
+    r1.y = R(0.5) * (zk.y - zm.y);
+    r2.x = R(0.5) * (zk.y + zm.y);
+    r2.y = R(-0.5) * (zk.x - zm.x);
+    spec[gr * K + k] = r1;
+    spec[(gr + 1) * K + k] = r2;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl, int B,
+            const cplx_t<R> *__restrict__ tw) {
+  using C = cplx_t<R>;
+  const int M = pl.M, K = M / 2 + 1;
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  const long long nrows = static_cast<long long>(M) * M;
+  const long long row0 = static_cast<long long>(blockIdx.x) * 2 * B;
+  // Z[k] = R1[k] + i R2[k] on 0..M/2 and conj(R1[M-k]) + i conj(R2[M-k]) above;
+  // stored conjugated for the inverse transform.
+  for (int i = threadIdx.x; i < B * K; i += blockDim.x) {
+    const int b = i / K, k = i - b * K;
+    const long long gr = row0 + 2 * b;
+    C r1, r2;
+    if (gr < nrows) {
+      r1 = spec[gr * K + k];
+      r2 = spec[(gr + 1) * K + k];
+    } else {
+      r1.x = r1.y = r2.x = r2.y = R(0);
+    }
+    C z;
+    z.x = r1.x - r2.y;
+    z.y = -(r1.y + r2.x);
+    b0[k * B + b] = z;
+    if (k > 0 && k < M - k) {
+      C zc;
+      zc.x = r1.x + r2.y;
+      zc.y = -(r2.x - r1.y);
+      b0[(M - k) * B + b] = zc;
+    }
+  }
+  __syncthreads();
+  const C *Z = fft_batch<R>(b0, b1, B, pl, tw);
+  for (int i = threadIdx.x; i < 2 * B * M; i += blockDim.x) {
+    const int r = i / M, xk = i - r * M;
+    const long long gr = row0 + r;
+    if (gr >= nrows) continue;
+    const C z = Z[xk * B + (r >> 1)];
+    grid[gr * M + xk] = (r & 1) ? -z.y : z.x;  // conj of the forward result
+  }
+}
+
+// ---------------------------------------------------------------- y passes
+
+template <typename R, bool INV>
+__global__ void __launch_bounds__(kThreads)
+k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int B, const cplx_t<R> *__restrict__ tw) {
+  using C = cplx_t<R>;
+  const int M = pl.M, K = M / 2 + 1;
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  const int kx0 = blockIdx.x * B;
+  const long long zoff = static_cast<long long>(blockIdx.y) * M * K;
+  for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
+    const int y = i / B, b = i - y * B;
+    C v;
+    if (kx0 + b < K) {
+      v = spec[zoff + static_cast<long long>(y) * K + kx0 + b];
+      if (INV) v = cconj(v);
+    } else {
+      v.x = v.y = R(0);
+    }
+    b0[i] = v;
+  }
+  __syncthreads();
+  const C *Z = fft_batch<R>(b0, b1, B, pl, tw);
+  for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
+    const int y = i / B, b = i - y * B;
+    if (kx0 + b < K) {
+      C v = Z[i];
+      if (INV) v = cconj(v);
+      spec[zoff + static_cast<long long>(y) * K + kx0 + b] = v;
+    }
+  }
+}
+
+// ------------------------------------------ z pass with scaling and energy
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int B, const cplx_t<R> *__restrict__ tw,
+              const double *__restrict__ axis_f, const double *__restrict__ axis_k2,
+              double wscale, double *__restrict__ epart, unsigned *__restrict__ done,
+              const double *__restrict__ qsq, double self_coef, double *__restrict__ E_out) {
+  using C = cplx_t<R>;
+  const int M = pl.M, K = M / 2 + 1;
+  const int npen = M * K;
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  const int c0 = blockIdx.x * B;
+  const long long zs = static_cast<long long>(M) * K;
+  for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
+    const int z = i / B, b = i - z * B;
+    C v;
+    if (c0 + b < npen) {
+      v = spec[z * zs + c0 + b];
+    } else {
+      v.x = v.y = R(0);
+    }
+    b0[i] = v;
+  }
+  __syncthreads();
+  C *Z = fft_batch<R>(b0, b1, B, pl, tw);
+  C *other = (Z == b0) ? b1 : b0;
+
+  double e = 0.0;
+  for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
+    const int kz = i / B, b = i - kz * B;
+    const int c = c0 + b;
+    C v = Z[i];
+    if (c < npen) {
+      const int ky = c / K, kx = c - ky * K;
+      const double k2 = axis_k2[kx] + axis_k2[ky] + axis_k2[kz];
+      const double w = (kx == 0 && ky == 0 && kz == 0)
+                           ? 0.0
+                           : wscale * axis_f[kx] * axis_f[ky] * axis_f[kz] / k2;
+      const double mu = (kx == 0 || 2 * kx == M) ? 1.0 : 2.0;
+      const double re = static_cast<double>(v.x), im = static_cast<double>(v.y);
+      e += 0.5 * mu * w * (re * re + im * im);
+      const R wr = static_cast<R>(w);
+      v.x = v.x * wr;  // conjugated for the inverse transform
+      v.y = -(v.y * wr);
+    } else {
+      v.x = v.y = R(0);
+    }
+    Z[i] = v;  // holds conj(w * G^)
+  }
+  __syncthreads();
+  const C *Y = fft_batch<R>(Z, other, B, pl, tw);
+  for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
+    const int z = i / B, b = i - z * B;
+    if (c0 + b < npen) spec[z * zs + c0 + b] = cconj(Y[i]);
+  }
+
+  // energy: block sum, then the last block adds all partials in order
+  __shared__ double red[kThreads];
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+    epart[blockIdx.x] = red[0];
+    __threadfence();
+    is_last = (atomicAdd(done, 1u) == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double s = 0.0;
+  for (int b = threadIdx.x; b < static_cast<int>(gridDim.x); b += kThreads)
+    s += __hip_atomic_load(&epart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double E = red[0];
+    if (self_coef != 0.0) E += self_coef * (*qsq);
+    *E_out = E;
+    *done = 0u;
+  }
+}
+
+template <typename R>
+hipError_t fft_impl(se_plan &p, double *E_dev) {
+  using C = cplx_t<R>;
+  const int M = p.prm.M, K = M / 2 + 1, B = p.fft_batch;
+  const size_t lds = 2 * sizeof(C) * M * B;
+  C *spec = static_cast<C *>(p.buf.spec);
+  const C *tw = static_cast<const C *>(p.buf.twiddle);
+  const int xblocks = (M * M + 2 * B - 1) / (2 * B);
+  stage_begin(p, SE_STAGE_FFT_X);
+  k_fft_x_r2c<R><<<xblocks, kThreads, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec,
+                                                     p.fft, B, tw);
+  stage_end(p, SE_STAGE_FFT_X);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 yg((K + B - 1) / B, M);
+  stage_begin(p, SE_STAGE_FFT_Y);
+  k_fft_y<R, false><<<yg, kThreads, lds, p.stream>>>(spec, p.fft, B, tw);
+  stage_end(p, SE_STAGE_FFT_Y);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const double self_coef = (p.prm.flags & SE_FLAG_ADD_SELF) ? -p.prm.xi / sqrt(M_PI) : 0.0;
+  stage_begin(p, SE_STAGE_FFT_Z_SCALE);
+  k_fft_z_scale<R><<<p.zfft_blocks, kThreads, lds, p.stream>>>(
+      spec, p.fft, B, tw, static_cast<const double *>(p.buf.axis_f),
+      static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks,
+      p.buf.done + 1, p.buf.qsq, self_coef, E_dev);
+  stage_end(p, SE_STAGE_FFT_Z_SCALE);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  stage_begin(p, SE_STAGE_IFFT_Y);
+  k_fft_y<R, true><<<yg, kThreads, lds, p.stream>>>(spec, p.fft, B, tw);
+  stage_end(p, SE_STAGE_IFFT_Y);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  stage_begin(p, SE_STAGE_IFFT_X);
+  k_fft_x_c2r<R><<<xblocks, kThreads, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), p.fft,
+                                                     B, tw);
+  stage_end(p, SE_STAGE_IFFT_X);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fft_forward_scale_inverse(se_plan &plan, double *E_dev) {
+  return plan.prm.dtype == SE_FP64 ? fft_impl<double>(plan, E_dev)
+                                   : fft_impl<float>(plan, E_dev);
+}
+
+}  // namespace sek

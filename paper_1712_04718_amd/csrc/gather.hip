@@ -1,0 +1,269 @@
+// Step 6 of Algorithm 1: gather the potential (SE eq. 4.9, SPME eq. 6.3)
+// and the force by analytic differentiation of the window (section 3.1;
+// eq. 4.12 read as F = -dE/dx):
+//   phi_m = sum_j Phi_j W_j(x_m),
+//   F_m   = -q_m sum_j Phi_j dW_j(x_m)/dx_m .
+// The same kernel serves the adjoint used for reverse-mode differentiation:
+// grad_q = gE phi and grad_x = -gE F, with gE read from device memory.
+//
+// One work-group per tile: the (T+S-1)^3 block of the scaled grid Phi that
+// the tile's particles touch is staged in LDS.  Each wave takes the tile's
+// particles in chunks:
+//   phase A: one lane per particle computes its window factors (and, for
+//            B-splines, their derivatives) into the wave's LDS area;
+//   phase B: lane (group, jx) owns the x-offset jx of one particle and sums
+//            over the S^2 (jy, jz) offsets; the S lanes of a particle are
+//            then combined in LDS.
+// FP32 sums are compensated (Kahan) at the y level and across lanes.
+#include "se_common.hpp"
+#include "window.hpp"
+
+namespace sek {
+namespace {
+
+extern __shared__ __align__(16) unsigned char h_smem[];
+
+template <typename R> struct Kahan {
+  R s = R(0), c = R(0);
+  __device__ inline void add(R v) {
+    const R y = v - c;
+    const R t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ inline R value() const { return s - c; }
+};
+
+// LDS layout: [tile block][reduction scratch][per wave: factors, anchors, indices]
+template <typename R, int WIN, int S, int T> struct GatherLds {
+  static constexpr int TS = T + S - 1;
+  static constexpr int CH = Chunk<S>::CH;
+  // SE: g (3S), offsets d (3), q; B-spline: g (3S), dg (3S), q
+  static constexpr int REC = (WIN == kGauss) ? 3 * S + 4 : 6 * S + 1;
+  static constexpr size_t BLK = sizeof(R) * ((TS * TS * TS + 3) & ~3);
+  static constexpr size_t RED = sizeof(R) * (kThreads / 64) * 64 * 4;
+  static constexpr size_t FAC = sizeof(R) * CH * REC;
+  static constexpr size_t IDX = 2 * sizeof(int) * CH;
+  static constexpr size_t TOTAL = BLK + RED + (kThreads / 64) * (FAC + IDX);
+};
+
+template <typename R, int WIN, int S, int T>
+__global__ void __launch_bounds__(kThreads)
+k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ sorted,
+         const int2 *__restrict__ meta, const int *__restrict__ offsets, int M, int ntx,
+         WindowConsts wc, const double *__restrict__ gscale, int mode, R self_coef,
+         R *__restrict__ out_pot, R *__restrict__ out_vec) {
+  using L = GatherLds<R, WIN, S, T>;
+  constexpr int TS = L::TS, CH = L::CH, REC = L::REC;
+  constexpr int GROUPS = Chunk<S>::GROUPS;
+  constexpr int OFF = Stencil<WIN, S>::OFF;
+  constexpr int NWAVES = kThreads / 64;
+
+  const int tile = blockIdx.x;
+  const int start = offsets[tile], end = offsets[tile + 1];
+  if (start == end) return;
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  R *blk = reinterpret_cast<R *>(h_smem);
+  R *wred = reinterpret_cast<R *>(h_smem + L::BLK) + wave * 64 * 4;
+  unsigned char *wbase = h_smem + L::BLK + L::RED + wave * (L::FAC + L::IDX);
+  R *fac = reinterpret_cast<R *>(wbase);
+  int *anc = reinterpret_cast<int *>(wbase + L::FAC);
+  int *org = anc + CH;
+
+  const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
+  const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
+  for (int i = tid; i < TS * TS * TS; i += kThreads) {
+    const int lz = i / (TS * TS), ly = (i / TS) % TS, lx = i % TS;
+    int gz = (bz + lz) % M, gy = (by + ly) % M, gx = (bx + lx) % M;
+    gz += gz < 0 ? M : 0;
+    gy += gy < 0 ? M : 0;
+    gx += gx < 0 ? M : 0;
+    blk[i] = phi_grid[(static_cast<long long>(gz) * M + gy) * M + gx];
+  }
+  __syncthreads();
+
+  const R scale = gscale ? static_cast<R>(*gscale) : R(1);
+  const int grp = lane / S, jx = lane - grp * S;
+  for (int base = start + wave * CH; base < end; base += NWAVES * CH) {
+    const int nval = min(CH, end - base);
+    // phase A
+    if (lane < nval) {
+      const SortedParticle<R> sp = sorted[base + lane];
+      const int2 mt = meta[base + lane];
+      R *f = fac + lane * REC;
+      R g[S], dg[S];
+      const R dd[3] = {sp.dx, sp.dy, sp.dz};
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        window_axis<R, WIN, S, WIN == kBspline>(dd[ax], wc, g, dg);
+#pragma unroll
+        for (int j = 0; j < S; ++j) f[ax * S + j] = g[j];
+        if constexpr (WIN == kBspline) {
+#pragma unroll
+          for (int j = 0; j < S; ++j) f[3 * S + ax * S + j] = dg[j];
+        } else {
+          f[3 * S + ax] = dd[ax];
+        }
+      }
+      f[REC - 1] = sp.q;
+      anc[lane] = mt.x;
+      org[lane] = mt.y;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // phase B
+    if (grp < GROUPS) {
+      for (int c = grp; c < nval; c += GROUPS) {
+        const R *f = fac + c * REC;
+        const int packed = anc[c];
+        const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
+        R gx, dgx, gy[S], dgy[S], gz[S], dgz[S];
+        gx = f[jx];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+          gy[j] = f[S + j];
+          gz[j] = f[2 * S + j];
+        }
+        if constexpr (WIN == kBspline) {
+          dgx = f[3 * S + jx];
+#pragma unroll
+          for (int j = 0; j < S; ++j) {
+            dgy[j] = f[4 * S + j];
+            dgz[j] = f[5 * S + j];
+          }
+        } else {
+          // d/dx_m of the Gaussian factor: 2 a h t_j g_j, t_j = j + OFF - d
+          const R dc = static_cast<R>(wc.dcoef);
+          dgx = dc * (static_cast<R>(jx + OFF) - f[3 * S + 0]) * gx;
+#pragma unroll
+          for (int j = 0; j < S; ++j) {
+            dgy[j] = dc * (static_cast<R>(j + OFF) - f[3 * S + 1]) * gy[j];
+            dgz[j] = dc * (static_cast<R>(j + OFF) - f[3 * S + 2]) * gz[j];
+          }
+        }
+        const R *col = blk + (az * TS + ay) * TS + ax + jx;
+        Kahan<R> s_pot, s_fy, s_fz;
+#pragma unroll
+        for (int jy = 0; jy < S; ++jy) {
+          R a0 = R(0), a1 = R(0);
+#pragma unroll
+          for (int jz = 0; jz < S; ++jz) {
+            const R v = col[(jz * TS + jy) * TS];
+            a0 += v * gz[jz];
+            a1 += v * dgz[jz];
+          }
+          s_pot.add(gy[jy] * a0);
+          s_fy.add(dgy[jy] * a0);
+          s_fz.add(gy[jy] * a1);
+        }
+        const R sp_v = s_pot.value();
+        R *mine = wred + lane * 4;
+        mine[0] = gx * sp_v;
+        mine[1] = dgx * sp_v;
+        mine[2] = gx * s_fy.value();
+        mine[3] = gx * s_fz.value();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (jx == 0) {
+          Kahan<R> t0, t1, t2, t3;
+          const R *g = wred + grp * S * 4;
+#pragma unroll
+          for (int l = 0; l < S; ++l) {
+            t0.add(g[4 * l + 0]);
+            t1.add(g[4 * l + 1]);
+            t2.add(g[4 * l + 2]);
+            t3.add(g[4 * l + 3]);
+          }
+          const R q = f[REC - 1];
+          const int orig = org[c];
+          const R pot = t0.value() + self_coef * q;
+          // potential-force mode: F = -q (t1, t2, t3); adjoint: -gE F = gE q (t1, t2, t3)
+          const R fq = (mode == kGatherPotentialForce) ? -scale * q : scale * q;
+          if (out_pot) out_pot[orig] = scale * pot;
+          if (out_vec) {
+            out_vec[3 * orig + 0] = fq * t1.value();
+            out_vec[3 * orig + 1] = fq * t2.value();
+            out_vec[3 * orig + 2] = fq * t3.value();
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <typename R, int WIN, int S, int T>
+hipError_t gather_one(se_plan &p, const double *gscale, int mode, void *pot, void *vec) {
+  const size_t lds = GatherLds<R, WIN, S, T>::TOTAL;
+  const double dcoef = (WIN == kGauss) ? 2.0 * p.a * p.h : 1.0 / p.h;
+  WindowConsts wc{p.cg, p.beta, exp(-2.0 * p.cg), dcoef};
+  const double self = (p.prm.flags & SE_FLAG_ADD_SELF) ? -2.0 * p.prm.xi / sqrt(M_PI) : 0.0;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gather<R, WIN, S, T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
+  stage_begin(p, SE_STAGE_GATHER);
+  k_gather<R, WIN, S, T><<<p.ntiles, kThreads, lds, p.stream>>>(
+      static_cast<const R *>(p.buf.grid), static_cast<const SortedParticle<R> *>(p.buf.sorted),
+      p.buf.meta, p.buf.offsets, p.prm.M, p.ntx, wc, gscale, mode, static_cast<R>(self),
+      static_cast<R *>(pot), static_cast<R *>(vec));
+  stage_end(p, SE_STAGE_GATHER);
+  return hipGetLastError();
+}
+
+template <typename R, int WIN, int T>
+hipError_t gather_dispatch_S(se_plan &p, const double *g, int mode, void *a, void *b) {
+  switch (p.prm.P) {
+    case 3: if constexpr (WIN == kBspline) return gather_one<R, WIN, 3, T>(p, g, mode, a, b); break;
+    case 4: return gather_one<R, WIN, 4, T>(p, g, mode, a, b);
+    case 5: if constexpr (WIN == kBspline) return gather_one<R, WIN, 5, T>(p, g, mode, a, b); break;
+    case 6: return gather_one<R, WIN, 6, T>(p, g, mode, a, b);
+    case 7: if constexpr (WIN == kBspline) return gather_one<R, WIN, 7, T>(p, g, mode, a, b); break;
+    case 8: return gather_one<R, WIN, 8, T>(p, g, mode, a, b);
+    case 10: if constexpr (WIN == kGauss) return gather_one<R, WIN, 10, T>(p, g, mode, a, b); break;
+    case 12: if constexpr (WIN == kGauss) return gather_one<R, WIN, 12, T>(p, g, mode, a, b); break;
+    case 14: if constexpr (WIN == kGauss) return gather_one<R, WIN, 14, T>(p, g, mode, a, b); break;
+    case 16: if constexpr (WIN == kGauss) return gather_one<R, WIN, 16, T>(p, g, mode, a, b); break;
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t gather_dispatch(se_plan &p, const double *g, int mode, void *a, void *b) {
+  const bool gauss = p.prm.window == SE_WINDOW_GAUSSIAN;
+  if (p.T == 16)
+    return gauss ? gather_dispatch_S<R, kGauss, 16>(p, g, mode, a, b)
+                 : gather_dispatch_S<R, kBspline, 16>(p, g, mode, a, b);
+  return gauss ? gather_dispatch_S<R, kGauss, 8>(p, g, mode, a, b)
+               : gather_dispatch_S<R, kBspline, 8>(p, g, mode, a, b);
+}
+
+}  // namespace
+
+size_t gather_lds_bytes(int real_size, int window, int S, int T) {
+  const size_t ts = T + S - 1;
+  const size_t groups = 64 / S, ch = groups * ((32 + groups - 1) / groups);
+  const size_t rec = window == SE_WINDOW_GAUSSIAN ? 3 * S + 4 : 6 * S + 1;
+  return real_size * ((ts * ts * ts + 3) & ~static_cast<size_t>(3)) +
+         real_size * (kThreads / 64) * 64 * 4 +
+         (kThreads / 64) * (real_size * ch * rec + 2 * 4 * ch);
+}
+
+hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode, void *out_pot,
+                         void *out_vec) {
+  if (N == 0 || (!out_pot && !out_vec)) return hipSuccess;
+  return plan.prm.dtype == SE_FP64 ? gather_dispatch<double>(plan, gscale, mode, out_pot, out_vec)
+                                   : gather_dispatch<float>(plan, gscale, mode, out_pot, out_vec);
+}
+
+}  // namespace sek

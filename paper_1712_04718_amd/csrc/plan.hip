@@ -1,0 +1,396 @@
+// Host side of the C ABI declared in include/sekspace.h: argument checks,
+// derived parameters (section 4, eq. 5.2), influence-function tables
+// (eqs. 4.6 and 6.2), FFT radix plan, workspace, and the call sequence.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "se_common.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+se_status fail(se_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+se_status fail(se_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+se_status hip_fail(hipError_t e, const char *where) {
+  return fail(SE_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool only_235(int m) {
+  for (int f : {2, 3, 5})
+    while (m % f == 0) m /= f;
+  return m == 1;
+}
+
+double shape_c(const se_params &p) { return p.c > 0.0 ? p.c : 0.95; }
+
+// eta of section 4 / eq. (5.2): eta = P L^2 xi^2 / (c^2 pi M^2).
+double eta_of(const se_params &p) {
+  const double c = shape_c(p);
+  return p.P * p.L * p.L * p.xi * p.xi / (c * c * M_PI * p.M * static_cast<double>(p.M));
+}
+
+int real_size(const se_params &p) { return p.dtype == SE_FP64 ? 8 : 4; }
+
+// Tile edge for spreading/gathering: 16 where there are still many tiles per
+// axis (fewer halo points per particle) and the LDS blocks fit, else 8.
+int choose_tile(const se_params &p) {
+  const int rs = real_size(p), S = p.P;
+  const auto fits = [&](int T) {
+    return sek::spread_lds_bytes(rs, S, T) <= sek::kMaxLds &&
+           sek::gather_lds_bytes(rs, p.window, S, T) <= sek::kMaxLds;
+  };
+  if (p.M >= 160 && fits(16)) return 16;
+  return 8;
+}
+
+int fft_batch_of(const se_params &p) {
+  const int csz = 2 * real_size(p);
+  int B = 65536 / (2 * p.M * csz);
+  if (B > 16) B = 16;
+  if (B < 1) B = 1;
+  return B;
+}
+
+sek::FftPlan radix_plan(int M) {
+  sek::FftPlan pl{};
+  pl.M = M;
+  int m = M, n = 0;
+  while (m % 8 == 0) { pl.radix[n++] = 8; m /= 8; }
+  if (m % 4 == 0) { pl.radix[n++] = 4; m /= 4; }
+  if (m % 2 == 0) { pl.radix[n++] = 2; m /= 2; }
+  while (m % 5 == 0) { pl.radix[n++] = 5; m /= 5; }
+  while (m % 3 == 0) { pl.radix[n++] = 3; m /= 3; }
+  pl.nstages = n;
+  return pl;
+}
+
+// Cardinal B-spline M_p at integer arguments 1..p-1 (section 6.1 recursion).
+double bspline_at(int p, double u) {
+  if (p == 2) return (u >= 0.0 && u <= 2.0) ? 1.0 - std::fabs(u - 1.0) : 0.0;
+  return u / (p - 1) * bspline_at(p - 1, u) + (p - u) / (p - 1) * bspline_at(p - 1, u - 1.0);
+}
+
+// |b(n)|^2 of the SPME influence function: 1 / |sum_{l=0}^{p-2} M_p(l+1) e^{2 pi i n l/M}|^2,
+// 0 where the sum vanishes (odd p at n = M/2).
+double spme_bmod2(int p, int M, int n) {
+  double re = 0.0, im = 0.0;
+  for (int l = 0; l <= p - 2; ++l) {
+    const double v = bspline_at(p, l + 1.0);
+    const double ang = 2.0 * M_PI * static_cast<double>(n) * l / M;
+    re += v * std::cos(ang);
+    im += v * std::sin(ang);
+  }
+  const double d = re * re + im * im;
+  return d > 1e-10 ? 1.0 / d : 0.0;
+}
+
+se_status check_params(const se_params *prm, double *eta_out) {
+  if (!prm) return fail(SE_ERR_ARG, "params is NULL");
+  const se_params &p = *prm;
+  if (!(p.L > 0.0) || !std::isfinite(p.L)) return fail(SE_ERR_ARG, "L must be finite and > 0 (got %g)", p.L);
+  if (!(p.xi > 0.0) || !std::isfinite(p.xi)) return fail(SE_ERR_ARG, "xi must be finite and > 0 (got %g)", p.xi);
+  if (!std::isfinite(p.c)) return fail(SE_ERR_ARG, "c must be finite");
+  if (p.window != SE_WINDOW_GAUSSIAN && p.window != SE_WINDOW_BSPLINE)
+    return fail(SE_ERR_ARG, "unknown window %d", p.window);
+  if (p.dtype != SE_FP32 && p.dtype != SE_FP64) return fail(SE_ERR_ARG, "unknown dtype %d", p.dtype);
+  if (p.flags & ~(SE_FLAG_ADD_SELF | SE_FLAG_TIMING)) return fail(SE_ERR_ARG, "unknown flags 0x%x", p.flags);
+  if (p.M < 8 || p.M > 512 || (p.M & 1) || !only_235(p.M))
+    return fail(SE_ERR_GRID, "M=%d must be even, 8..512 and of the form 2^a 3^b 5^c", p.M);
+  if (p.P > p.M) return fail(SE_ERR_GRID, "support %d exceeds M=%d", p.P, p.M);
+  double eta = 0.0;
+  if (p.window == SE_WINDOW_GAUSSIAN) {
+    if ((p.P & 1) || p.P < 4 || p.P > 16)
+      return fail(SE_ERR_UNSUPPORTED, "Gaussian support P=%d: built for even P in 4..16", p.P);
+    eta = eta_of(p);
+    if (!(eta > 0.0 && eta < 1.0))
+      return fail(SE_ERR_ETA, "eta = P L^2 xi^2 / (c^2 pi M^2) = %g is outside (0,1)", eta);
+  } else {
+    if (p.P < 3 || p.P > 8)
+      return fail(SE_ERR_UNSUPPORTED, "B-spline order p=%d: built for 3..8", p.P);
+  }
+  if (eta_out) *eta_out = eta;
+  return SE_OK;
+}
+
+struct Sizes {
+  size_t grid, spec, sorted, meta, key, counts, offsets, done, part, qsq, tw, f, k2, total;
+};
+
+Sizes sizes_of(const se_params &p, int n_max, int ntiles, int bin_blocks, int zblocks) {
+  const size_t rs = real_size(p), M = p.M, K = M / 2 + 1;
+  const size_t n = n_max > 0 ? n_max : 1;
+  Sizes s{};
+  auto al = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+  s.grid = al(M * M * M * rs);
+  s.spec = al(M * M * K * 2 * rs);
+  s.sorted = al(n * 4 * rs);
+  s.meta = al(n * 8);
+  s.key = al(n * 8);
+  s.counts = al(ntiles * 4);
+  s.offsets = al((ntiles + 1) * 4);
+  s.done = al(2 * 4);
+  s.part = al((bin_blocks + zblocks) * 8);
+  s.qsq = al(8);
+  s.tw = al(M * 2 * rs);
+  s.f = al(M * 8);
+  s.k2 = al(M * 8);
+  s.total = s.grid + s.spec + s.sorted + s.meta + s.key + s.counts + s.offsets + s.done +
+            s.part + s.qsq + s.tw + s.f + s.k2;
+  return s;
+}
+
+void derive(se_plan &pl) {
+  const se_params &p = pl.prm;
+  pl.h = p.L / p.M;
+  pl.wscale = 4.0 * M_PI / (p.L * p.L * p.L);
+  if (p.window == SE_WINDOW_GAUSSIAN) {
+    pl.eta = eta_of(p);
+    pl.a = 2.0 * p.xi * p.xi / pl.eta;
+    pl.cg = pl.a * pl.h * pl.h;
+    pl.beta = pl.h * std::sqrt(pl.a / M_PI);
+  } else {
+    pl.eta = pl.a = pl.cg = pl.beta = 0.0;
+  }
+  pl.T = choose_tile(p);
+  pl.ntx = (p.M + pl.T - 1) / pl.T;
+  pl.ntiles = pl.ntx * pl.ntx * pl.ntx;
+  pl.bin_blocks = (pl.n_max + sek::kThreads - 1) / sek::kThreads;
+  if (pl.bin_blocks < 1) pl.bin_blocks = 1;
+  pl.fft_batch = fft_batch_of(p);
+  pl.zfft_blocks = (p.M * (p.M / 2 + 1) + pl.fft_batch - 1) / pl.fft_batch;
+  pl.fft = radix_plan(p.M);
+}
+
+template <typename R>
+hipError_t upload_twiddles(se_plan &pl) {
+  const int M = pl.prm.M;
+  std::vector<R> tw(2 * M);
+  for (int j = 0; j < M; ++j) {
+    const double ang = 2.0 * M_PI * j / M;
+    tw[2 * j] = static_cast<R>(std::cos(ang));
+    tw[2 * j + 1] = static_cast<R>(-std::sin(ang));
+  }
+  return hipMemcpy(pl.buf.twiddle, tw.data(), sizeof(R) * 2 * M, hipMemcpyHostToDevice);
+}
+
+void destroy_events(se_plan &pl) {
+  if (!pl.timing) return;
+  for (int i = 0; i < SE_NUM_STAGES; ++i) {
+    if (pl.ev_begin[i]) (void)hipEventDestroy(pl.ev_begin[i]);
+    if (pl.ev_end[i]) (void)hipEventDestroy(pl.ev_end[i]);
+    pl.ev_begin[i] = pl.ev_end[i] = nullptr;
+  }
+}
+
+void free_all(se_plan &pl) {
+  destroy_events(pl);
+  void *ptrs[] = {pl.buf.grid, pl.buf.spec, pl.buf.sorted, pl.buf.meta, pl.buf.key,
+                  pl.buf.counts, pl.buf.offsets, pl.buf.done, pl.buf.part, pl.buf.qsq,
+                  pl.buf.twiddle, pl.buf.axis_f, pl.buf.axis_k2};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  pl.buf = sek::DeviceBuffers{};
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *se_status_string(se_status s) {
+  switch (s) {
+    case SE_OK: return "SE_OK";
+    case SE_ERR_ARG: return "SE_ERR_ARG: invalid argument";
+    case SE_ERR_GRID: return "SE_ERR_GRID: unsupported grid size";
+    case SE_ERR_ETA: return "SE_ERR_ETA: Gaussian shape eta outside (0,1)";
+    case SE_ERR_UNSUPPORTED: return "SE_ERR_UNSUPPORTED: window/support/precision not built";
+    case SE_ERR_WORKSPACE: return "SE_ERR_WORKSPACE: device allocation failed";
+    case SE_ERR_HIP: return "SE_ERR_HIP: HIP runtime error";
+    case SE_ERR_STATE: return "SE_ERR_STATE: no forward pass on this plan yet";
+  }
+  return "unknown se_status";
+}
+
+const char *se_last_error(void) { return g_last_error.c_str(); }
+
+se_status se_params_check(const se_params *prm, double *eta) { return check_params(prm, eta); }
+
+se_status se_plan_workspace_size(const se_params *prm, int n_max, size_t *bytes) {
+  se_status s = check_params(prm, nullptr);
+  if (s != SE_OK) return s;
+  if (n_max < 1) return fail(SE_ERR_ARG, "n_max must be >= 1 (got %d)", n_max);
+  if (!bytes) return fail(SE_ERR_ARG, "bytes is NULL");
+  se_plan tmp{};
+  tmp.prm = *prm;
+  tmp.n_max = n_max;
+  derive(tmp);
+  *bytes = sizes_of(*prm, n_max, tmp.ntiles, tmp.bin_blocks, tmp.zfft_blocks).total;
+  return SE_OK;
+}
+
+se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_plan **out) {
+  if (!out) return fail(SE_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  se_status s = check_params(prm, nullptr);
+  if (s != SE_OK) return s;
+  if (n_max < 1) return fail(SE_ERR_ARG, "n_max must be >= 1 (got %d)", n_max);
+
+  se_plan *pl = new (std::nothrow) se_plan{};
+  if (!pl) return fail(SE_ERR_WORKSPACE, "host allocation failed");
+  pl->prm = *prm;
+  if (pl->prm.c <= 0.0) pl->prm.c = 0.95;
+  pl->n_max = n_max;
+  pl->stream = static_cast<hipStream_t>(hip_stream);
+  pl->last_N = -1;
+  derive(*pl);
+  hipError_t e = hipGetDevice(&pl->device);
+  if (e != hipSuccess) {
+    delete pl;
+    return hip_fail(e, "hipGetDevice");
+  }
+
+  const Sizes sz = sizes_of(pl->prm, n_max, pl->ntiles, pl->bin_blocks, pl->zfft_blocks);
+  struct { void **p; size_t n; } allocs[] = {
+      {&pl->buf.grid, sz.grid},     {&pl->buf.spec, sz.spec},
+      {&pl->buf.sorted, sz.sorted}, {reinterpret_cast<void **>(&pl->buf.meta), sz.meta},
+      {reinterpret_cast<void **>(&pl->buf.key), sz.key},
+      {reinterpret_cast<void **>(&pl->buf.counts), sz.counts},
+      {reinterpret_cast<void **>(&pl->buf.offsets), sz.offsets},
+      {reinterpret_cast<void **>(&pl->buf.done), sz.done},
+      {reinterpret_cast<void **>(&pl->buf.part), sz.part},
+      {reinterpret_cast<void **>(&pl->buf.qsq), sz.qsq},
+      {&pl->buf.twiddle, sz.tw},    {&pl->buf.axis_f, sz.f},
+      {&pl->buf.axis_k2, sz.k2}};
+  for (auto &a : allocs) {
+    e = hipMalloc(a.p, a.n);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      free_all(*pl);
+      delete pl;
+      return fail(SE_ERR_WORKSPACE, "hipMalloc(%zu) failed: %s", a.n, hipGetErrorString(e));
+    }
+  }
+  pl->buf.bytes = sz.total;
+
+  // tables (double precision on the host)
+  const int M = pl->prm.M;
+  std::vector<double> f(M), k2(M);
+  for (int n = 0; n < M; ++n) {
+    const int ns = (2 * n <= M) ? n : n - M;  // signed frequency; Nyquist gets |n| = M/2
+    const double k = 2.0 * M_PI * ns / pl->prm.L;
+    k2[n] = k * k;
+    const double xi2 = pl->prm.xi * pl->prm.xi;
+    if (pl->prm.window == SE_WINDOW_GAUSSIAN)
+      f[n] = std::exp(-(1.0 - pl->eta) * k2[n] / (4.0 * xi2));             // eq. (4.6)
+    else
+      f[n] = spme_bmod2(pl->prm.P, M, n) * std::exp(-k2[n] / (4.0 * xi2));  // eq. (6.2)
+  }
+  e = hipMemcpy(pl->buf.axis_f, f.data(), sizeof(double) * M, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->buf.axis_k2, k2.data(), sizeof(double) * M, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = pl->prm.dtype == SE_FP64 ? upload_twiddles<double>(*pl) : upload_twiddles<float>(*pl);
+  pl->timing = (pl->prm.flags & SE_FLAG_TIMING) != 0;
+  for (int i = 0; i < SE_NUM_STAGES && pl->timing && e == hipSuccess; ++i) {
+    e = hipEventCreate(&pl->ev_begin[i]);
+    if (e == hipSuccess) e = hipEventCreate(&pl->ev_end[i]);
+  }
+  if (e == hipSuccess) e = hipMemset(pl->buf.counts, 0, sz.counts);
+  if (e == hipSuccess) e = hipMemset(pl->buf.done, 0, sz.done);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_all(*pl);
+    delete pl;
+    return hip_fail(e, "plan set-up");
+  }
+  *out = pl;
+  return SE_OK;
+}
+
+se_status se_plan_set_stream(se_plan *plan, void *hip_stream) {
+  if (!plan) return fail(SE_ERR_ARG, "plan is NULL");
+  plan->stream = static_cast<hipStream_t>(hip_stream);
+  return SE_OK;
+}
+
+se_status se_plan_eta(const se_plan *plan, double *eta) {
+  if (!plan || !eta) return fail(SE_ERR_ARG, "NULL argument");
+  *eta = plan->eta;
+  return SE_OK;
+}
+
+se_status se_plan_stage_times(se_plan *plan, double *ms, int n) {
+  if (!plan || (!ms && n > 0) || n < 0) return fail(SE_ERR_ARG, "bad arguments");
+  if (!plan->timing) return fail(SE_ERR_STATE, "plan was created without SE_FLAG_TIMING");
+  for (int i = 0; i < n && i < SE_NUM_STAGES; ++i) {
+    ms[i] = -1.0;
+    if (!plan->ev_used[i]) continue;
+    hipError_t e = hipEventSynchronize(plan->ev_end[i]);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, plan->ev_begin[i], plan->ev_end[i]);
+    if (e != hipSuccess) return hip_fail(e, "stage timing");
+    ms[i] = t;
+  }
+  for (int i = SE_NUM_STAGES; i < n; ++i) ms[i] = -1.0;
+  return SE_OK;
+}
+
+se_status se_plan_destroy(se_plan *plan) {
+  if (!plan) return SE_OK;
+  hipError_t e = hipStreamSynchronize(plan->stream);
+  free_all(*plan);
+  delete plan;
+  return e == hipSuccess ? SE_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+se_status se_forward(se_plan *plan, int N, const void *x, const void *q, double *E_dev) {
+  if (!plan) return fail(SE_ERR_ARG, "plan is NULL");
+  if (N < 0 || N > plan->n_max) return fail(SE_ERR_ARG, "N=%d outside [0, n_max=%d]", N, plan->n_max);
+  if (N > 0 && (!x || !q)) return fail(SE_ERR_ARG, "x or q is NULL");
+  if (!E_dev) return fail(SE_ERR_ARG, "E_dev is NULL");
+  hipError_t e = sek::launch_bin(*plan, N, x, q);
+  if (e != hipSuccess) return hip_fail(e, "binning");
+  if ((e = sek::launch_spread(*plan, N)) != hipSuccess) return hip_fail(e, "spreading");
+  if ((e = sek::launch_fft_forward_scale_inverse(*plan, E_dev)) != hipSuccess)
+    return hip_fail(e, "FFT/scaling");
+  plan->last_N = N;
+  return SE_OK;
+}
+
+se_status se_gather(se_plan *plan, void *phi, void *F) {
+  if (!plan) return fail(SE_ERR_ARG, "plan is NULL");
+  if (plan->last_N < 0) return fail(SE_ERR_STATE, "se_gather before se_forward");
+  hipError_t e = sek::launch_gather(*plan, plan->last_N, nullptr, sek::kGatherPotentialForce, phi, F);
+  return e == hipSuccess ? SE_OK : hip_fail(e, "gathering");
+}
+
+se_status se_kspace(se_plan *plan, int N, const void *x, const void *q, double *E_dev, void *phi,
+                    void *F) {
+  se_status s = se_forward(plan, N, x, q, E_dev);
+  if (s != SE_OK) return s;
+  return se_gather(plan, phi, F);
+}
+
+se_status se_backward(se_plan *plan, const double *gE_dev, void *grad_x, void *grad_q) {
+  if (!plan) return fail(SE_ERR_ARG, "plan is NULL");
+  if (!gE_dev) return fail(SE_ERR_ARG, "gE_dev is NULL");
+  if (plan->last_N < 0) return fail(SE_ERR_STATE, "se_backward before se_forward");
+  hipError_t e = sek::launch_gather(*plan, plan->last_N, gE_dev, sek::kGatherAdjoint, grad_q, grad_x);
+  return e == hipSuccess ? SE_OK : hip_fail(e, "adjoint gathering");
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Per-axis window factors of the two methods, evaluated for one particle.
+//
+// Each particle's factors are computed once, by one lane, into LDS ("phase
+// A" of the spreading and gathering kernels); the accumulation loops then
+// read them.  Grid units: a particle with anchor floor(x/h) = i0 and offset
+// d = x/h - i0 in [0,1) touches the S grid points i0 + OFF + j, j = 0..S-1.
+//
+// SE (section 4): truncated Gaussian, OFF = -(P/2 - 1).  Per axis
+//   g_j = beta exp(-cg t_j^2),  t_j = j + OFF - d   (= (x_j - x)/h),
+// with cg = a h^2, a = 2 xi^2 / eta and beta = h sqrt(a/pi), so that the
+// product over three axes is the h^3-weighted Gaussian of eq. (4.5).  The
+// FP64 factors follow the fast Gaussian gridding recurrence of eqs.
+// (4.10)-(4.11): g_{j+1} = g_j r_j with r_j = exp(-cg (2 t_j + 1)) and
+// r_{j+1} = r_j exp(-2 cg), i.e. two exponentials per axis instead of P.
+// FP32 factors are evaluated one by one (see window_axis).  The derivative
+// factor used for forces is the derivative with respect to the particle
+// coordinate, d/dx_m W(x_j - x_m) = 2 a (x_j - x_m) W, i.e. per axis
+// dg_j = 2 a h t_j g_j.
+//
+// SPME (section 6): cardinal B-spline of order p, OFF = -(p - 1),
+//   g_j = M_p(d + p - 1 - j),  dg_j = (1/h) M_p'(d + p - 1 - j),
+// with M_p built by the recursion of section 6.1 from M_2 and
+// M_p' (u) = M_{p-1}(u) - M_{p-1}(u - 1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace sek {
+
+constexpr int kGauss = 0;
+constexpr int kBspline = 1;
+
+template <int WIN, int S> struct Stencil {
+  static constexpr int OFF = (WIN == kGauss) ? -(S / 2 - 1) : -(S - 1);
+};
+
+// Particles per wave and round in the spreading/gathering kernels: a
+// multiple of the 64/S particle groups of a wave, about 32, at most 64 (one
+// lane per particle while computing factors).
+template <int S> struct Chunk {
+  static constexpr int GROUPS = 64 / S;
+  static constexpr int ROUNDS = (32 + GROUPS - 1) / GROUPS;
+  static constexpr int CH = GROUPS * ROUNDS;
+  static_assert(CH <= 64, "chunk larger than a wave");
+};
+
+struct WindowConsts {
+  double cg;     // Gaussian exponent in grid units (SE)
+  double beta;   // per-axis Gaussian normalisation (SE)
+  double kap;    // exp(-2 cg), ratio of successive recurrence factors (SE)
+  double dcoef;  // SE: 2 a h; SPME: 1/h   (derivative scale)
+};
+
+// All S factors of one axis (and optionally their derivatives).
+//
+// FP32 evaluates every Gaussian factor directly with an accurate expf: a
+// recurrence started from the tail factors (which carry the largest
+// argument-rounding error) would pass that relative error on to the large
+// central factors.  FP64 uses the fast Gaussian gridding recurrence, whose
+// accumulated rounding stays near 1e-15.
+template <typename R, int WIN, int S, bool DERIV>
+__device__ inline void window_axis(R d, const WindowConsts &wc, R (&g)[S], R (&dg)[S]) {
+  if constexpr (WIN == kGauss) {
+    constexpr int OFF = Stencil<WIN, S>::OFF;
+    const R cg = static_cast<R>(wc.cg);
+    const R beta = static_cast<R>(wc.beta);
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        const R t = static_cast<R>(OFF + j) - d;
+        g[j] = beta * expf(-cg * t * t);
+        if constexpr (DERIV) dg[j] = static_cast<R>(wc.dcoef) * t * g[j];
+      }
+    } else {
+      const R t0 = static_cast<R>(OFF) - d;
+      R gj = beta * exp(-cg * t0 * t0);
+      R rj = exp(-cg * (R(2) * t0 + R(1)));
+      const R kap = static_cast<R>(wc.kap);
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        g[j] = gj;
+        if constexpr (DERIV) dg[j] = static_cast<R>(wc.dcoef) * (t0 + R(j)) * gj;
+        gj *= rj;
+        rj *= kap;
+      }
+    }
+  } else {
+    // v[i] = M_n(d + i), i = 0..n-1, built up from n = 2.
+    R v[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) v[i] = R(0);
+    v[0] = d;
+    v[1] = R(1) - d;
+#pragma unroll
+    for (int n = 2; n < S; ++n) {
+      // order n -> n + 1:
+      // M_{n+1}(d+i) = ((d+i) M_n(d+i) + (n+1-d-i) M_n(d+i-1)) / n
+      if (n == S - 1 && DERIV) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+          const int i = S - 1 - j;  // dg_j = (1/h)(M_{S-1}(d+i) - M_{S-1}(d+i-1))
+          const R hi = (i <= S - 2) ? v[i] : R(0);
+          const R lo = (i >= 1) ? v[i - 1] : R(0);
+          dg[j] = static_cast<R>(wc.dcoef) * (hi - lo);
+        }
+      }
+      const R inv = R(1) / static_cast<R>(n);
+#pragma unroll
+      for (int i = n; i >= 0; --i) {
+        const R cur = (i <= n - 1) ? v[i] : R(0);
+        const R prev = (i >= 1) ? v[i - 1] : R(0);
+        v[i] = ((d + R(i)) * cur + (R(n + 1) - d - R(i)) * prev) * inv;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) g[j] = v[S - 1 - j];
+  }
+}
+
+}  // namespace sek

@@ -1,0 +1,54 @@
+"""Helpers shared by the GPU tests: run the GPU path and the oracle on the
+same (exactly representable) inputs and measure their disagreement."""
+import numpy as np
+import torch
+
+from oracle import se_oracle as O
+from paper_1712_04718_amd import SEPlan
+
+DEV = torch.device("cuda:0")
+TOL = {torch.float32: 1e-5, torch.float64: 1e-9}
+
+
+def to_dev(x, q, dtype):
+    xt = torch.tensor(np.asarray(x), dtype=dtype, device=DEV)
+    qt = torch.tensor(np.asarray(q), dtype=dtype, device=DEV)
+    return xt, qt
+
+
+def as_oracle_inputs(xt, qt):
+    """The device inputs, promoted exactly to float64 for the oracle."""
+    return xt.double().cpu().numpy(), qt.double().cpu().numpy()
+
+
+def oracle_kspace(window, x, q, L, xi, M, P):
+    if window == "gaussian":
+        return O.se_kspace(x, q, L, xi, M, P)
+    return O.spme_kspace(x, q, L, xi, M, P)
+
+
+def gpu_kspace(x, q, L, xi, M, P, dtype, window="gaussian", add_self=False):
+    xt, qt = to_dev(x, q, dtype)
+    plan = SEPlan(M, P, L, xi, window=window, dtype=dtype, n_max=max(1, len(q)),
+                  add_self=add_self)
+    E, phi, F = plan.kspace(xt, qt)
+    torch.cuda.synchronize()
+    out = (E.item(), phi.double().cpu().numpy(), F.double().cpu().numpy())
+    return out, plan, xt, qt
+
+
+def errors(gpu, ref):
+    (E, phi, F), (Eo, phio, Fo) = gpu, ref
+    return (abs(E - Eo) / abs(Eo) if Eo != 0 else abs(E),
+            O.rel_rms(phi, phio), O.rel_rms(F, Fo))
+
+
+_SYSTEMS = {}
+
+
+def cached_system(name):
+    """(x, q, spec) of a named workload, generated once per test session."""
+    from workloads import make_system
+    if name not in _SYSTEMS:
+        _SYSTEMS[name] = make_system(name)
+    return _SYSTEMS[name]

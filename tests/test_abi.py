@@ -1,0 +1,82 @@
+"""The C-ABI library: it loads, exports every symbol the header declares, and
+its host-side argument checks behave as documented.  No GPU calls."""
+import math
+import os
+import re
+
+import pytest
+
+from paper_1712_04718_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "include", "sekspace.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(se_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    declared = _declared_functions()
+    assert declared, "no declarations parsed"
+    assert sorted(_lib.EXPORTS) == declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    lib = _lib.load()
+    for code, name in _lib.STATUS_NAMES.items():
+        assert lib.se_status_string(code).decode().startswith(name)
+
+
+def _check(**kw):
+    base = dict(M=96, P=8, L=100.0, xi=0.3, c=0.95, window=0, dtype=0, flags=0)
+    base.update(kw)
+    prm = _lib.make_params(**base)
+    return _lib.params_check(prm)
+
+
+def test_eta_matches_paper_formula():
+    """eta = P L^2 xi^2 / (c^2 pi M^2) (section 4, eq. 5.2)."""
+    for (M, P, L, xi) in [(96, 8, 100.0, 0.3), (32, 8, 10.0, 1.5), (192, 8, 220.0, 0.35),
+                          (40, 10, 40.0, 0.3)]:
+        st, eta = _check(M=M, P=P, L=L, xi=xi)
+        assert st == _lib.SE_OK
+        assert abs(eta - P * L * L * xi * xi / (0.95 ** 2 * math.pi * M * M)) < 1e-15
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(L=0.0), 1), (dict(L=-1.0), 1), (dict(xi=0.0), 1), (dict(L=float("nan")), 1),
+    (dict(window=7), 1), (dict(dtype=3), 1), (dict(flags=8), 1),
+    (dict(M=33), 2), (dict(M=14), 2), (dict(M=6), 2), (dict(M=1024), 2), (dict(M=10, P=12), 2),
+    (dict(P=7), 4), (dict(P=18), 4), (dict(P=2), 4),
+    (dict(window=1, P=2), 4), (dict(window=1, P=9), 4),
+    (dict(xi=3.0), 3),
+])
+def test_invalid_parameters_rejected(kw, status):
+    st, _ = _check(**kw)
+    assert st == status
+    assert _lib.load().se_last_error().decode() != ""
+
+
+def test_valid_parameter_sets():
+    for kw in [dict(), dict(dtype=1), dict(window=1, P=4), dict(window=1, P=3),
+               dict(window=1, P=7), dict(M=40, L=40.0, P=6), dict(M=30, L=10.0, xi=1.0, P=8)]:
+        st, _ = _check(**kw)
+        assert st == _lib.SE_OK, kw
+
+
+def test_workspace_size():
+    prm = _lib.make_params(96, 8, 100.0, 0.3)
+    st, b = _lib.workspace_size(prm, 100200)
+    assert st == 0
+    M, K = 96, 49
+    assert b >= M ** 3 * 4 + M * M * K * 8 + 100200 * 16
+    st, b64 = _lib.workspace_size(_lib.make_params(96, 8, 100.0, 0.3, dtype=1), 100200)
+    assert st == 0 and b64 > b
+    st, _ = _lib.workspace_size(prm, 0)
+    assert st == 1  # SE_ERR_ARG

@@ -1,0 +1,210 @@
+"""GPU path vs the FP64 oracle, element by element on identical inputs.
+
+Bar: relative rms error of E, phi and F against the oracle at the same
+(M, P, window) <= 1e-5 in FP32 and <= 1e-9 in FP64.  Sizes span several
+tiles and a ragged tail; the full-size workloads are checked on E and on
+sampled particles.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import (DEV, TOL, as_oracle_inputs, cached_system, errors, gpu_kspace,
+                      oracle_kspace, to_dev)
+from oracle import se_oracle as O
+from paper_1712_04718_amd import SEPlan
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float32, torch.float64]
+
+
+def _rand(N, L, seed, neutral=True):
+    rng = np.random.default_rng(seed)
+    x = rng.random((N, 3)) * L
+    q = rng.standard_normal(N)
+    if neutral:
+        q -= q.mean()
+    return x, q
+
+
+def _parity(x, q, L, xi, M, P, dtype, window="gaussian", tol=None):
+    print(f"[parity] N={len(q)} L={L} xi={xi} M={M} P={P} {window} {dtype}", flush=True)
+    out, plan, xt, qt = gpu_kspace(x, q, L, xi, M, P, dtype, window)
+    xo, qo = as_oracle_inputs(xt, qt)
+    ref = oracle_kspace(window, xo, qo, L, xi, M, P)
+    e = errors(out, ref)
+    lim = tol if tol is not None else TOL[dtype]
+    assert max(e) < lim, (e, lim)
+    return e
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("P", [4, 6, 8, 10, 12, 14, 16])
+@pytest.mark.parametrize("M", [32, 30])
+def test_gaussian_window(M, P, dtype):
+    """SE window at every built support; M = 30 leaves a ragged last tile."""
+    x, q = _rand(777, 10.0, 100 + P)
+    _parity(x, q, 10.0, 1.2, M, P, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("p", [3, 4, 5, 6, 7, 8])
+def test_bspline_window(p, dtype):
+    """SPME window at every built order (odd p includes the Nyquist B = 0 mode)."""
+    x, q = _rand(777, 10.0, 200 + p)
+    _parity(x, q, 10.0, 1.2, 30, p, dtype, window="bspline")
+
+
+@pytest.mark.parametrize("M", [8, 10, 12, 16, 18, 20, 24, 40, 48, 50, 60, 64, 72, 80, 90,
+                               96, 100, 120, 128, 144, 160, 192])
+def test_grid_sizes(M):
+    """Every radix path of the FFT (2, 3, 4, 5, 8 and mixes), small to large M;
+    xi = M / 4L as in section 5.3, so eta does not depend on M."""
+    L = 10.0
+    x, q = _rand(300, L, 300 + M)
+    _parity(x, q, L, M / (4 * L), M, 4 if M < 12 else 6, torch.float64)
+    _parity(x, q, L, M / (4 * L), M, 4 if M < 12 else 6, torch.float32)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_positions_on_edges(dtype):
+    """Particles on grid points, at 0, just below L, outside [0, L) (wrapped)."""
+    L, M = 10.0, 32
+    h = L / M
+    pts = [[0.0, 0.0, 0.0], [h, 2 * h, 3 * h], [L - 1e-7, L - 1e-7, 0.5],
+           [np.nextafter(L, 0), 1.0, 2.0], [-0.3, 4.0, 5.0], [L + 0.7, -2 * L + 0.1, 3 * L],
+           [5.0, 5.0, 5.0], [16 * h, 8 * h, 24 * h]]
+    x = np.array(pts)
+    q = np.array([1.0, -1.0, 0.5, -0.5, 0.25, -0.25, 2.0, -2.0])
+    _parity(x, q, L, 1.0, M, 8, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_dense_cluster(dtype):
+    """Many particles in one tile (long per-tile lists, LDS atomic conflicts)."""
+    rng = np.random.default_rng(5)
+    x = 3.0 + rng.random((3000, 3)) * 0.5
+    q = rng.standard_normal(3000)
+    _parity(x, q, 10.0, 1.2, 32, 8, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_single_and_non_neutral(dtype):
+    """N = 1 and a non-neutral set: k = 0 is dropped, nothing else changes.
+    A lone charge feels no k-space force in the exact sum, so its tiny
+    method-level force is compared in absolute terms."""
+    x1, q1 = np.array([[1.0, 2.0, 3.0]]), np.array([1.0])
+    (E, phi, F), _, xt, qt = gpu_kspace(x1, q1, 5.0, 1.0, 16, 6, dtype)
+    Eo, phio, Fo = O.se_kspace(*as_oracle_inputs(xt, qt), 5.0, 1.0, 16, 6)
+    assert abs(E - Eo) < TOL[dtype] * abs(Eo)
+    assert abs(phi[0] - phio[0]) < TOL[dtype] * abs(phio[0])
+    assert np.max(np.abs(F - Fo)) < TOL[dtype] * abs(phio[0])
+    x, q = _rand(500, 10.0, 6, neutral=False)
+    _parity(x, q, 10.0, 1.2, 32, 8, dtype)
+
+
+def test_empty_input():
+    plan = SEPlan(16, 6, 5.0, 1.0, dtype=torch.float64, n_max=10)
+    x = torch.empty(0, 3, dtype=torch.float64, device=DEV)
+    q = torch.empty(0, dtype=torch.float64, device=DEV)
+    E, phi, F = plan.kspace(x, q)
+    torch.cuda.synchronize()
+    assert E.item() == 0.0 and phi.numel() == 0 and F.numel() == 0
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_add_self_flag(dtype):
+    """SE_FLAG_ADD_SELF adds -(xi/sqrt pi) sum q^2 to E and -2 xi q/sqrt pi to phi."""
+    x, q = _rand(400, 10.0, 7)
+    (E0, p0, F0), *_ = gpu_kspace(x, q, 10.0, 1.2, 32, 8, dtype)
+    (E1, p1, F1), _, xt, qt = gpu_kspace(x, q, 10.0, 1.2, 32, 8, dtype, add_self=True)
+    qo = qt.double().cpu().numpy()
+    xi = 1.2
+    assert abs((E1 - E0) - (-xi / math.sqrt(math.pi) * np.sum(qo * qo))) < TOL[dtype] * abs(E0)
+    assert np.max(np.abs((p1 - p0) - (-2 * xi / math.sqrt(math.pi) * qo))) < TOL[dtype] * 10 * np.abs(p0).max()
+    # float atomics make repeated evaluations agree to rounding, not bitwise
+    assert O.rel_rms(F1, F0) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_plan_reuse_with_smaller_input(dtype):
+    """A plan reused for a second, smaller input gives the fresh-plan result."""
+    L, xi, M, P = 10.0, 1.2, 32, 8
+    x1, q1 = _rand(900, L, 8)
+    x2, q2 = _rand(333, L, 9)
+    plan = SEPlan(M, P, L, xi, dtype=dtype, n_max=900)
+    for (x, q) in ((x1, q1), (x2, q2), (x1, q1)):
+        xt, qt = to_dev(x, q, dtype)
+        E, phi, F = plan.kspace(xt, qt)
+        torch.cuda.synchronize()
+        ref = O.se_kspace(*as_oracle_inputs(xt, qt), L, xi, M, P)
+        e = errors((E.item(), phi.double().cpu().numpy(), F.double().cpu().numpy()), ref)
+        assert max(e) < TOL[dtype], e
+
+
+def test_invalid_calls_raise():
+    """Host-side checks: N above n_max, wrong dtype, gather before forward."""
+    from paper_1712_04718_amd import SeError
+    plan = SEPlan(16, 6, 5.0, 1.0, dtype=torch.float32, n_max=4)
+    with pytest.raises(RuntimeError):
+        plan.gather()
+    x = torch.zeros(5, 3, device=DEV)
+    q = torch.zeros(5, device=DEV)
+    with pytest.raises(ValueError):
+        plan.kspace(x, q)
+    with pytest.raises(TypeError):
+        plan.kspace(x[:4].double(), q[:4].double())
+    with pytest.raises(SeError):
+        SEPlan(16, 7, 5.0, 1.0)
+
+
+# --------------------------------------------------------------- full sizes
+
+def _sampled_parity(name, P, dtype, window="gaussian", M=None, nsample=2000, tol=None):
+    x, q, spec = cached_system(name)
+    M = M or spec.M
+    print(f"[full] {name} N={len(q)} M={M} P={P} {window} {dtype}", flush=True)
+    xt, qt = to_dev(x, q, dtype)
+    plan = SEPlan(M, P, spec.L, spec.xi, window=window, dtype=dtype, n_max=len(q))
+    E, phi, F = plan.kspace(xt, qt)
+    torch.cuda.synchronize()
+    xo, qo = as_oracle_inputs(xt, qt)
+    L, xi = spec.L, spec.xi
+    if window == "gaussian":
+        eta = O.se_eta(L, xi, M, P)
+        G = O.se_spread(xo, qo, L, M, P, xi, eta)
+        Eo, Phi = O.scale_and_energy(G, O.se_influence(L, xi, M, eta), L)
+    else:
+        G = O.spme_spread(xo, qo, L, M, P)
+        Eo, Phi = O.scale_and_energy(G, O.spme_influence(L, xi, M, P), L)
+    idx = np.random.default_rng(42).choice(len(q), size=min(nsample, len(q)), replace=False)
+    if window == "gaussian":
+        phio, Fo = O.se_gather(xo[idx], qo[idx], L, M, P, xi, eta, Phi)
+    else:
+        phio, Fo = O.spme_gather(xo[idx], qo[idx], L, M, P, Phi)
+    eE = abs(E.item() - Eo) / abs(Eo)
+    ephi = O.rel_rms(phi.double().cpu().numpy()[idx], phio)
+    eF = O.rel_rms(F.double().cpu().numpy()[idx], Fo)
+    print(f"[full] {name} P={P} {dtype}: E {eE:.2e} phi {ephi:.2e} F {eF:.2e}", flush=True)
+    lim = tol if tol is not None else TOL[dtype]
+    assert max(eE, ephi, eF) < lim, (eE, ephi, eF)
+
+
+@pytest.mark.parametrize("P,dtype", [(6, torch.float32), (10, torch.float32),
+                                     (6, torch.float64), (10, torch.float64)])
+def test_full_water_L40(P, dtype):
+    _sampled_parity("water_L40", P, dtype)
+
+
+@pytest.mark.parametrize("P,dtype", [(6, torch.float32), (8, torch.float32),
+                                     (8, torch.float64), (12, torch.float64)])
+def test_full_water_L100(P, dtype):
+    _sampled_parity("water_L100", P, dtype)
+
+
+@pytest.mark.parametrize("window,P", [("gaussian", 8), ("bspline", 4), ("bspline", 6)])
+def test_full_ions_1M(window, P):
+    _sampled_parity("ions_1M", P, torch.float32, window=window)
