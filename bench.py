@@ -33,6 +33,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def tile_edge(M):
+    """Tile edge the library picks for this grid (16, 12 or 8: the largest
+    leaving at least 512 tiles; LDS limits do not bind at P = 8)."""
+    for T in (16, 12):
+        if (-(-M // T)) ** 3 >= 512:
+            return T
+    return 8
+
+
 def kernel_work(stage, N, M, P, rs):
     """Algorithmic work of one launch of a stage: (kind, amount).
     Bytes for the grid passes and binning, flops for spread and gather."""
@@ -46,6 +55,10 @@ def kernel_work(stage, N, M, P, rs):
         return "flops", N * 2 * P ** 3                     # a multiply and an add per point
     if stage == "gather":
         return "flops", N * 4 * P ** 3                     # two multiply-adds per point
+    if stage == "fold":
+        T = tile_edge(M)
+        ts = T + P - 1
+        return "bytes", ((M + T - 1) // T) ** 3 * ts ** 3 * rs + grid
     if stage == "fft_x":
         return "bytes", grid + spec
     if stage == "ifft_x":

@@ -74,7 +74,8 @@ typedef enum { SE_FP32 = 0, SE_FP64 = 1 } se_dtype;
 enum {
     SE_STAGE_BIN_COUNT = 0,  /* zero grid, tile histogram, tile offsets       */
     SE_STAGE_BIN_SCATTER,    /* write particles in tile order                */
-    SE_STAGE_SPREAD,         /* step 2                                        */
+    SE_STAGE_SPREAD,         /* step 2 (tile blocks)                          */
+    SE_STAGE_FOLD,           /* step 2, tile blocks summed into the grid      */
     SE_STAGE_FFT_X,          /* step 3, real-to-complex along x              */
     SE_STAGE_FFT_Y,          /* step 3, along y                              */
     SE_STAGE_FFT_Z_SCALE,    /* steps 3-5 along z: FFT, scale + energy, IFFT */

@@ -18,7 +18,7 @@ SE_FP32 = 0
 SE_FP64 = 1
 SE_FLAG_ADD_SELF = 1
 SE_FLAG_TIMING = 2
-STAGES = ("bin_count", "bin_scatter", "spread", "fft_x", "fft_y", "fft_z_scale",
+STAGES = ("bin_count", "bin_scatter", "spread", "fold", "fft_x", "fft_y", "fft_z_scale",
           "ifft_y", "ifft_x", "gather")
 
 STATUS_NAMES = {

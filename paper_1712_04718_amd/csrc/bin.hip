@@ -6,10 +6,10 @@
 // tile touch one (T+S-1)^3 block of the grid.  Spreading and gathering then
 // run one work-group per tile with that block staged in LDS.
 //
-// k_bin_count: zero the spread grid, compute each particle's tile and its
-//   rank inside the tile (atomic counter), and the per-block sums of q^2;
-//   the last block to finish turns the tile counts into offsets (exclusive
-//   scan), resets the counts for the next call and totals q^2.
+// k_bin_count: each particle's tile and its rank inside the tile (atomic
+//   counter), and per-block sums of q^2;
+// k_bin_scan: one work-group turns the tile counts into offsets (exclusive
+//   scan), resets the counts for the next call and totals q^2;
 // k_bin_scatter: write the particles in tile order as (offsets from the
 //   anchor in grid units, q) plus (packed local anchor, original index).
 #include "se_common.hpp"
@@ -26,55 +26,57 @@ __device__ inline long long floor_div_mod(double u, int M, double *frac) {
 
 template <typename R>
 __global__ void __launch_bounds__(kThreads)
-k_bin_count(int N, const R *__restrict__ x, const R *__restrict__ q, double h,
-            int M, int T, int ntx, int *__restrict__ counts,
-            int2 *__restrict__ key, double *__restrict__ qsq_part,
-            unsigned *__restrict__ done, int *__restrict__ offsets, int ntiles,
-            double *__restrict__ qsq_total, R *__restrict__ grid,
-            long long ngrid) {
+k_bin_count(int N, const R *__restrict__ x, const R *__restrict__ q, double h, int M, int T,
+            int ntx, int *__restrict__ counts, int2 *__restrict__ key,
+            double *__restrict__ qsq_part) {
   const int tid = threadIdx.x;
-  // zero the spread grid (accumulated with atomics by the spreading kernel)
-  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + tid; i < ngrid;
-       i += static_cast<long long>(gridDim.x) * blockDim.x)
-    grid[i] = R(0);
-
   const int n = blockIdx.x * blockDim.x + tid;
   double qq = 0.0;
+  int tile = -1;
   if (n < N) {
     double frac;
     const int ax = static_cast<int>(floor_div_mod(static_cast<double>(x[3 * n + 0]) / h, M, &frac));
     const int ay = static_cast<int>(floor_div_mod(static_cast<double>(x[3 * n + 1]) / h, M, &frac));
     const int az = static_cast<int>(floor_div_mod(static_cast<double>(x[3 * n + 2]) / h, M, &frac));
-    const int tile = ((az / T) * ntx + ay / T) * ntx + ax / T;
-    const int rank = atomicAdd(&counts[tile], 1);
-    key[n] = make_int2(tile, rank);
+    tile = ((az / T) * ntx + ay / T) * ntx + ax / T;
     const double qn = static_cast<double>(q[n]);
     qq = qn * qn;
   }
-
-  __shared__ double red[kThreads];
-  red[tid] = qq;
+  // Runs of equal tiles among neighbouring lanes (the atoms of a molecule are
+  // usually adjacent in the input) take one atomic per run.
+  const int lane = tid & 63;
+  const int prev = __shfl_up(tile, 1);
+  const bool head = lane == 0 || tile != prev;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+  const int run0 = 63 - __clzll(heads & upto);            // first lane of my run
+  const unsigned long long after = heads & ~upto;
+  const int run_end = after ? __ffsll(after) - 1 : 64;    // first lane of the next run
+  int base = 0;
+  if (head && tile >= 0) base = atomicAdd(&counts[tile * kCountStride], run_end - lane);
+  base = __shfl(base, run0);
+  if (tile >= 0) key[n] = make_int2(tile, base + lane - run0);
+  for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o);
+  __shared__ double red[kThreads / 64];
+  if ((tid & 63) == 0) red[tid >> 6] = qq;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    qsq_part[blockIdx.x] = s;
   }
-  if (tid == 0) qsq_part[blockIdx.x] = red[0];
+}
 
-  // Last-arriving block: exclusive scan of the tile counts.
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) is_last = (atomicAdd(done, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-
+// One work-group: exclusive scan of the tile counts into offsets, counts reset
+// for the next call, and the total of q^2 (fixed order, deterministic).
+__global__ void __launch_bounds__(kThreads)
+k_bin_scan(int *__restrict__ counts, int *__restrict__ offsets, int ntiles,
+           const double *__restrict__ qsq_part, int nparts, double *__restrict__ qsq_total) {
+  const int tid = threadIdx.x;
   const int chunk = (ntiles + kThreads - 1) / kThreads;
   const int lo = min(tid * chunk, ntiles), hi = min(lo + chunk, ntiles);
   int local = 0;
-  for (int t = lo; t < hi; ++t)
-    local += __hip_atomic_load(&counts[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int t = lo; t < hi; ++t) local += counts[t * kCountStride];
   __shared__ int scan[kThreads];
   scan[tid] = local;
   __syncthreads();
@@ -84,29 +86,25 @@ k_bin_count(int N, const R *__restrict__ x, const R *__restrict__ q, double h,
     scan[tid] += v;
     __syncthreads();
   }
-  int run = scan[tid] - local;  // exclusive prefix of this chunk
+  int run = scan[tid] - local;
   for (int t = lo; t < hi; ++t) {
-    const int c = __hip_atomic_load(&counts[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int c = counts[t * kCountStride];
     offsets[t] = run;
     run += c;
-    counts[t] = 0;  // ready for the next call
+    counts[t * kCountStride] = 0;
   }
   if (tid == kThreads - 1) offsets[ntiles] = scan[kThreads - 1];
 
-  // total of q^2 in a fixed order (deterministic)
+  __shared__ double red[kThreads];
   double s = 0.0;
-  for (int b = tid; b < static_cast<int>(gridDim.x); b += kThreads)
-    s += __hip_atomic_load(&qsq_part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int b = tid; b < nparts; b += kThreads) s += qsq_part[b];
   red[tid] = s;
   __syncthreads();
   for (int st = kThreads / 2; st > 0; st >>= 1) {
     if (tid < st) red[tid] += red[tid + st];
     __syncthreads();
   }
-  if (tid == 0) {
-    *qsq_total = red[0];
-    *done = 0u;
-  }
+  if (tid == 0) *qsq_total = red[0];
 }
 
 template <typename R>
@@ -135,15 +133,21 @@ k_bin_scatter(int N, const R *__restrict__ x, const R *__restrict__ q, double h,
 template <typename R>
 hipError_t bin_impl(se_plan &p, int N, const void *x, const void *q) {
   const int M = p.prm.M;
-  const long long ngrid = static_cast<long long>(M) * M * M;
-  const int blocks = N > 0 ? (N + kThreads - 1) / kThreads : 1;
+  const int blocks = N > 0 ? (N + kThreads - 1) / kThreads : 0;
+  hipError_t e = hipSuccess;
   stage_begin(p, SE_STAGE_BIN_COUNT);
-  k_bin_count<R><<<blocks, kThreads, 0, p.stream>>>(
-      N, static_cast<const R *>(x), static_cast<const R *>(q), p.h, M, p.T, p.ntx,
-      p.buf.counts, p.buf.key, p.buf.part, p.buf.done, p.buf.offsets, p.ntiles,
-      p.buf.qsq, static_cast<R *>(p.buf.grid), ngrid);
+  if (blocks > 0) {
+    k_bin_count<R><<<blocks, kThreads, 0, p.stream>>>(
+        N, static_cast<const R *>(x), static_cast<const R *>(q), p.h, M, p.T, p.ntx,
+        p.buf.counts, p.buf.key, p.buf.part);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    k_bin_scan<<<1, kThreads, 0, p.stream>>>(p.buf.counts, p.buf.offsets, p.ntiles, p.buf.part,
+                                           blocks, p.buf.qsq);
+    e = hipGetLastError();
+  }
   stage_end(p, SE_STAGE_BIN_COUNT);
-  hipError_t e = hipGetLastError();
   if (e != hipSuccess || N == 0) return e;
   stage_begin(p, SE_STAGE_BIN_SCATTER);
   k_bin_scatter<R><<<blocks, kThreads, 0, p.stream>>>(

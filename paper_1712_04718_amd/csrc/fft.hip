@@ -3,17 +3,17 @@
 //
 // Five passes over a half spectrum C[z][y][kx], kx = 0..M/2 (row length
 // K = M/2 + 1), all built on one batched Stockham FFT held in LDS:
-//   x_r2c : pairs of real rows packed as one complex row, FFT, split into two
-//           half spectra;
+//   x_r2c : pairs of real rows packed as one complex row, transformed, and
+//           split into two half spectra;
 //   y_fwd : FFT along y of B adjacent kx columns of one z-plane;
 //   z     : FFT along z of B adjacent (y,kx) pencils, scale by the
 //           influence function w(k) (eq. 4.6 for SE, eq. 6.2 for SPME)
 //           times 4 pi / L^3, accumulate the energy
 //             E = 1/2 sum_k mu(kx) w(k) |G^(k)|^2   (FP64),
 //           mu = 1 on kx = 0 and kx = M/2 and 2 elsewhere (Hermitian half),
-//           then the inverse FFT along z; the last block adds the partial
-//           energies in a fixed order;
-//   y_inv : inverse FFT along y;
+//           then the inverse FFT along z; one energy partial per block;
+//   y_inv : inverse FFT along y; its first work-group adds the energy
+//           partials in a fixed order;
 //   x_c2r : two half spectra rebuilt into one Hermitian-packed complex row,
 //           inverse FFT, real and imaginary parts are the two real rows.
 // Forward transforms use e^{-i k.x}, inverse ones e^{+i k.x}, both
@@ -28,6 +28,10 @@ namespace sek {
 namespace {
 
 extern __shared__ __align__(16) unsigned char f_smem[];
+
+// Complex elements per thread when a work-group loads its B pencils
+// (M * B <= 16 * threads for every plan, see fft_batch_of).
+constexpr int kMaxPerThread = 16;
 
 template <typename C> __device__ inline C cmul(C a, C b) {
   C r;
@@ -105,22 +109,24 @@ template <typename R, typename C> __device__ inline void dft8(C *v) {
   v[3] = cadd(e[3], w3);   v[7] = csub(e[3], w3);
 }
 
-// One radix stage of the Stockham autosort FFT on B pencils:
+// One radix stage of the Stockham autosort FFT on B = 2^lgB pencils:
 //   in[(j + r M/R) B + b] -> twiddle by w^{r k}, k = j mod Ns, w = e^{-2pi i/(Ns R)}
 //   -> R-point DFT -> out[((j/Ns) Ns R + k + r Ns) B + b].
 template <typename R, int RAD>
-__device__ inline void stockham_stage(const cplx_t<R> *in, cplx_t<R> *out, int M, int B,
-                                      int Ns, const cplx_t<R> *__restrict__ tw) {
+__device__ inline void stockham_stage(const cplx_t<R> *in, cplx_t<R> *out, int M, int lgB,
+                                      int Ns, unsigned ns_magic, int tstep,
+                                      const cplx_t<R> *tw) {
   using C = cplx_t<R>;
   const int nb = M / RAD;
-  const int total = nb * B;
-  const int tstep = M / (Ns * RAD);
+  const int total = nb << lgB;
+  const int bmask = (1 << lgB) - 1;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int b = t % B, j = t / B;
-    const int k = j % Ns;
+    const int b = t & bmask, j = t >> lgB;
+    const int q = (Ns == 1) ? j : fast_div(j, ns_magic);
+    const int k = j - q * Ns;
     C v[RAD];
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) v[r] = in[(j + r * nb) * B + b];
+    for (int r = 0; r < RAD; ++r) v[r] = in[((j + r * nb) << lgB) + b];
     if (k != 0) {
 #pragma unroll
       for (int r = 1; r < RAD; ++r) v[r] = cmul(v[r], tw[r * k * tstep]);
@@ -130,30 +136,30 @@ __device__ inline void stockham_stage(const cplx_t<R> *in, cplx_t<R> *out, int M
     if constexpr (RAD == 4) dft4<R, C>(v);
     if constexpr (RAD == 5) dft5<R, C>(v);
     if constexpr (RAD == 8) dft8<R, C>(v);
-    const int dst = (j / Ns) * Ns * RAD + k;
+    const int dst = q * Ns * RAD + k;
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) out[(dst + r * Ns) * B + b] = v[r];
+    for (int r = 0; r < RAD; ++r) out[((dst + r * Ns) << lgB) + b] = v[r];
   }
 }
 
-// Forward FFT of B pencils held in buf0; returns the buffer with the result.
+// Forward FFT of B = 2^lgB pencils held in buf0; returns the buffer with the result.
 template <typename R>
-__device__ cplx_t<R> *fft_batch(cplx_t<R> *buf0, cplx_t<R> *buf1, int B, const FftPlan &pl,
-                                const cplx_t<R> *__restrict__ tw) {
+__device__ cplx_t<R> *fft_batch(cplx_t<R> *buf0, cplx_t<R> *buf1, int lgB, const FftPlan &pl,
+                                const cplx_t<R> *tw) {
   cplx_t<R> *in = buf0, *out = buf1;
-  int Ns = 1;
   for (int s = 0; s < pl.nstages; ++s) {
-    const int rad = pl.radix[s];
-    switch (rad) {
-      case 2: stockham_stage<R, 2>(in, out, pl.M, B, Ns, tw); break;
-      case 3: stockham_stage<R, 3>(in, out, pl.M, B, Ns, tw); break;
-      case 4: stockham_stage<R, 4>(in, out, pl.M, B, Ns, tw); break;
-      case 5: stockham_stage<R, 5>(in, out, pl.M, B, Ns, tw); break;
-      default: stockham_stage<R, 8>(in, out, pl.M, B, Ns, tw); break;
+    const int Ns = pl.ns[s];
+    const unsigned mg = pl.ns_magic[s];
+    const int ts = pl.tstep[s];
+    switch (pl.radix[s]) {
+      case 2: stockham_stage<R, 2>(in, out, pl.M, lgB, Ns, mg, ts, tw); break;
+      case 3: stockham_stage<R, 3>(in, out, pl.M, lgB, Ns, mg, ts, tw); break;
+      case 4: stockham_stage<R, 4>(in, out, pl.M, lgB, Ns, mg, ts, tw); break;
+      case 5: stockham_stage<R, 5>(in, out, pl.M, lgB, Ns, mg, ts, tw); break;
+      default: stockham_stage<R, 8>(in, out, pl.M, lgB, Ns, mg, ts, tw); break;
     }
     __syncthreads();
     cplx_t<R> *t = in; in = out; out = t;
-    Ns *= rad;
   }
   return in;
 }
@@ -162,30 +168,41 @@ __device__ cplx_t<R> *fft_batch(cplx_t<R> *buf0, cplx_t<R> *buf1, int B, const F
 
 template <typename R>
 __global__ void __launch_bounds__(kThreads)
-k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl, int B,
-            const cplx_t<R> *__restrict__ tw) {
+k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB,
+            const cplx_t<R> *__restrict__ tw_g) {
   using C = cplx_t<R>;
-  const int M = pl.M, K = M / 2 + 1;
+  const int M = pl.M, K = M / 2 + 1, B = 1 << lgB;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  C *twl = b1 + M * B;  // twiddles staged in LDS
+  for (int i = threadIdx.x; i < M; i += blockDim.x) twl[i] = tw_g[i];
   const long long nrows = static_cast<long long>(M) * M;
   const long long row0 = static_cast<long long>(blockIdx.x) * 2 * B;
-  // row r of the batch goes to pencil r/2, real part for even r, imag for odd
-  for (int i = threadIdx.x; i < 2 * B * M; i += blockDim.x) {
-    const int r = i / M, xk = i - r * M;
-    const long long gr = row0 + r;
-    const R v = gr < nrows ? grid[gr * M + xk] : R(0);
-    R *slot = reinterpret_cast<R *>(&b0[xk * B + (r >> 1)]);
-    slot[r & 1] = v;
+  // row r of the batch goes to pencil r/2, real part for even r, imag for odd;
+  // all loads are issued before the first LDS store
+  R v[2 * kMaxPerThread];
+#pragma unroll
+  for (int k = 0; k < 2 * kMaxPerThread; ++k) {
+    const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
+    const long long gr = row0 + fast_div(i, pl.m_magic);
+    v[k] = (i < 2 * B * M && gr < nrows) ? grid[row0 * M + i] : R(0);
+  }
+#pragma unroll
+  for (int k = 0; k < 2 * kMaxPerThread; ++k) {
+    const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
+    if (i < 2 * B * M) {
+      const int r = fast_div(i, pl.m_magic), xk = i - r * M;
+      reinterpret_cast<R *>(&b0[xk * B + (r >> 1)])[r & 1] = v[k];
+    }
   }
   __syncthreads();
-  const C *Z = fft_batch<R>(b0, b1, B, pl, tw);
+  const C *Z = fft_batch<R>(b0, b1, lgB, pl, twl);
   // Z = FFT(r1 + i r2): R1[k] = (Z[k] + conj Z[M-k]) / 2, R2[k] = (Z[k] - conj Z[M-k]) / 2i
   for (int i = threadIdx.x; i < B * K; i += blockDim.x) {
-    const int b = i / K, k = i - b * K;
+    const int b = fast_div(i, pl.k_magic), k = i - b * K;
     const long long gr = row0 + 2 * b;
     if (gr >= nrows) continue;
     const C zk = Z[k * B + b];
-    const C zm = Z[((M - k) % M) * B + b];
+    const C zm = Z[(k == 0 ? 0 : M - k) * B + b];
     C r1, r2;
     r1.x = R(0.5) * (zk.x + zm.x);
     r1.y = R(0.5) * (zk.y - zm.y);
@@ -198,17 +215,19 @@ k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl
 
 template <typename R>
 __global__ void __launch_bounds__(kThreads)
-k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl, int B,
-            const cplx_t<R> *__restrict__ tw) {
+k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl, int lgB,
+            const cplx_t<R> *__restrict__ tw_g) {
   using C = cplx_t<R>;
-  const int M = pl.M, K = M / 2 + 1;
+  const int M = pl.M, K = M / 2 + 1, B = 1 << lgB;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  C *twl = b1 + M * B;  // twiddles staged in LDS
+  for (int i = threadIdx.x; i < M; i += blockDim.x) twl[i] = tw_g[i];
   const long long nrows = static_cast<long long>(M) * M;
   const long long row0 = static_cast<long long>(blockIdx.x) * 2 * B;
   // Z[k] = R1[k] + i R2[k] on 0..M/2 and conj(R1[M-k]) + i conj(R2[M-k]) above;
   // stored conjugated for the inverse transform.
   for (int i = threadIdx.x; i < B * K; i += blockDim.x) {
-    const int b = i / K, k = i - b * K;
+    const int b = fast_div(i, pl.k_magic), k = i - b * K;
     const long long gr = row0 + 2 * b;
     C r1, r2;
     if (gr < nrows) {
@@ -229,9 +248,9 @@ k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl
     }
   }
   __syncthreads();
-  const C *Z = fft_batch<R>(b0, b1, B, pl, tw);
+  const C *Z = fft_batch<R>(b0, b1, lgB, pl, twl);
   for (int i = threadIdx.x; i < 2 * B * M; i += blockDim.x) {
-    const int r = i / M, xk = i - r * M;
+    const int r = fast_div(i, pl.m_magic), xk = i - r * M;
     const long long gr = row0 + r;
     if (gr >= nrows) continue;
     const C z = Z[xk * B + (r >> 1)];
@@ -241,33 +260,70 @@ k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl
 
 // ---------------------------------------------------------------- y passes
 
+// For the inverse pass, work-group (0,0) also adds the energy partials of
+// the z pass in a fixed order and writes E (plus the self energy if asked).
+struct EnergyOut {
+  const double *part;
+  int nparts;
+  const double *qsq;
+  double self_coef;
+  double *E;
+};
+
 template <typename R, bool INV>
 __global__ void __launch_bounds__(kThreads)
-k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int B, const cplx_t<R> *__restrict__ tw) {
+k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__restrict__ tw_g,
+        EnergyOut eo) {
   using C = cplx_t<R>;
-  const int M = pl.M, K = M / 2 + 1;
+  const int M = pl.M, K = M / 2 + 1, B = 1 << lgB;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  C *twl = b1 + M * B;  // twiddles staged in LDS
+  for (int i = threadIdx.x; i < M; i += blockDim.x) twl[i] = tw_g[i];
   const int kx0 = blockIdx.x * B;
   const long long zoff = static_cast<long long>(blockIdx.y) * M * K;
-  for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
-    const int y = i / B, b = i - y * B;
-    C v;
-    if (kx0 + b < K) {
-      v = spec[zoff + static_cast<long long>(y) * K + kx0 + b];
-      if (INV) v = cconj(v);
-    } else {
-      v.x = v.y = R(0);
+  {
+    C v[kMaxPerThread];
+#pragma unroll
+    for (int k = 0; k < kMaxPerThread; ++k) {
+      const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
+      const int y = i >> lgB, b = i & (B - 1);
+      if (i < M * B && kx0 + b < K) {
+        v[k] = spec[zoff + static_cast<long long>(y) * K + kx0 + b];
+        if (INV) v[k] = cconj(v[k]);
+      } else {
+        v[k].x = v[k].y = R(0);
+      }
     }
-    b0[i] = v;
+#pragma unroll
+    for (int k = 0; k < kMaxPerThread; ++k) {
+      const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
+      if (i < M * B) b0[i] = v[k];
+    }
   }
   __syncthreads();
-  const C *Z = fft_batch<R>(b0, b1, B, pl, tw);
+  const C *Z = fft_batch<R>(b0, b1, lgB, pl, twl);
   for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
-    const int y = i / B, b = i - y * B;
+    const int y = i >> lgB, b = i & (B - 1);
     if (kx0 + b < K) {
       C v = Z[i];
       if (INV) v = cconj(v);
       spec[zoff + static_cast<long long>(y) * K + kx0 + b] = v;
+    }
+  }
+  if (INV && blockIdx.x == 0 && blockIdx.y == 0) {
+    __shared__ double red[kThreads];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < eo.nparts; b += blockDim.x) s += eo.part[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double E = red[0];
+      if (eo.self_coef != 0.0) E += eo.self_coef * (*eo.qsq);
+      *eo.E = E;
     }
   }
 }
@@ -276,37 +332,46 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int B, const cplx_t<R> *__rest
 
 template <typename R>
 __global__ void __launch_bounds__(kThreads)
-k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int B, const cplx_t<R> *__restrict__ tw,
+k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__restrict__ tw_g,
               const double *__restrict__ axis_f, const double *__restrict__ axis_k2,
-              double wscale, double *__restrict__ epart, unsigned *__restrict__ done,
-              const double *__restrict__ qsq, double self_coef, double *__restrict__ E_out) {
+              double wscale, double *__restrict__ epart) {
   using C = cplx_t<R>;
-  const int M = pl.M, K = M / 2 + 1;
+  const int M = pl.M, K = M / 2 + 1, B = 1 << lgB;
   const int npen = M * K;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  C *twl = b1 + M * B;  // twiddles staged in LDS
+  for (int i = threadIdx.x; i < M; i += blockDim.x) twl[i] = tw_g[i];
   const int c0 = blockIdx.x * B;
   const long long zs = static_cast<long long>(M) * K;
-  for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
-    const int z = i / B, b = i - z * B;
-    C v;
-    if (c0 + b < npen) {
-      v = spec[z * zs + c0 + b];
-    } else {
-      v.x = v.y = R(0);
+  {
+    C v[kMaxPerThread];
+#pragma unroll
+    for (int k = 0; k < kMaxPerThread; ++k) {
+      const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
+      const int z = i >> lgB, b = i & (B - 1);
+      if (i < M * B && c0 + b < npen) {
+        v[k] = spec[z * zs + c0 + b];
+      } else {
+        v[k].x = v[k].y = R(0);
+      }
     }
-    b0[i] = v;
+#pragma unroll
+    for (int k = 0; k < kMaxPerThread; ++k) {
+      const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
+      if (i < M * B) b0[i] = v[k];
+    }
   }
   __syncthreads();
-  C *Z = fft_batch<R>(b0, b1, B, pl, tw);
+  C *Z = fft_batch<R>(b0, b1, lgB, pl, twl);
   C *other = (Z == b0) ? b1 : b0;
 
   double e = 0.0;
   for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
-    const int kz = i / B, b = i - kz * B;
+    const int kz = i >> lgB, b = i & (B - 1);
     const int c = c0 + b;
     C v = Z[i];
     if (c < npen) {
-      const int ky = c / K, kx = c - ky * K;
+      const int ky = fast_div(c, pl.k_magic), kx = c - ky * K;
       const double k2 = axis_k2[kx] + axis_k2[ky] + axis_k2[kz];
       const double w = (kx == 0 && ky == 0 && kz == 0)
                            ? 0.0
@@ -323,80 +388,60 @@ k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int B, const cplx_t<R> *
     Z[i] = v;  // holds conj(w * G^)
   }
   __syncthreads();
-  const C *Y = fft_batch<R>(Z, other, B, pl, tw);
+  const C *Y = fft_batch<R>(Z, other, lgB, pl, twl);
   for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
-    const int z = i / B, b = i - z * B;
+    const int z = i >> lgB, b = i & (B - 1);
     if (c0 + b < npen) spec[z * zs + c0 + b] = cconj(Y[i]);
   }
 
-  // energy: block sum, then the last block adds all partials in order
+  // energy: one partial per block, added in a fixed order by the next pass
   __shared__ double red[kThreads];
   red[threadIdx.x] = e;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  __shared__ int is_last;
-  if (threadIdx.x == 0) {
-    epart[blockIdx.x] = red[0];
-    __threadfence();
-    is_last = (atomicAdd(done, 1u) == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double s = 0.0;
-  for (int b = threadIdx.x; b < static_cast<int>(gridDim.x); b += kThreads)
-    s += __hip_atomic_load(&epart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int st = kThreads / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double E = red[0];
-    if (self_coef != 0.0) E += self_coef * (*qsq);
-    *E_out = E;
-    *done = 0u;
-  }
+  if (threadIdx.x == 0) epart[blockIdx.x] = red[0];
 }
 
 template <typename R>
 hipError_t fft_impl(se_plan &p, double *E_dev) {
   using C = cplx_t<R>;
   const int M = p.prm.M, K = M / 2 + 1, B = p.fft_batch;
-  const size_t lds = 2 * sizeof(C) * M * B;
+  int lgB = 0;
+  while ((1 << lgB) < B) ++lgB;
+  const size_t lds = sizeof(C) * (2 * M * B + M);
   C *spec = static_cast<C *>(p.buf.spec);
   const C *tw = static_cast<const C *>(p.buf.twiddle);
   const int xblocks = (M * M + 2 * B - 1) / (2 * B);
+  hipError_t e = hipSuccess;
   stage_begin(p, SE_STAGE_FFT_X);
-  k_fft_x_r2c<R><<<xblocks, kThreads, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec,
-                                                     p.fft, B, tw);
+  k_fft_x_r2c<R><<<xblocks, p.fft_threads, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec,
+                                                     p.fft, lgB, tw);
   stage_end(p, SE_STAGE_FFT_X);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const dim3 yg((K + B - 1) / B, M);
+  const EnergyOut none{nullptr, 0, nullptr, 0.0, nullptr};
   stage_begin(p, SE_STAGE_FFT_Y);
-  k_fft_y<R, false><<<yg, kThreads, lds, p.stream>>>(spec, p.fft, B, tw);
+  k_fft_y<R, false><<<yg, p.fft_threads, lds, p.stream>>>(spec, p.fft, lgB, tw, none);
   stage_end(p, SE_STAGE_FFT_Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const double self_coef = (p.prm.flags & SE_FLAG_ADD_SELF) ? -p.prm.xi / sqrt(M_PI) : 0.0;
   stage_begin(p, SE_STAGE_FFT_Z_SCALE);
-  k_fft_z_scale<R><<<p.zfft_blocks, kThreads, lds, p.stream>>>(
-      spec, p.fft, B, tw, static_cast<const double *>(p.buf.axis_f),
-      static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks,
-      p.buf.done + 1, p.buf.qsq, self_coef, E_dev);
+  k_fft_z_scale<R><<<p.zfft_blocks, p.fft_threads, lds, p.stream>>>(
+      spec, p.fft, lgB, tw, static_cast<const double *>(p.buf.axis_f),
+      static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks);
   stage_end(p, SE_STAGE_FFT_Z_SCALE);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  const double self_coef = (p.prm.flags & SE_FLAG_ADD_SELF) ? -p.prm.xi / sqrt(M_PI) : 0.0;
+  const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.qsq, self_coef, E_dev};
   stage_begin(p, SE_STAGE_IFFT_Y);
-  k_fft_y<R, true><<<yg, kThreads, lds, p.stream>>>(spec, p.fft, B, tw);
+  k_fft_y<R, true><<<yg, p.fft_threads, lds, p.stream>>>(spec, p.fft, lgB, tw, eo);
   stage_end(p, SE_STAGE_IFFT_Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   stage_begin(p, SE_STAGE_IFFT_X);
-  k_fft_x_c2r<R><<<xblocks, kThreads, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), p.fft,
-                                                     B, tw);
+  k_fft_x_c2r<R><<<xblocks, p.fft_threads, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), p.fft,
+                                                     lgB, tw);
   stage_end(p, SE_STAGE_IFFT_X);
   return hipGetLastError();
 }

@@ -7,14 +7,14 @@
 // grad_q = gE phi and grad_x = -gE F, with gE read from device memory.
 //
 // One work-group per tile: the (T+S-1)^3 block of the scaled grid Phi that
-// the tile's particles touch is staged in LDS.  Each wave takes the tile's
-// particles in chunks:
-//   phase A: one lane per particle computes its window factors (and, for
-//            B-splines, their derivatives) into the wave's LDS area;
+// the tile's particles touch is staged in LDS, and the tile's particles are
+// taken in chunks of one per thread:
+//   phase A: each thread computes its particle's window factors (and, for
+//            B-splines, their derivatives) into LDS;
 //   phase B: lane (group, jx) owns the x-offset jx of one particle and sums
 //            over the S^2 (jy, jz) offsets; the S lanes of a particle are
-//            then combined in LDS.
-// FP32 sums are compensated (Kahan) at the y level and across lanes.
+//            then combined (shuffle tree for S = 4, 8, 16; in LDS otherwise).
+// Per-lane sums over y are compensated (Kahan).
 #include "se_common.hpp"
 #include "window.hpp"
 
@@ -34,17 +34,25 @@ template <typename R> struct Kahan {
   __device__ inline R value() const { return s - c; }
 };
 
-// LDS layout: [tile block][reduction scratch][per wave: factors, anchors, indices]
+// particles per phase-A round: one per thread, fewer when the factor table
+// would exceed 32 KB
+constexpr int gather_chunk(int real_size, int rec) {
+  return (real_size * rec * kThreads <= 32768) ? kThreads
+         : (real_size * rec * (kThreads / 2) <= 32768) ? kThreads / 2 : kThreads / 4;
+}
+constexpr int gather_rec(int window, int S) { return window == kGauss ? 3 * S + 4 : 6 * S + 1; }
+
+// LDS layout: [tile block][lane partials][factors][anchors][original indices]
 template <typename R, int WIN, int S, int T> struct GatherLds {
   static constexpr int TS = T + S - 1;
-  static constexpr int CH = Chunk<S>::CH;
   // SE: g (3S), offsets d (3), q; B-spline: g (3S), dg (3S), q
-  static constexpr int REC = (WIN == kGauss) ? 3 * S + 4 : 6 * S + 1;
+  static constexpr int REC = gather_rec(WIN, S);
+  static constexpr int CHUNK = gather_chunk(sizeof(R), REC);
   static constexpr size_t BLK = sizeof(R) * ((TS * TS * TS + 3) & ~3);
-  static constexpr size_t RED = sizeof(R) * (kThreads / 64) * 64 * 4;
-  static constexpr size_t FAC = sizeof(R) * CH * REC;
-  static constexpr size_t IDX = 2 * sizeof(int) * CH;
-  static constexpr size_t TOTAL = BLK + RED + (kThreads / 64) * (FAC + IDX);
+  static constexpr size_t RED = sizeof(R) * kThreads * 4;
+  static constexpr size_t FAC = sizeof(R) * CHUNK * REC;
+  static constexpr size_t IDX = 2 * sizeof(int) * CHUNK;
+  static constexpr size_t TOTAL = BLK + RED + FAC + IDX;
 };
 
 template <typename R, int WIN, int S, int T>
@@ -54,10 +62,11 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
          WindowConsts wc, const double *__restrict__ gscale, int mode, R self_coef,
          R *__restrict__ out_pot, R *__restrict__ out_vec) {
   using L = GatherLds<R, WIN, S, T>;
-  constexpr int TS = L::TS, CH = L::CH, REC = L::REC;
-  constexpr int GROUPS = Chunk<S>::GROUPS;
+  constexpr int TS = L::TS, REC = L::REC, CHUNK = L::CHUNK;
+  constexpr int GROUPS = 64 / S;
   constexpr int OFF = Stencil<WIN, S>::OFF;
   constexpr int NWAVES = kThreads / 64;
+  constexpr bool POW2 = (S & (S - 1)) == 0;
 
   const int tile = blockIdx.x;
   const int start = offsets[tile], end = offsets[tile + 1];
@@ -66,33 +75,30 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   R *blk = reinterpret_cast<R *>(h_smem);
-  R *wred = reinterpret_cast<R *>(h_smem + L::BLK) + wave * 64 * 4;
-  unsigned char *wbase = h_smem + L::BLK + L::RED + wave * (L::FAC + L::IDX);
-  R *fac = reinterpret_cast<R *>(wbase);
-  int *anc = reinterpret_cast<int *>(wbase + L::FAC);
-  int *org = anc + CH;
+  R *red = reinterpret_cast<R *>(h_smem + L::BLK);
+  R *fac = reinterpret_cast<R *>(h_smem + L::BLK + L::RED);
+  int *anc = reinterpret_cast<int *>(h_smem + L::BLK + L::RED + L::FAC);
+  int *org = anc + CHUNK;
 
   const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
   const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
   for (int i = tid; i < TS * TS * TS; i += kThreads) {
     const int lz = i / (TS * TS), ly = (i / TS) % TS, lx = i % TS;
-    int gz = (bz + lz) % M, gy = (by + ly) % M, gx = (bx + lx) % M;
-    gz += gz < 0 ? M : 0;
-    gy += gy < 0 ? M : 0;
-    gx += gx < 0 ? M : 0;
+    const int gz = wrap_index(bz + lz, M), gy = wrap_index(by + ly, M), gx = wrap_index(bx + lx, M);
     blk[i] = phi_grid[(static_cast<long long>(gz) * M + gy) * M + gx];
   }
-  __syncthreads();
 
   const R scale = gscale ? static_cast<R>(*gscale) : R(1);
   const int grp = lane / S, jx = lane - grp * S;
-  for (int base = start + wave * CH; base < end; base += NWAVES * CH) {
-    const int nval = min(CH, end - base);
-    // phase A
-    if (lane < nval) {
-      const SortedParticle<R> sp = sorted[base + lane];
-      const int2 mt = meta[base + lane];
-      R *f = fac + lane * REC;
+  R *wred = red + wave * 64 * 4;
+  for (int base = start; base < end; base += CHUNK) {
+    const int nval = min(CHUNK, end - base);
+    __syncthreads();  // grid block staged; previous round done with the factors
+    // phase A: factors of particle base + tid
+    if (tid < nval) {
+      const SortedParticle<R> sp = sorted[base + tid];
+      const int2 mt = meta[base + tid];
+      R *f = fac + tid * REC;
       R g[S], dg[S];
       const R dd[3] = {sp.dx, sp.dy, sp.dz};
 #pragma unroll
@@ -108,15 +114,13 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
         }
       }
       f[REC - 1] = sp.q;
-      anc[lane] = mt.x;
-      org[lane] = mt.y;
+      anc[tid] = mt.x;
+      org[tid] = mt.y;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // phase B
+    __syncthreads();
+    // phase B: particle groups of S lanes across the work-group
     if (grp < GROUPS) {
-      for (int c = grp; c < nval; c += GROUPS) {
+      for (int c = wave * GROUPS + grp; c < nval; c += NWAVES * GROUPS) {
         const R *f = fac + c * REC;
         const int packed = anc[c];
         const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
@@ -160,42 +164,58 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
           s_fz.add(gy[jy] * a1);
         }
         const R sp_v = s_pot.value();
-        R *mine = wred + lane * 4;
-        mine[0] = gx * sp_v;
-        mine[1] = dgx * sp_v;
-        mine[2] = gx * s_fy.value();
-        mine[3] = gx * s_fz.value();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (jx == 0) {
-          Kahan<R> t0, t1, t2, t3;
-          const R *g = wred + grp * S * 4;
+        R t0 = gx * sp_v, t1 = dgx * sp_v, t2 = gx * s_fy.value(), t3 = gx * s_fz.value();
+        if constexpr (POW2) {
+          // pairwise tree over the S lanes of the group
 #pragma unroll
-          for (int l = 0; l < S; ++l) {
-            t0.add(g[4 * l + 0]);
-            t1.add(g[4 * l + 1]);
-            t2.add(g[4 * l + 2]);
-            t3.add(g[4 * l + 3]);
+          for (int o = S / 2; o > 0; o >>= 1) {
+            t0 += __shfl_xor(t0, o);
+            t1 += __shfl_xor(t1, o);
+            t2 += __shfl_xor(t2, o);
+            t3 += __shfl_xor(t3, o);
           }
+        } else {
+          R *mine = wred + lane * 4;
+          mine[0] = t0;
+          mine[1] = t1;
+          mine[2] = t2;
+          mine[3] = t3;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (jx == 0) {
+            Kahan<R> k0, k1, k2, k3;
+            const R *g = wred + grp * S * 4;
+#pragma unroll
+            for (int l = 0; l < S; ++l) {
+              k0.add(g[4 * l + 0]);
+              k1.add(g[4 * l + 1]);
+              k2.add(g[4 * l + 2]);
+              k3.add(g[4 * l + 3]);
+            }
+            t0 = k0.value();
+            t1 = k1.value();
+            t2 = k2.value();
+            t3 = k3.value();
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        }
+        if (jx == 0) {
           const R q = f[REC - 1];
           const int orig = org[c];
-          const R pot = t0.value() + self_coef * q;
+          const R pot = t0 + self_coef * q;
           // potential-force mode: F = -q (t1, t2, t3); adjoint: -gE F = gE q (t1, t2, t3)
           const R fq = (mode == kGatherPotentialForce) ? -scale * q : scale * q;
           if (out_pot) out_pot[orig] = scale * pot;
           if (out_vec) {
-            out_vec[3 * orig + 0] = fq * t1.value();
-            out_vec[3 * orig + 1] = fq * t2.value();
-            out_vec[3 * orig + 2] = fq * t3.value();
+            out_vec[3 * orig + 0] = fq * t1;
+            out_vec[3 * orig + 1] = fq * t2;
+            out_vec[3 * orig + 2] = fq * t3;
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -244,6 +264,9 @@ hipError_t gather_dispatch(se_plan &p, const double *g, int mode, void *a, void 
   if (p.T == 16)
     return gauss ? gather_dispatch_S<R, kGauss, 16>(p, g, mode, a, b)
                  : gather_dispatch_S<R, kBspline, 16>(p, g, mode, a, b);
+  if (p.T == 12)
+    return gauss ? gather_dispatch_S<R, kGauss, 12>(p, g, mode, a, b)
+                 : gather_dispatch_S<R, kBspline, 12>(p, g, mode, a, b);
   return gauss ? gather_dispatch_S<R, kGauss, 8>(p, g, mode, a, b)
                : gather_dispatch_S<R, kBspline, 8>(p, g, mode, a, b);
 }
@@ -252,11 +275,11 @@ hipError_t gather_dispatch(se_plan &p, const double *g, int mode, void *a, void 
 
 size_t gather_lds_bytes(int real_size, int window, int S, int T) {
   const size_t ts = T + S - 1;
-  const size_t groups = 64 / S, ch = groups * ((32 + groups - 1) / groups);
-  const size_t rec = window == SE_WINDOW_GAUSSIAN ? 3 * S + 4 : 6 * S + 1;
+  const int win = window == SE_WINDOW_GAUSSIAN ? kGauss : kBspline;
+  const size_t rec = gather_rec(win, S);
+  const size_t chunk = gather_chunk(real_size, static_cast<int>(rec));
   return real_size * ((ts * ts * ts + 3) & ~static_cast<size_t>(3)) +
-         real_size * (kThreads / 64) * 64 * 4 +
-         (kThreads / 64) * (real_size * ch * rec + 2 * 4 * ch);
+         static_cast<size_t>(real_size) * kThreads * 4 + real_size * chunk * rec + 2 * 4 * chunk;
 }
 
 hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode, void *out_pot,

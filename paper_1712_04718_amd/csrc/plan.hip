@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -46,23 +47,30 @@ double eta_of(const se_params &p) {
 
 int real_size(const se_params &p) { return p.dtype == SE_FP64 ? 8 : 4; }
 
-// Tile edge for spreading/gathering: 16 where there are still many tiles per
-// axis (fewer halo points per particle) and the LDS blocks fit, else 8.
+// Tile edge for spreading/gathering: the largest of 16, 12, 8 that still
+// leaves at least 512 tiles (enough work-groups for 256 CUs) and whose LDS
+// blocks fit; larger tiles have fewer halo points per particle.
 int choose_tile(const se_params &p) {
   const int rs = real_size(p), S = p.P;
   const auto fits = [&](int T) {
     return sek::spread_lds_bytes(rs, S, T) <= sek::kMaxLds &&
            sek::gather_lds_bytes(rs, p.window, S, T) <= sek::kMaxLds;
   };
-  if (p.M >= 160 && fits(16)) return 16;
+  for (int T : {16, 12}) {
+    const long long nt = (p.M + T - 1) / T;
+    if (nt * nt * nt >= 512 && fits(T)) return T;
+  }
   return 8;
 }
 
+// FFT work-groups are kFftThreads lanes holding B pencils: B a power of two
+// with M * B <= 16 * kFftThreads (elements per lane when loading) and two LDS
+// buffers of M x B complex plus the M twiddles in 64 KB.
+constexpr int kFftThreads = 256;
 int fft_batch_of(const se_params &p) {
   const int csz = 2 * real_size(p);
-  int B = 65536 / (2 * p.M * csz);
-  if (B > 16) B = 16;
-  if (B < 1) B = 1;
+  int B = 16;
+  while (B > 1 && (p.M * B > 16 * kFftThreads || (2 * p.M * B + p.M) * csz > 65536)) B >>= 1;
   return B;
 }
 
@@ -76,6 +84,15 @@ sek::FftPlan radix_plan(int M) {
   while (m % 5 == 0) { pl.radix[n++] = 5; m /= 5; }
   while (m % 3 == 0) { pl.radix[n++] = 3; m /= 3; }
   pl.nstages = n;
+  int ns = 1;
+  for (int s = 0; s < n; ++s) {
+    pl.ns[s] = ns;
+    pl.ns_magic[s] = sek::div_magic(ns);
+    pl.tstep[s] = M / (ns * pl.radix[s]);
+    ns *= pl.radix[s];
+  }
+  pl.m_magic = sek::div_magic(M);
+  pl.k_magic = sek::div_magic(M / 2 + 1);
   return pl;
 }
 
@@ -128,29 +145,58 @@ se_status check_params(const se_params *prm, double *eta_out) {
 }
 
 struct Sizes {
-  size_t grid, spec, sorted, meta, key, counts, offsets, done, part, qsq, tw, f, k2, total;
+  size_t grid, ghost, cover, cover_count, spec, sorted, meta, key, counts, offsets, part, qsq, tw,
+      f, k2, total;
 };
 
-Sizes sizes_of(const se_params &p, int n_max, int ntiles, int bin_blocks, int zblocks) {
+// (tile * 64 + index) pairs of the tile blocks covering each grid index along
+// one axis: block of tile t starts at grid index t*T + OFF and spans TS points
+// (periodically wrapped).
+std::vector<std::vector<int>> cover_lists(int M, int T, int S, int off) {
+  const int ntx = (M + T - 1) / T, TS = T + S - 1;
+  std::vector<std::vector<int>> lists(M);
+  for (int t = 0; t < ntx; ++t)
+    for (int l = 0; l < TS; ++l) {
+      int g = (t * T + off + l) % M;
+      if (g < 0) g += M;
+      lists[g].push_back(t * 64 + l);
+    }
+  return lists;
+}
+
+int stencil_offset(const se_params &p) {
+  return p.window == SE_WINDOW_GAUSSIAN ? -(p.P / 2 - 1) : -(p.P - 1);
+}
+
+size_t max_cover(const se_params &p, int T) {
+  size_t kc = 0;
+  for (const auto &l : cover_lists(p.M, T, p.P, stencil_offset(p))) kc = std::max(kc, l.size());
+  return kc;
+}
+
+Sizes sizes_of(const se_params &p, int n_max, int ntiles, int bin_blocks, int zblocks, int T) {
   const size_t rs = real_size(p), M = p.M, K = M / 2 + 1;
   const size_t n = n_max > 0 ? n_max : 1;
   Sizes s{};
   auto al = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+  const size_t TS = T + p.P - 1;
   s.grid = al(M * M * M * rs);
+  s.ghost = al(static_cast<size_t>(ntiles) * TS * TS * TS * rs);
+  s.cover = al(M * max_cover(p, T) * 4);
+  s.cover_count = al(M * 4);
   s.spec = al(M * M * K * 2 * rs);
   s.sorted = al(n * 4 * rs);
   s.meta = al(n * 8);
   s.key = al(n * 8);
-  s.counts = al(ntiles * 4);
+  s.counts = al(static_cast<size_t>(ntiles) * sek::kCountStride * 4);
   s.offsets = al((ntiles + 1) * 4);
-  s.done = al(2 * 4);
   s.part = al((bin_blocks + zblocks) * 8);
   s.qsq = al(8);
   s.tw = al(M * 2 * rs);
   s.f = al(M * 8);
   s.k2 = al(M * 8);
-  s.total = s.grid + s.spec + s.sorted + s.meta + s.key + s.counts + s.offsets + s.done +
-            s.part + s.qsq + s.tw + s.f + s.k2;
+  s.total = s.grid + s.ghost + s.cover + s.cover_count + s.spec + s.sorted + s.meta + s.key +
+            s.counts + s.offsets + s.part + s.qsq + s.tw + s.f + s.k2;
   return s;
 }
 
@@ -172,6 +218,7 @@ void derive(se_plan &pl) {
   pl.bin_blocks = (pl.n_max + sek::kThreads - 1) / sek::kThreads;
   if (pl.bin_blocks < 1) pl.bin_blocks = 1;
   pl.fft_batch = fft_batch_of(p);
+  pl.fft_threads = kFftThreads;
   pl.zfft_blocks = (p.M * (p.M / 2 + 1) + pl.fft_batch - 1) / pl.fft_batch;
   pl.fft = radix_plan(p.M);
 }
@@ -199,9 +246,9 @@ void destroy_events(se_plan &pl) {
 
 void free_all(se_plan &pl) {
   destroy_events(pl);
-  void *ptrs[] = {pl.buf.grid, pl.buf.spec, pl.buf.sorted, pl.buf.meta, pl.buf.key,
-                  pl.buf.counts, pl.buf.offsets, pl.buf.done, pl.buf.part, pl.buf.qsq,
-                  pl.buf.twiddle, pl.buf.axis_f, pl.buf.axis_k2};
+  void *ptrs[] = {pl.buf.grid, pl.buf.ghost, pl.buf.cover, pl.buf.cover_count, pl.buf.spec,
+                  pl.buf.sorted, pl.buf.meta, pl.buf.key, pl.buf.counts, pl.buf.offsets,
+                  pl.buf.part, pl.buf.qsq, pl.buf.twiddle, pl.buf.axis_f, pl.buf.axis_k2};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   pl.buf = sek::DeviceBuffers{};
@@ -238,7 +285,7 @@ se_status se_plan_workspace_size(const se_params *prm, int n_max, size_t *bytes)
   tmp.prm = *prm;
   tmp.n_max = n_max;
   derive(tmp);
-  *bytes = sizes_of(*prm, n_max, tmp.ntiles, tmp.bin_blocks, tmp.zfft_blocks).total;
+  *bytes = sizes_of(*prm, n_max, tmp.ntiles, tmp.bin_blocks, tmp.zfft_blocks, tmp.T).total;
   return SE_OK;
 }
 
@@ -263,14 +310,16 @@ se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_p
     return hip_fail(e, "hipGetDevice");
   }
 
-  const Sizes sz = sizes_of(pl->prm, n_max, pl->ntiles, pl->bin_blocks, pl->zfft_blocks);
+  const Sizes sz = sizes_of(pl->prm, n_max, pl->ntiles, pl->bin_blocks, pl->zfft_blocks, pl->T);
   struct { void **p; size_t n; } allocs[] = {
-      {&pl->buf.grid, sz.grid},     {&pl->buf.spec, sz.spec},
+      {&pl->buf.grid, sz.grid},     {&pl->buf.ghost, sz.ghost},
+      {reinterpret_cast<void **>(&pl->buf.cover), sz.cover},
+      {reinterpret_cast<void **>(&pl->buf.cover_count), sz.cover_count},
+      {&pl->buf.spec, sz.spec},
       {&pl->buf.sorted, sz.sorted}, {reinterpret_cast<void **>(&pl->buf.meta), sz.meta},
       {reinterpret_cast<void **>(&pl->buf.key), sz.key},
       {reinterpret_cast<void **>(&pl->buf.counts), sz.counts},
       {reinterpret_cast<void **>(&pl->buf.offsets), sz.offsets},
-      {reinterpret_cast<void **>(&pl->buf.done), sz.done},
       {reinterpret_cast<void **>(&pl->buf.part), sz.part},
       {reinterpret_cast<void **>(&pl->buf.qsq), sz.qsq},
       {&pl->buf.twiddle, sz.tw},    {&pl->buf.axis_f, sz.f},
@@ -310,7 +359,23 @@ se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_p
     if (e == hipSuccess) e = hipEventCreate(&pl->ev_end[i]);
   }
   if (e == hipSuccess) e = hipMemset(pl->buf.counts, 0, sz.counts);
-  if (e == hipSuccess) e = hipMemset(pl->buf.done, 0, sz.done);
+  if (e == hipSuccess) {
+    const auto lists = cover_lists(M, pl->T, pl->prm.P, stencil_offset(pl->prm));
+    size_t kc = 0;
+    for (const auto &l : lists) kc = std::max(kc, l.size());
+    std::vector<int> cover(M * kc, 0), count(M);
+    for (int g = 0; g < M; ++g) {
+      count[g] = static_cast<int>(lists[g].size());
+      for (size_t k = 0; k < lists[g].size(); ++k) cover[g * kc + k] = lists[g][k];
+    }
+    e = hipMemcpy(pl->buf.cover, cover.data(), sizeof(int) * cover.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(pl->buf.cover_count, count.data(), sizeof(int) * M, hipMemcpyHostToDevice);
+    pl->fold = sek::FoldTables{pl->buf.cover, pl->buf.cover_count, static_cast<int>(kc),
+                               pl->T + pl->prm.P - 1, pl->ntx};
+    const int TS = pl->T + pl->prm.P - 1;
+    pl->fold_by_tiles = (M % pl->T == 0) && (TS <= M) && (pl->ntx >= (TS + pl->T - 1) / pl->T);
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_all(*pl);
@@ -364,7 +429,7 @@ se_status se_forward(se_plan *plan, int N, const void *x, const void *q, double 
   if (!E_dev) return fail(SE_ERR_ARG, "E_dev is NULL");
   hipError_t e = sek::launch_bin(*plan, N, x, q);
   if (e != hipSuccess) return hip_fail(e, "binning");
-  if ((e = sek::launch_spread(*plan, N)) != hipSuccess) return hip_fail(e, "spreading");
+  if ((e = sek::launch_spread(*plan)) != hipSuccess) return hip_fail(e, "spreading");
   if ((e = sek::launch_fft_forward_scale_inverse(*plan, E_dev)) != hipSuccess)
     return hip_fail(e, "FFT/scaling");
   plan->last_N = N;

@@ -28,21 +28,55 @@ template <typename R> struct alignas(4 * sizeof(R)) SortedParticle {
 
 constexpr int kMaxRadixStages = 16;
 
+// Division by a runtime constant d <= 1024 of a numerator n with
+// n * (magic * d - 2^32) < 2^32 (true for every index below): the high half
+// of n * magic, magic = ceil(2^32 / d).
+__host__ __device__ inline unsigned div_magic(unsigned d) {
+  return d <= 1 ? 0u : static_cast<unsigned>(((1ull << 32) + d - 1) / d);
+}
+__device__ inline int fast_div(int n, unsigned magic) {
+  return static_cast<int>(__umulhi(static_cast<unsigned>(n), magic));
+}
+
+// v mod M for v in a few periods of [0, M) (no division).
+__device__ inline int wrap_index(int v, int M) {
+  while (v < 0) v += M;
+  while (v >= M) v -= M;
+  return v;
+}
+
 struct FftPlan {
   int M;                        // transform length
   int nstages;                  // number of radix stages
   int radix[kMaxRadixStages];   // radices in stage order (2, 3, 4, 5, 8)
+  int ns[kMaxRadixStages];      // product of the radices of the earlier stages
+  unsigned ns_magic[kMaxRadixStages];  // div_magic(ns[s])
+  int tstep[kMaxRadixStages];   // M / (ns[s] * radix[s]): twiddle index step
+  unsigned m_magic;             // div_magic(M)
+  unsigned k_magic;             // div_magic(M / 2 + 1)
+};
+
+// Which tile blocks of the ghost array cover each grid index along one axis
+// (the same along all three axes of the cubic grid).
+struct FoldTables {
+  const int *cover;  // [M][KC]: tile * 64 + index inside the tile block
+  const int *count;  // [M]: entries used in cover[g]
+  int KC;            // entries per grid index
+  int TS;            // tile block edge T + S - 1
+  int ntx;           // tiles per axis
 };
 
 struct DeviceBuffers {
-  void *grid = nullptr;       // M^3 real: spread grid G, later the scaled grid Phi
+  void *grid = nullptr;       // M^3 real: the scaled grid Phi (input of gathering)
+  void *ghost = nullptr;      // ntiles * (T+S-1)^3 real: spread tile blocks
+  int *cover = nullptr;       // fold tables (FoldTables)
+  int *cover_count = nullptr;
   void *spec = nullptr;       // M*M*(M/2+1) complex half spectrum
   void *sorted = nullptr;     // n_max SortedParticle<R>
   int2 *meta = nullptr;       // n_max (packed local anchor, original index)
   int2 *key = nullptr;        // n_max (tile, rank within tile)
-  int *counts = nullptr;      // ntiles
+  int *counts = nullptr;      // ntiles, one per kCountStride ints (own cache line)
   int *offsets = nullptr;     // ntiles + 1
-  unsigned *done = nullptr;   // 2 arrival counters (binning, energy)
   double *part = nullptr;     // per-block partial sums (q^2 and energy)
   double *qsq = nullptr;      // sum q^2 of the last forward
   void *twiddle = nullptr;    // M complex: e^{-2 pi i j / M}
@@ -74,9 +108,12 @@ struct se_plan {
   int bin_blocks;  // blocks of the binning kernel for n_max
   int zfft_blocks; // blocks of the z-pass (energy partials)
   int fft_batch;   // pencils per FFT work-group
+  int fft_threads; // threads per FFT work-group
 
   sek::FftPlan fft;
   sek::DeviceBuffers buf;
+  sek::FoldTables fold;
+  bool fold_by_tiles;  // tiles partition the grid: tile-structured fold
 
   int last_N;      // particles of the last se_forward, -1 before the first
 
@@ -92,7 +129,7 @@ namespace sek {
 // Launch wrappers (one per translation unit); each enqueues on plan.stream
 // and returns the launch status.
 hipError_t launch_bin(se_plan &plan, int N, const void *x, const void *q);
-hipError_t launch_spread(se_plan &plan, int N);
+hipError_t launch_spread(se_plan &plan);
 hipError_t launch_fft_forward_scale_inverse(se_plan &plan, double *E_dev);
 hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode,
                          void *out_pot, void *out_vec);
@@ -117,6 +154,10 @@ constexpr size_t kMaxLds = 160 * 1024;
 constexpr int kGatherPotentialForce = 0;  // out_pot = phi, out_vec = F
 constexpr int kGatherAdjoint = 1;         // out_pot = gE phi, out_vec = -gE F
 
-constexpr int kThreads = 256;  // work-group size of every kernel but the scan
+constexpr int kThreads = 256;  // work-group size of every kernel
+
+// Tile counters are spaced one cache line apart: device-wide atomics on the
+// same line serialise, on different lines they proceed in parallel.
+constexpr int kCountStride = 32;
 
 }  // namespace sek

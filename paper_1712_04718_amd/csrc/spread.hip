@@ -1,16 +1,27 @@
 // Step 2 of Algorithm 1: spread the charges onto the grid (SE eq. 4.5 or
-// SPME eq. 6.1) without global atomics on the hot loop.
+// SPME eq. 6.1), with neither global atomics nor floating-point atomics in
+// the FP32 path.
 //
 // One work-group per tile of T^3 anchor points.  The particles anchored in
-// the tile touch a (T+S-1)^3 block of the grid, which is accumulated in LDS
-// with LDS atomics and then added to the global grid once (coalesced rows).
-// Each wave takes the tile's particles in chunks:
-//   phase A: one lane per particle computes its 3S separable window factors
-//            (charge folded into the x factors) into the wave's LDS area;
-//   phase B: the wave holds 64/S particle groups of S lanes; lane
+// the tile touch a (T+S-1)^3 block of the grid, accumulated in LDS and then
+// stored, with plain coalesced stores, as the tile's own block of a "ghost"
+// array; a fold kernel then adds the overlapping blocks that cover each grid
+// point, so no grid zeroing and no global atomics are needed.
+//
+// LDS accumulation:
+//   FP32: fixed point in 32-bit integers with a per-tile scale
+//         2^30 / (wmax * sum_tile |q|), where wmax bounds every window value
+//         (beta^3 for the Gaussian, 1 for B-splines): no partial sum can leave
+//         (-2^31, 2^31), each contribution is rounded once, and the result
+//         does not depend on the order of the additions.  (Integer LDS atomics
+//         run far faster than floating-point ones on this chip.)
+//   FP64: LDS double atomics.
+// Work split: the tile's particles are taken in chunks of one per thread;
+//   phase A: each thread computes its particle's 3S window factors (charge
+//            and scale folded into the x factors) into LDS;
+//   phase B: each wave holds 64/S particle groups of S lanes; lane
 //            (group, jx) owns the x-offset jx of one particle and adds its
-//            S^2 (jy, jz) products, so one LDS instruction touches S
-//            consecutive addresses per particle.
+//            S^2 (jy, jz) products.
 #include "se_common.hpp"
 #include "window.hpp"
 
@@ -19,65 +30,97 @@ namespace {
 
 extern __shared__ __align__(16) unsigned char g_smem[];
 
+template <typename R> struct Acc;
+template <> struct Acc<float> { using T = int; };      // fixed point
+template <> struct Acc<double> { using T = double; };  // floating point
+
+// particles per phase-A round: one per thread, fewer when the factor table
+// would exceed 32 KB
+constexpr int spread_chunk(int real_size, int S) {
+  return (real_size * 3 * S * kThreads <= 32768) ? kThreads
+         : (real_size * 3 * S * (kThreads / 2) <= 32768) ? kThreads / 2 : kThreads / 4;
+}
+
 template <typename R, int S, int T> struct SpreadLds {
   static constexpr int TS = T + S - 1;
-  static constexpr int CH = Chunk<S>::CH;
-  static constexpr int REC = 3 * S;                         // factors per particle
-  static constexpr size_t BLK = sizeof(R) * TS * TS * TS;
-  static constexpr size_t FAC = sizeof(R) * CH * REC;       // per wave
-  static constexpr size_t ANC = sizeof(int) * CH;           // per wave
-  static constexpr size_t TOTAL = BLK + (kThreads / 64) * (FAC + ANC);
+  static constexpr int REC = 3 * S;
+  static constexpr int CHUNK = spread_chunk(sizeof(R), S);
+  static constexpr size_t BLK = sizeof(typename Acc<R>::T) * ((TS * TS * TS + 3) & ~3);
+  static constexpr size_t FAC = sizeof(R) * CHUNK * REC;
+  static constexpr size_t ANC = sizeof(int) * CHUNK;
+  static constexpr size_t TOTAL = BLK + FAC + ANC + 64;
 };
 
 template <typename R, int WIN, int S, int T>
 __global__ void __launch_bounds__(kThreads)
 k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ meta,
-         const int *__restrict__ offsets, int M, int ntx, WindowConsts wc,
-         R *__restrict__ grid) {
+         const int *__restrict__ offsets, WindowConsts wc, double wmax, R *__restrict__ ghost) {
   using L = SpreadLds<R, S, T>;
-  constexpr int TS = L::TS, CH = L::CH, REC = L::REC;
-  constexpr int GROUPS = Chunk<S>::GROUPS;
-  constexpr int OFF = Stencil<WIN, S>::OFF;
+  using A = typename Acc<R>::T;
+  constexpr int TS = L::TS, REC = L::REC, TS3 = TS * TS * TS, kChunk = L::CHUNK;
+  constexpr int GROUPS = 64 / S;
   constexpr int NWAVES = kThreads / 64;
+  constexpr bool FIXED = sizeof(R) == 4;
 
   const int tile = blockIdx.x;
   const int start = offsets[tile], end = offsets[tile + 1];
-  if (start == end) return;  // uniform across the work-group
-
   const int tid = threadIdx.x;
+  R *out = ghost + static_cast<long long>(tile) * TS3;
+  if (start == end) {  // uniform across the work-group
+    for (int i = tid; i < TS3; i += kThreads) out[i] = R(0);
+    return;
+  }
+
+  A *blk = reinterpret_cast<A *>(g_smem);
+  R *fac = reinterpret_cast<R *>(g_smem + L::BLK);
+  int *anc = reinterpret_cast<int *>(g_smem + L::BLK + L::FAC);
+  double *red = reinterpret_cast<double *>(g_smem + L::BLK + L::FAC + L::ANC);
+
+  for (int i = tid; i < TS3; i += kThreads) blk[i] = A(0);
+
+  // fixed-point scale of this tile
+  double scale = 1.0, inv_scale = 1.0;
+  if constexpr (FIXED) {
+    double s = 0.0;
+    for (int p = start + tid; p < end; p += kThreads) s += fabs(static_cast<double>(sorted[p].q));
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    double qsum = 0.0;
+    for (int w = 0; w < NWAVES; ++w) qsum += red[w];
+    const double bound = wmax * qsum;
+    if (bound > 0.0) {
+      scale = 1073741824.0 / bound;  // 2^30
+      inv_scale = bound / 1073741824.0;
+    }
+  }
+
   const int wave = tid >> 6, lane = tid & 63;
-  R *blk = reinterpret_cast<R *>(g_smem);
-  R *fac = reinterpret_cast<R *>(g_smem + L::BLK + wave * (L::FAC + L::ANC));
-  int *anc = reinterpret_cast<int *>(reinterpret_cast<unsigned char *>(fac) + L::FAC);
-
-  for (int i = tid; i < TS * TS * TS; i += kThreads) blk[i] = R(0);
-  __syncthreads();
-
   const int grp = lane / S, jx = lane - grp * S;
-  for (int base = start + wave * CH; base < end; base += NWAVES * CH) {
-    const int nval = min(CH, end - base);
-    // phase A: factors of particle base + lane
-    if (lane < nval) {
-      const SortedParticle<R> sp = sorted[base + lane];
+  for (int base = start; base < end; base += kChunk) {
+    const int nval = min(kChunk, end - base);
+    __syncthreads();  // previous round done with fac / anc; blk zeroed
+    // phase A: factors of particle base + tid
+    if (tid < nval) {
+      const SortedParticle<R> sp = sorted[base + tid];
       R g[S], unused[S];
-      R *f = fac + lane * REC;
+      R *f = fac + tid * REC;
+      const R qs = static_cast<R>(static_cast<double>(sp.q) * scale);
       window_axis<R, WIN, S, false>(sp.dx, wc, g, unused);
 #pragma unroll
-      for (int j = 0; j < S; ++j) f[j] = sp.q * g[j];
+      for (int j = 0; j < S; ++j) f[j] = qs * g[j];
       window_axis<R, WIN, S, false>(sp.dy, wc, g, unused);
 #pragma unroll
       for (int j = 0; j < S; ++j) f[S + j] = g[j];
       window_axis<R, WIN, S, false>(sp.dz, wc, g, unused);
 #pragma unroll
       for (int j = 0; j < S; ++j) f[2 * S + j] = g[j];
-      anc[lane] = meta[base + lane].x;
+      anc[tid] = meta[base + tid].x;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // phase B: accumulate into the tile block
+    __syncthreads();
+    // phase B
     if (grp < GROUPS) {
-      for (int c = grp; c < nval; c += GROUPS) {
+      for (int c = wave * GROUPS + grp; c < nval; c += NWAVES * GROUPS) {
         const R *f = fac + c * REC;
         const int packed = anc[c];
         const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
@@ -88,33 +131,111 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
           gy[j] = f[S + j];
           gz[j] = f[2 * S + j];
         }
-        R *row = blk + (az * TS + ay) * TS + ax + jx;
+        A *row = blk + (az * TS + ay) * TS + ax + jx;
 #pragma unroll
         for (int jz = 0; jz < S; ++jz) {
           const R wz = wq * gz[jz];
 #pragma unroll
-          for (int jy = 0; jy < S; ++jy)
-            unsafeAtomicAdd(row + (jz * TS + jy) * TS, wz * gy[jy]);
+          for (int jy = 0; jy < S; ++jy) {
+            if constexpr (FIXED)
+              atomicAdd(row + (jz * TS + jy) * TS, __float2int_rn(wz * gy[jy]));
+            else
+              unsafeAtomicAdd(row + (jz * TS + jy) * TS, wz * gy[jy]);
+          }
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
+  for (int i = tid; i < TS3; i += kThreads) {
+    if constexpr (FIXED)
+      out[i] = static_cast<R>(static_cast<double>(blk[i]) * inv_scale);
+    else
+      out[i] = blk[i];
+  }
+}
 
-  // add the block to the global grid (periodic wrap of the halo)
+// ------------------------------------------------------------------ fold
+// The spread grid is the sum of the tile blocks that cover each point.
+
+// General case: per grid point, tables of the covering (tile, local index)
+// pairs along each axis (packed as tile * 64 + local index).
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+k_fold(const R *__restrict__ ghost, FoldTables ft, int M, R *__restrict__ grid) {
+  const long long n = static_cast<long long>(M) * M * M;
+  const long long i = static_cast<long long>(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int x = static_cast<int>(i % M);
+  const long long zy = i / M;
+  const int y = static_cast<int>(zy % M), z = static_cast<int>(zy / M);
+  const int TS = ft.TS, TS3 = TS * TS * TS, KC = ft.KC;
+  R s = R(0);
+  const int nz = ft.count[z], ny = ft.count[y], nx = ft.count[x];
+  for (int iz = 0; iz < nz; ++iz) {
+    const int cz = ft.cover[z * KC + iz];
+    for (int iy = 0; iy < ny; ++iy) {
+      const int cy = ft.cover[y * KC + iy];
+      const long long base =
+          static_cast<long long>(((cz >> 6) * ft.ntx + (cy >> 6)) * ft.ntx) * TS3 +
+          ((cz & 63) * TS + (cy & 63)) * TS;
+      for (int ix = 0; ix < nx; ++ix) {
+        const int cx = ft.cover[x * KC + ix];
+        s += ghost[base + static_cast<long long>(cx >> 6) * TS3 + (cx & 63)];
+      }
+    }
+  }
+  grid[i] = s;
+}
+
+// Tiles partition the grid (M = ntx T) and no block wraps onto itself
+// (T + S - 1 <= M): work-group t writes the T^3 points starting at t T + OFF.
+// Along each axis a point with local index l gets block t at l, block t-1 at
+// l + T, block t-2 at l + 2T, while the local index stays inside the block.
+// Every candidate is loaded (clamped to a valid address) before any is used,
+// so the loads overlap; consecutive threads read consecutive x.
+template <typename R, int WIN, int S, int T>
+__global__ void __launch_bounds__(kThreads)
+k_fold_tiles(const R *__restrict__ ghost, int M, int ntx, R *__restrict__ grid) {
+  constexpr int TS = T + S - 1, TS3 = TS * TS * TS, T3 = T * T * T;
+  constexpr int MAXK = (TS + T - 1) / T;
+  constexpr int OFF = Stencil<WIN, S>::OFF;
+  const int tile = blockIdx.x;
   const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
-  const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
-  for (int i = tid; i < TS * TS * TS; i += kThreads) {
-    const R v = blk[i];
-    if (v == R(0)) continue;
-    const int lz = i / (TS * TS), ly = (i / TS) % TS, lx = i % TS;
-    int gz = (bz + lz) % M, gy = (by + ly) % M, gx = (bx + lx) % M;
+  int sz[MAXK], sy[MAXK], sx[MAXK];
+#pragma unroll
+  for (int k = 0; k < MAXK; ++k) {
+    sz[k] = tz - k + (tz < k ? ntx : 0);
+    sy[k] = ty - k + (ty < k ? ntx : 0);
+    sx[k] = tx - k + (tx < k ? ntx : 0);
+  }
+  for (int i = threadIdx.x; i < T3; i += kThreads) {
+    const int lz = i / (T * T), ly = (i / T) % T, lx = i % T;
+    R v[MAXK][MAXK][MAXK];
+#pragma unroll
+    for (int kz = 0; kz < MAXK; ++kz)
+#pragma unroll
+      for (int ky = 0; ky < MAXK; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < MAXK; ++kx) {
+          const int cz = min(lz + kz * T, TS - 1), cy = min(ly + ky * T, TS - 1);
+          const int cx = min(lx + kx * T, TS - 1);
+          v[kz][ky][kx] = ghost[static_cast<long long>((sz[kz] * ntx + sy[ky]) * ntx + sx[kx]) * TS3 +
+                                (cz * TS + cy) * TS + cx];
+        }
+    R s = R(0);
+#pragma unroll
+    for (int kz = 0; kz < MAXK; ++kz)
+#pragma unroll
+      for (int ky = 0; ky < MAXK; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < MAXK; ++kx)
+          if (lz + kz * T < TS && ly + ky * T < TS && lx + kx * T < TS) s += v[kz][ky][kx];
+    int gz = tz * T + OFF + lz, gy = ty * T + OFF + ly, gx = tx * T + OFF + lx;
     gz += gz < 0 ? M : 0;
     gy += gy < 0 ? M : 0;
     gx += gx < 0 ? M : 0;
-    unsafeAtomicAdd(grid + (static_cast<long long>(gz) * M + gy) * M + gx, v);
+    grid[(static_cast<long long>(gz) * M + gy) * M + gx] = s;
   }
 }
 
@@ -122,6 +243,7 @@ template <typename R, int WIN, int S, int T>
 hipError_t spread_one(se_plan &p) {
   const size_t lds = SpreadLds<R, S, T>::TOTAL;
   WindowConsts wc{p.cg, p.beta, exp(-2.0 * p.cg), 0.0};
+  const double wmax = (WIN == kGauss) ? p.beta * p.beta * p.beta : 1.0;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_spread<R, WIN, S, T>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -130,9 +252,23 @@ hipError_t spread_one(se_plan &p) {
   }
   stage_begin(p, SE_STAGE_SPREAD);
   k_spread<R, WIN, S, T><<<p.ntiles, kThreads, lds, p.stream>>>(
-      static_cast<const SortedParticle<R> *>(p.buf.sorted), p.buf.meta, p.buf.offsets,
-      p.prm.M, p.ntx, wc, static_cast<R *>(p.buf.grid));
+      static_cast<const SortedParticle<R> *>(p.buf.sorted), p.buf.meta, p.buf.offsets, wc, wmax,
+      static_cast<R *>(p.buf.ghost));
   stage_end(p, SE_STAGE_SPREAD);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int M = p.prm.M;
+  stage_begin(p, SE_STAGE_FOLD);
+  if (p.fold_by_tiles) {
+    k_fold_tiles<R, WIN, S, T><<<p.ntiles, kThreads, 0, p.stream>>>(
+        static_cast<const R *>(p.buf.ghost), M, p.ntx, static_cast<R *>(p.buf.grid));
+  } else {
+    const long long ngrid = static_cast<long long>(M) * M * M;
+    k_fold<R><<<static_cast<unsigned>((ngrid + kThreads - 1) / kThreads), kThreads, 0,
+                p.stream>>>(static_cast<const R *>(p.buf.ghost), p.fold, M,
+                            static_cast<R *>(p.buf.grid));
+  }
+  stage_end(p, SE_STAGE_FOLD);
   return hipGetLastError();
 }
 
@@ -159,6 +295,8 @@ hipError_t spread_dispatch(se_plan &p) {
   const bool gauss = p.prm.window == SE_WINDOW_GAUSSIAN;
   if (p.T == 16)
     return gauss ? spread_dispatch_S<R, kGauss, 16>(p) : spread_dispatch_S<R, kBspline, 16>(p);
+  if (p.T == 12)
+    return gauss ? spread_dispatch_S<R, kGauss, 12>(p) : spread_dispatch_S<R, kBspline, 12>(p);
   return gauss ? spread_dispatch_S<R, kGauss, 8>(p) : spread_dispatch_S<R, kBspline, 8>(p);
 }
 
@@ -166,12 +304,13 @@ hipError_t spread_dispatch(se_plan &p) {
 
 size_t spread_lds_bytes(int real_size, int S, int T) {
   const size_t ts = T + S - 1;
-  const size_t groups = 64 / S, ch = groups * ((32 + groups - 1) / groups);
-  return real_size * ts * ts * ts + (kThreads / 64) * (real_size * ch * 3 * S + 4 * ch);
+  const size_t acc = real_size == 4 ? 4 : 8;
+  const size_t chunk = spread_chunk(real_size, S);
+  return acc * ((ts * ts * ts + 3) & ~static_cast<size_t>(3)) +
+         static_cast<size_t>(real_size) * chunk * 3 * S + 4 * chunk + 64;
 }
 
-hipError_t launch_spread(se_plan &plan, int N) {
-  if (N == 0) return hipSuccess;
+hipError_t launch_spread(se_plan &plan) {
   return plan.prm.dtype == SE_FP64 ? spread_dispatch<double>(plan)
                                    : spread_dispatch<float>(plan);
 }
