@@ -164,17 +164,102 @@ __device__ cplx_t<R> *fft_batch(cplx_t<R> *buf0, cplx_t<R> *buf1, int lgB, const
   return in;
 }
 
+// Compile-time variant for a fixed M and batch: every stage's radix, stride
+// and twiddle step are constants, so the index arithmetic folds away and
+// the butterfly loops unroll.
+struct RadixList {
+  int n;
+  int r[kMaxRadixStages];
+};
+constexpr RadixList radix_list(int M) {
+  RadixList l{0, {}};
+  int m = M;
+  while (m % 8 == 0) { l.r[l.n++] = 8; m /= 8; }
+  if (m % 4 == 0) { l.r[l.n++] = 4; m /= 4; }
+  if (m % 2 == 0) { l.r[l.n++] = 2; m /= 2; }
+  while (m % 5 == 0) { l.r[l.n++] = 5; m /= 5; }
+  while (m % 3 == 0) { l.r[l.n++] = 3; m /= 3; }
+  return l;
+}
+
+template <typename R, int M, int LGB, int RAD, int NS>
+__device__ inline void stockham_stage_ct(const cplx_t<R> *in, cplx_t<R> *out,
+                                         const cplx_t<R> *tw) {
+  using C = cplx_t<R>;
+  constexpr int B = 1 << LGB, NB = M / RAD, TOTAL = NB * B, TSTEP = M / (NS * RAD);
+#pragma unroll
+  for (int t0 = 0; t0 < TOTAL; t0 += kThreads) {
+    const int t = t0 + static_cast<int>(threadIdx.x);
+    if (TOTAL % kThreads == 0 || t < TOTAL) {
+      const int b = t & (B - 1), j = t >> LGB;
+      const int q = j / NS, k = j - q * NS;
+      C v[RAD];
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[r] = in[((j + r * NB) << LGB) + b];
+      if (NS > 1 && k != 0) {
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) v[r] = cmul(v[r], tw[r * k * TSTEP]);
+      }
+      if constexpr (RAD == 2) dft2<R, C>(v);
+      if constexpr (RAD == 3) dft3<R, C>(v);
+      if constexpr (RAD == 4) dft4<R, C>(v);
+      if constexpr (RAD == 5) dft5<R, C>(v);
+      if constexpr (RAD == 8) dft8<R, C>(v);
+      const int dst = q * NS * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) out[((dst + r * NS) << LGB) + b] = v[r];
+    }
+  }
+}
+
+template <typename R, int M, int LGB, int STAGE, int NS>
+__device__ inline cplx_t<R> *fft_batch_ct(cplx_t<R> *in, cplx_t<R> *out, const cplx_t<R> *tw) {
+  constexpr RadixList L = radix_list(M);
+  if constexpr (STAGE == L.n) {
+    return in;
+  } else {
+    constexpr int RAD = L.r[STAGE];
+    stockham_stage_ct<R, M, LGB, RAD, NS>(in, out, tw);
+    __syncthreads();
+    return fft_batch_ct<R, M, LGB, STAGE + 1, NS * RAD>(out, in, tw);
+  }
+}
+
+// Forward FFT of the B pencils in buf0, compile-time (MC > 0) or run-time plan.
+template <typename R, int MC, int LGBC>
+__device__ inline cplx_t<R> *fft_any(cplx_t<R> *buf0, cplx_t<R> *buf1, int lgB, const FftPlan &pl,
+                                     const cplx_t<R> *tw) {
+  if constexpr (MC > 0)
+    return fft_batch_ct<R, MC, LGBC, 0, 1>(buf0, buf1, tw);
+  else
+    return fft_batch<R>(buf0, buf1, lgB, pl, tw);
+}
+
+// i / M and i / (M/2+1): constant divisors when M is known at compile time,
+// else the plan's magic multipliers.
+template <int MC> __device__ inline int div_M(int i, const FftPlan &pl) {
+  if constexpr (MC > 0) return i / MC;
+  else return fast_div(i, pl.m_magic);
+}
+template <int MC> __device__ inline int div_K(int i, const FftPlan &pl) {
+  if constexpr (MC > 0) return i / (MC / 2 + 1);
+  else return fast_div(i, pl.k_magic);
+}
+
 // ---------------------------------------------------------------- x passes
 
-template <typename R>
+template <typename R, int MC, int LGBC>
 __global__ void __launch_bounds__(kThreads)
 k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB,
             const cplx_t<R> *__restrict__ tw_g) {
   using C = cplx_t<R>;
-  const int M = pl.M, K = M / 2 + 1, B = 1 << lgB;
+  constexpr bool CT = MC > 0;
+  const int M = CT ? MC : pl.M;
+  const int lgb = CT ? LGBC : lgB;
+  const int K = M / 2 + 1, B = 1 << lgb;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
   C *twl = b1 + M * B;  // twiddles staged in LDS
-  for (int i = threadIdx.x; i < M; i += blockDim.x) twl[i] = tw_g[i];
+  for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
   const long long nrows = static_cast<long long>(M) * M;
   const long long row0 = static_cast<long long>(blockIdx.x) * 2 * B;
   // row r of the batch goes to pencil r/2, real part for even r, imag for odd;
@@ -182,23 +267,23 @@ k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl
   R v[2 * kMaxPerThread];
 #pragma unroll
   for (int k = 0; k < 2 * kMaxPerThread; ++k) {
-    const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
-    const long long gr = row0 + fast_div(i, pl.m_magic);
+    const int i = threadIdx.x + k * kThreads;
+    const long long gr = row0 + div_M<MC>(i, pl);
     v[k] = (i < 2 * B * M && gr < nrows) ? grid[row0 * M + i] : R(0);
   }
 #pragma unroll
   for (int k = 0; k < 2 * kMaxPerThread; ++k) {
-    const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
+    const int i = threadIdx.x + k * kThreads;
     if (i < 2 * B * M) {
-      const int r = fast_div(i, pl.m_magic), xk = i - r * M;
+      const int r = div_M<MC>(i, pl), xk = i - r * M;
       reinterpret_cast<R *>(&b0[xk * B + (r >> 1)])[r & 1] = v[k];
     }
   }
   __syncthreads();
-  const C *Z = fft_batch<R>(b0, b1, lgB, pl, twl);
+  const C *Z = fft_any<R, MC, LGBC>(b0, b1, lgb, pl, twl);
   // Z = FFT(r1 + i r2): R1[k] = (Z[k] + conj Z[M-k]) / 2, R2[k] = (Z[k] - conj Z[M-k]) / 2i
-  for (int i = threadIdx.x; i < B * K; i += blockDim.x) {
-    const int b = fast_div(i, pl.k_magic), k = i - b * K;
+  for (int i = threadIdx.x; i < B * K; i += kThreads) {
+    const int b = div_K<MC>(i, pl), k = i - b * K;
     const long long gr = row0 + 2 * b;
     if (gr >= nrows) continue;
     const C zk = Z[k * B + b];
@@ -213,21 +298,24 @@ k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl
   }
 }
 
-template <typename R>
+template <typename R, int MC, int LGBC>
 __global__ void __launch_bounds__(kThreads)
 k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl, int lgB,
             const cplx_t<R> *__restrict__ tw_g) {
   using C = cplx_t<R>;
-  const int M = pl.M, K = M / 2 + 1, B = 1 << lgB;
+  constexpr bool CT = MC > 0;
+  const int M = CT ? MC : pl.M;
+  const int lgb = CT ? LGBC : lgB;
+  const int K = M / 2 + 1, B = 1 << lgb;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
   C *twl = b1 + M * B;  // twiddles staged in LDS
-  for (int i = threadIdx.x; i < M; i += blockDim.x) twl[i] = tw_g[i];
+  for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
   const long long nrows = static_cast<long long>(M) * M;
   const long long row0 = static_cast<long long>(blockIdx.x) * 2 * B;
   // Z[k] = R1[k] + i R2[k] on 0..M/2 and conj(R1[M-k]) + i conj(R2[M-k]) above;
   // stored conjugated for the inverse transform.
-  for (int i = threadIdx.x; i < B * K; i += blockDim.x) {
-    const int b = fast_div(i, pl.k_magic), k = i - b * K;
+  for (int i = threadIdx.x; i < B * K; i += kThreads) {
+    const int b = div_K<MC>(i, pl), k = i - b * K;
     const long long gr = row0 + 2 * b;
     C r1, r2;
     if (gr < nrows) {
@@ -248,9 +336,9 @@ k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl
     }
   }
   __syncthreads();
-  const C *Z = fft_batch<R>(b0, b1, lgB, pl, twl);
-  for (int i = threadIdx.x; i < 2 * B * M; i += blockDim.x) {
-    const int r = fast_div(i, pl.m_magic), xk = i - r * M;
+  const C *Z = fft_any<R, MC, LGBC>(b0, b1, lgb, pl, twl);
+  for (int i = threadIdx.x; i < 2 * B * M; i += kThreads) {
+    const int r = div_M<MC>(i, pl), xk = i - r * M;
     const long long gr = row0 + r;
     if (gr >= nrows) continue;
     const C z = Z[xk * B + (r >> 1)];
@@ -270,23 +358,26 @@ struct EnergyOut {
   double *E;
 };
 
-template <typename R, bool INV>
+template <typename R, int MC, int LGBC, bool INV>
 __global__ void __launch_bounds__(kThreads)
 k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__restrict__ tw_g,
         EnergyOut eo) {
   using C = cplx_t<R>;
-  const int M = pl.M, K = M / 2 + 1, B = 1 << lgB;
+  constexpr bool CT = MC > 0;
+  const int M = CT ? MC : pl.M;
+  const int lgb = CT ? LGBC : lgB;
+  const int K = M / 2 + 1, B = 1 << lgb;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
   C *twl = b1 + M * B;  // twiddles staged in LDS
-  for (int i = threadIdx.x; i < M; i += blockDim.x) twl[i] = tw_g[i];
+  for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
   const int kx0 = blockIdx.x * B;
   const long long zoff = static_cast<long long>(blockIdx.y) * M * K;
   {
     C v[kMaxPerThread];
 #pragma unroll
     for (int k = 0; k < kMaxPerThread; ++k) {
-      const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
-      const int y = i >> lgB, b = i & (B - 1);
+      const int i = threadIdx.x + k * kThreads;
+      const int y = i >> lgb, b = i & (B - 1);
       if (i < M * B && kx0 + b < K) {
         v[k] = spec[zoff + static_cast<long long>(y) * K + kx0 + b];
         if (INV) v[k] = cconj(v[k]);
@@ -296,14 +387,14 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
     }
 #pragma unroll
     for (int k = 0; k < kMaxPerThread; ++k) {
-      const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
+      const int i = threadIdx.x + k * kThreads;
       if (i < M * B) b0[i] = v[k];
     }
   }
   __syncthreads();
-  const C *Z = fft_batch<R>(b0, b1, lgB, pl, twl);
-  for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
-    const int y = i >> lgB, b = i & (B - 1);
+  const C *Z = fft_any<R, MC, LGBC>(b0, b1, lgb, pl, twl);
+  for (int i = threadIdx.x; i < M * B; i += kThreads) {
+    const int y = i >> lgb, b = i & (B - 1);
     if (kx0 + b < K) {
       C v = Z[i];
       if (INV) v = cconj(v);
@@ -330,25 +421,28 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
 
 // ------------------------------------------ z pass with scaling and energy
 
-template <typename R>
+template <typename R, int MC, int LGBC>
 __global__ void __launch_bounds__(kThreads)
 k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__restrict__ tw_g,
               const double *__restrict__ axis_f, const double *__restrict__ axis_k2,
               double wscale, double *__restrict__ epart) {
   using C = cplx_t<R>;
-  const int M = pl.M, K = M / 2 + 1, B = 1 << lgB;
+  constexpr bool CT = MC > 0;
+  const int M = CT ? MC : pl.M;
+  const int lgb = CT ? LGBC : lgB;
+  const int K = M / 2 + 1, B = 1 << lgb;
   const int npen = M * K;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
   C *twl = b1 + M * B;  // twiddles staged in LDS
-  for (int i = threadIdx.x; i < M; i += blockDim.x) twl[i] = tw_g[i];
+  for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
   const int c0 = blockIdx.x * B;
   const long long zs = static_cast<long long>(M) * K;
   {
     C v[kMaxPerThread];
 #pragma unroll
     for (int k = 0; k < kMaxPerThread; ++k) {
-      const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
-      const int z = i >> lgB, b = i & (B - 1);
+      const int i = threadIdx.x + k * kThreads;
+      const int z = i >> lgb, b = i & (B - 1);
       if (i < M * B && c0 + b < npen) {
         v[k] = spec[z * zs + c0 + b];
       } else {
@@ -357,21 +451,21 @@ k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R>
     }
 #pragma unroll
     for (int k = 0; k < kMaxPerThread; ++k) {
-      const int i = threadIdx.x + k * static_cast<int>(blockDim.x);
+      const int i = threadIdx.x + k * kThreads;
       if (i < M * B) b0[i] = v[k];
     }
   }
   __syncthreads();
-  C *Z = fft_batch<R>(b0, b1, lgB, pl, twl);
+  C *Z = fft_any<R, MC, LGBC>(b0, b1, lgb, pl, twl);
   C *other = (Z == b0) ? b1 : b0;
 
   double e = 0.0;
-  for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
-    const int kz = i >> lgB, b = i & (B - 1);
+  for (int i = threadIdx.x; i < M * B; i += kThreads) {
+    const int kz = i >> lgb, b = i & (B - 1);
     const int c = c0 + b;
     C v = Z[i];
     if (c < npen) {
-      const int ky = fast_div(c, pl.k_magic), kx = c - ky * K;
+      const int ky = div_K<MC>(c, pl), kx = c - ky * K;
       const double k2 = axis_k2[kx] + axis_k2[ky] + axis_k2[kz];
       const double w = (kx == 0 && ky == 0 && kz == 0)
                            ? 0.0
@@ -388,9 +482,9 @@ k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R>
     Z[i] = v;  // holds conj(w * G^)
   }
   __syncthreads();
-  const C *Y = fft_batch<R>(Z, other, lgB, pl, twl);
-  for (int i = threadIdx.x; i < M * B; i += blockDim.x) {
-    const int z = i >> lgB, b = i & (B - 1);
+  const C *Y = fft_any<R, MC, LGBC>(Z, other, lgb, pl, twl);
+  for (int i = threadIdx.x; i < M * B; i += kThreads) {
+    const int z = i >> lgb, b = i & (B - 1);
     if (c0 + b < npen) spec[z * zs + c0 + b] = cconj(Y[i]);
   }
 
@@ -405,30 +499,33 @@ k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R>
   if (threadIdx.x == 0) epart[blockIdx.x] = red[0];
 }
 
-template <typename R>
-hipError_t fft_impl(se_plan &p, double *E_dev) {
+template <typename R, int MC>
+hipError_t fft_run(se_plan &p, double *E_dev) {
+  constexpr int LGBC = MC > 0 ? fft_lgb(MC, sizeof(R)) : 0;
   using C = cplx_t<R>;
   const int M = p.prm.M, K = M / 2 + 1, B = p.fft_batch;
   int lgB = 0;
   while ((1 << lgB) < B) ++lgB;
+  // The compiled kernels assume this M and batch; the grids below assume B.
+  if (MC > 0 && (MC != M || LGBC != lgB || p.fft_threads != kThreads)) return hipErrorInvalidValue;
   const size_t lds = sizeof(C) * (2 * M * B + M);
   C *spec = static_cast<C *>(p.buf.spec);
   const C *tw = static_cast<const C *>(p.buf.twiddle);
   const int xblocks = (M * M + 2 * B - 1) / (2 * B);
   hipError_t e = hipSuccess;
   stage_begin(p, SE_STAGE_FFT_X);
-  k_fft_x_r2c<R><<<xblocks, p.fft_threads, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec,
+  k_fft_x_r2c<R, MC, LGBC><<<xblocks, p.fft_threads, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec,
                                                      p.fft, lgB, tw);
   stage_end(p, SE_STAGE_FFT_X);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const dim3 yg((K + B - 1) / B, M);
   const EnergyOut none{nullptr, 0, nullptr, 0.0, nullptr};
   stage_begin(p, SE_STAGE_FFT_Y);
-  k_fft_y<R, false><<<yg, p.fft_threads, lds, p.stream>>>(spec, p.fft, lgB, tw, none);
+  k_fft_y<R, MC, LGBC, false><<<yg, p.fft_threads, lds, p.stream>>>(spec, p.fft, lgB, tw, none);
   stage_end(p, SE_STAGE_FFT_Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   stage_begin(p, SE_STAGE_FFT_Z_SCALE);
-  k_fft_z_scale<R><<<p.zfft_blocks, p.fft_threads, lds, p.stream>>>(
+  k_fft_z_scale<R, MC, LGBC><<<p.zfft_blocks, p.fft_threads, lds, p.stream>>>(
       spec, p.fft, lgB, tw, static_cast<const double *>(p.buf.axis_f),
       static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks);
   stage_end(p, SE_STAGE_FFT_Z_SCALE);
@@ -436,14 +533,34 @@ hipError_t fft_impl(se_plan &p, double *E_dev) {
   const double self_coef = (p.prm.flags & SE_FLAG_ADD_SELF) ? -p.prm.xi / sqrt(M_PI) : 0.0;
   const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.qsq, self_coef, E_dev};
   stage_begin(p, SE_STAGE_IFFT_Y);
-  k_fft_y<R, true><<<yg, p.fft_threads, lds, p.stream>>>(spec, p.fft, lgB, tw, eo);
+  k_fft_y<R, MC, LGBC, true><<<yg, p.fft_threads, lds, p.stream>>>(spec, p.fft, lgB, tw, eo);
   stage_end(p, SE_STAGE_IFFT_Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   stage_begin(p, SE_STAGE_IFFT_X);
-  k_fft_x_c2r<R><<<xblocks, p.fft_threads, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), p.fft,
+  k_fft_x_c2r<R, MC, LGBC><<<xblocks, p.fft_threads, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), p.fft,
                                                      lgB, tw);
   stage_end(p, SE_STAGE_IFFT_X);
   return hipGetLastError();
+}
+
+// Grid sizes with a compile-time FFT; any other size runs the generic passes.
+template <typename R>
+hipError_t fft_impl(se_plan &p, double *E_dev) {
+  switch (p.prm.M) {
+    case 16: return fft_run<R, 16>(p, E_dev);
+    case 24: return fft_run<R, 24>(p, E_dev);
+    case 32: return fft_run<R, 32>(p, E_dev);
+    case 40: return fft_run<R, 40>(p, E_dev);
+    case 48: return fft_run<R, 48>(p, E_dev);
+    case 64: return fft_run<R, 64>(p, E_dev);
+    case 80: return fft_run<R, 80>(p, E_dev);
+    case 96: return fft_run<R, 96>(p, E_dev);
+    case 128: return fft_run<R, 128>(p, E_dev);
+    case 160: return fft_run<R, 160>(p, E_dev);
+    case 192: return fft_run<R, 192>(p, E_dev);
+    case 256: return fft_run<R, 256>(p, E_dev);
+    default: return fft_run<R, 0>(p, E_dev);
+  }
 }
 
 }  // namespace

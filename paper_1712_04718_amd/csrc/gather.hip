@@ -14,7 +14,9 @@
 //   phase B: lane (group, jx) owns the x-offset jx of one particle and sums
 //            over the S^2 (jy, jz) offsets; the S lanes of a particle are
 //            then combined (shuffle tree for S = 4, 8, 16; in LDS otherwise).
-// Per-lane sums over y are compensated (Kahan).
+// Per-lane sums over y are compensated (Kahan) for B-splines; for the
+// Gaussian the derivative sums are rearranged around the stencil centre (see
+// phase B) and the lane parts are combined by a pairwise tree.
 #include "se_common.hpp"
 #include "window.hpp"
 
@@ -124,47 +126,75 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
         const R *f = fac + c * REC;
         const int packed = anc[c];
         const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
-        R gx, dgx, gy[S], dgy[S], gz[S], dgz[S];
-        gx = f[jx];
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-          gy[j] = f[S + j];
-          gz[j] = f[2 * S + j];
-        }
-        if constexpr (WIN == kBspline) {
-          dgx = f[3 * S + jx];
+        R t0, t1, t2, t3;  // this lane's parts of phi, and of F / (-q) along x, y, z
+        if constexpr (WIN == kGauss) {
+          // d/dx_m of a Gaussian factor is dc (j + OFF - d) g_j.  With the
+          // centred weights c_j = j + OFF - 1/2 and e = d - 1/2 (|e| <= 1/2):
+          //   sum_j (j + OFF - d) g_j a_j = sum_j c_j g_j a_j - e sum_j g_j a_j,
+          // so the derivative needs one extra weighted sum per axis.
+          const R dc = static_cast<R>(wc.dcoef);
+          const R gx = f[jx];
+          const R ex = f[3 * S + 0] - R(0.5), ey = f[3 * S + 1] - R(0.5), ez = f[3 * S + 2] - R(0.5);
+          R gy[S], gz[S], cy[S], cz[S];
 #pragma unroll
           for (int j = 0; j < S; ++j) {
+            gy[j] = f[S + j];
+            gz[j] = f[2 * S + j];
+            cy[j] = (static_cast<R>(j + OFF) - R(0.5)) * gy[j];
+            cz[j] = (static_cast<R>(j + OFF) - R(0.5)) * gz[j];
+          }
+          const R *col = blk + (az * TS + ay) * TS + ax + jx;
+          R s0 = R(0), s1 = R(0), s2 = R(0);
+#pragma unroll
+          for (int jy = 0; jy < S; ++jy) {
+            R a0 = R(0), b1 = R(0);
+#pragma unroll
+            for (int jz = 0; jz < S; ++jz) {
+              const R v = col[(jz * TS + jy) * TS];
+              a0 += v * gz[jz];
+              b1 += v * cz[jz];
+            }
+            s0 += gy[jy] * a0;  // sum g_y g_z Phi
+            s1 += cy[jy] * a0;  // sum c_y g_y g_z Phi
+            s2 += gy[jy] * b1;  // sum g_y c_z g_z Phi
+          }
+          const R dgx = dc * (static_cast<R>(jx + OFF) - f[3 * S + 0]) * gx;
+          t0 = gx * s0;
+          t1 = dgx * s0;
+          t2 = dc * gx * (s1 - ey * s0);
+          t3 = dc * gx * (s2 - ez * s0);
+          (void)ex;
+        } else {
+          const R gx = f[jx], dgx = f[3 * S + jx];
+          R gy[S], dgy[S], gz[S], dgz[S];
+#pragma unroll
+          for (int j = 0; j < S; ++j) {
+            gy[j] = f[S + j];
+            gz[j] = f[2 * S + j];
             dgy[j] = f[4 * S + j];
             dgz[j] = f[5 * S + j];
           }
-        } else {
-          // d/dx_m of the Gaussian factor: 2 a h t_j g_j, t_j = j + OFF - d
-          const R dc = static_cast<R>(wc.dcoef);
-          dgx = dc * (static_cast<R>(jx + OFF) - f[3 * S + 0]) * gx;
+          const R *col = blk + (az * TS + ay) * TS + ax + jx;
+          Kahan<R> s_pot, s_fy, s_fz;
 #pragma unroll
-          for (int j = 0; j < S; ++j) {
-            dgy[j] = dc * (static_cast<R>(j + OFF) - f[3 * S + 1]) * gy[j];
-            dgz[j] = dc * (static_cast<R>(j + OFF) - f[3 * S + 2]) * gz[j];
+          for (int jy = 0; jy < S; ++jy) {
+            R a0 = R(0), a1 = R(0);
+#pragma unroll
+            for (int jz = 0; jz < S; ++jz) {
+              const R v = col[(jz * TS + jy) * TS];
+              a0 += v * gz[jz];
+              a1 += v * dgz[jz];
+            }
+            s_pot.add(gy[jy] * a0);
+            s_fy.add(dgy[jy] * a0);
+            s_fz.add(gy[jy] * a1);
           }
+          const R sp_v = s_pot.value();
+          t0 = gx * sp_v;
+          t1 = dgx * sp_v;
+          t2 = gx * s_fy.value();
+          t3 = gx * s_fz.value();
         }
-        const R *col = blk + (az * TS + ay) * TS + ax + jx;
-        Kahan<R> s_pot, s_fy, s_fz;
-#pragma unroll
-        for (int jy = 0; jy < S; ++jy) {
-          R a0 = R(0), a1 = R(0);
-#pragma unroll
-          for (int jz = 0; jz < S; ++jz) {
-            const R v = col[(jz * TS + jy) * TS];
-            a0 += v * gz[jz];
-            a1 += v * dgz[jz];
-          }
-          s_pot.add(gy[jy] * a0);
-          s_fy.add(dgy[jy] * a0);
-          s_fz.add(gy[jy] * a1);
-        }
-        const R sp_v = s_pot.value();
-        R t0 = gx * sp_v, t1 = dgx * sp_v, t2 = gx * s_fy.value(), t3 = gx * s_fz.value();
         if constexpr (POW2) {
           // pairwise tree over the S lanes of the group
 #pragma unroll

@@ -63,16 +63,7 @@ int choose_tile(const se_params &p) {
   return 8;
 }
 
-// FFT work-groups are kFftThreads lanes holding B pencils: B a power of two
-// with M * B <= 16 * kFftThreads (elements per lane when loading) and two LDS
-// buffers of M x B complex plus the M twiddles in 64 KB.
-constexpr int kFftThreads = 256;
-int fft_batch_of(const se_params &p) {
-  const int csz = 2 * real_size(p);
-  int B = 16;
-  while (B > 1 && (p.M * B > 16 * kFftThreads || (2 * p.M * B + p.M) * csz > 65536)) B >>= 1;
-  return B;
-}
+int fft_batch_of(const se_params &p) { return 1 << sek::fft_lgb(p.M, real_size(p)); }
 
 sek::FftPlan radix_plan(int M) {
   sek::FftPlan pl{};
@@ -218,7 +209,7 @@ void derive(se_plan &pl) {
   pl.bin_blocks = (pl.n_max + sek::kThreads - 1) / sek::kThreads;
   if (pl.bin_blocks < 1) pl.bin_blocks = 1;
   pl.fft_batch = fft_batch_of(p);
-  pl.fft_threads = kFftThreads;
+  pl.fft_threads = sek::kThreads;
   pl.zfft_blocks = (p.M * (p.M / 2 + 1) + pl.fft_batch - 1) / pl.fft_batch;
   pl.fft = radix_plan(p.M);
 }

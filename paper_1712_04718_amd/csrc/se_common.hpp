@@ -156,6 +156,17 @@ constexpr int kGatherAdjoint = 1;         // out_pot = gE phi, out_vec = -gE F
 
 constexpr int kThreads = 256;  // work-group size of every kernel
 
+// Pencils per FFT work-group, as log2: B a power of two, at most 16, with
+// M * B <= 16 * kThreads (elements per thread when loading) and two LDS
+// buffers of M x B complex plus the M twiddles within 64 KB.
+constexpr int fft_lgb(int M, int real_size) {
+  int B = 16;
+  while (B > 1 && (M * B > 16 * kThreads || (2 * M * B + M) * 2 * real_size > 65536)) B >>= 1;
+  int lg = 0;
+  while ((1 << lg) < B) ++lg;
+  return lg;
+}
+
 // Tile counters are spaced one cache line apart: device-wide atomics on the
 // same line serialise, on different lines they proceed in parallel.
 constexpr int kCountStride = 32;
