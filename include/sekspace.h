@@ -68,7 +68,8 @@ typedef enum { SE_FP32 = 0, SE_FP64 = 1 } se_dtype;
 #define SE_FLAG_ADD_SELF 1u  /* add the self terms of eqs. (1.5)-(1.6):
                                 phi += -2 xi q / sqrt(pi), E += -(xi/sqrt(pi)) sum q^2 */
 #define SE_FLAG_TIMING 2u    /* record a HIP event pair around every kernel launch
-                                (on the plan's stream) for se_plan_stage_times    */
+                                (on the plan's stream) for se_plan_stage_times;
+                                such a plan must not be captured in a graph      */
 
 /* Kernel stages of one evaluation, in launch order (se_plan_stage_times). */
 enum {
@@ -127,10 +128,13 @@ se_status se_plan_set_stream(se_plan *plan, void *hip_stream);
 /* Read back the derived eta (0 for the B-spline window). */
 se_status se_plan_eta(const se_plan *plan, double *eta);
 
-/* Plans created with SE_FLAG_TIMING: wait for the last recorded launches
- * and write the duration in milliseconds of each stage's most recent launch
- * to ms[0..n-1] (stage order above; -1 for a stage not launched since the
- * plan was created).  SE_ERR_STATE for plans without the flag. */
+/* Plans created with SE_FLAG_TIMING: wait for the recorded launches and
+ * write to ms[0..n-1] (stage order above) the mean duration in milliseconds
+ * of each stage's launches since the previous call (or since plan creation);
+ * -1 for a stage not launched in that interval.  Every launch is counted: the
+ * plan keeps a ring of event pairs per stage and, once a ring is full, waits
+ * for the oldest pair before reusing it.  A timing plan must not be captured
+ * into a HIP graph.  SE_ERR_STATE for plans without the flag. */
 se_status se_plan_stage_times(se_plan *plan, double *ms, int n);
 
 /* Release the plan and its workspace (synchronises its stream first). */

@@ -119,8 +119,8 @@ class SEPlan:
         return gx, gq
 
     def stage_times(self):
-        """{stage: milliseconds} of the most recent launch of each kernel
-        (plans created with ``timing=True``); waits for those launches."""
+        """{stage: mean milliseconds per launch} over the launches since the
+        previous call (plans created with ``timing=True``); waits for them."""
         n = len(_lib.STAGES)
         buf = (ctypes.c_double * n)()
         _lib.check(self.lib.se_plan_stage_times(self._plan, buf, n))

@@ -82,12 +82,32 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
   int *anc = reinterpret_cast<int *>(h_smem + L::BLK + L::RED + L::FAC);
   int *org = anc + CHUNK;
 
+  // Stage the block: loads are issued in unrolled batches into registers and
+  // only then written to LDS, so a thread has a batch of loads in flight
+  // instead of waiting for each one in turn.
   const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
   const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
-  for (int i = tid; i < TS * TS * TS; i += kThreads) {
-    const int lz = i / (TS * TS), ly = (i / TS) % TS, lx = i % TS;
-    const int gz = wrap_index(bz + lz, M), gy = wrap_index(by + ly, M), gx = wrap_index(bx + lx, M);
-    blk[i] = phi_grid[(static_cast<long long>(gz) * M + gy) * M + gx];
+  constexpr int TS3 = TS * TS * TS;
+  constexpr int NST = (TS3 + kThreads - 1) / kThreads;  // elements per thread
+  constexpr int BATCH = sizeof(R) == 4 ? 16 : 8;
+#pragma unroll
+  for (int k0 = 0; k0 < NST; k0 += BATCH) {
+    R v[BATCH];
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int i = tid + (k0 + k) * kThreads;
+      if (k0 + k < NST && i < TS3) {
+        const int lz = i / (TS * TS), rem = i - lz * (TS * TS);
+        const int ly = rem / TS, lx = rem - ly * TS;
+        const int gz = wrap_near(bz + lz, M), gy = wrap_near(by + ly, M), gx = wrap_near(bx + lx, M);
+        v[k] = phi_grid[(gz * M + gy) * M + gx];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int i = tid + (k0 + k) * kThreads;
+      if (k0 + k < NST && i < TS3) blk[i] = v[k];
+    }
   }
 
   const R scale = gscale ? static_cast<R>(*gscale) : R(1);

@@ -228,11 +228,12 @@ hipError_t upload_twiddles(se_plan &pl) {
 
 void destroy_events(se_plan &pl) {
   if (!pl.timing) return;
-  for (int i = 0; i < SE_NUM_STAGES; ++i) {
-    if (pl.ev_begin[i]) (void)hipEventDestroy(pl.ev_begin[i]);
-    if (pl.ev_end[i]) (void)hipEventDestroy(pl.ev_end[i]);
-    pl.ev_begin[i] = pl.ev_end[i] = nullptr;
-  }
+  for (auto &t : pl.timers)
+    for (int k = 0; k < sek::kTimingSlots; ++k) {
+      if (t.begin[k]) (void)hipEventDestroy(t.begin[k]);
+      if (t.end[k]) (void)hipEventDestroy(t.end[k]);
+      t.begin[k] = t.end[k] = nullptr;
+    }
 }
 
 void free_all(se_plan &pl) {
@@ -295,6 +296,14 @@ se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_p
   pl->stream = static_cast<hipStream_t>(hip_stream);
   pl->last_N = -1;
   derive(*pl);
+  // staged tile blocks index the grid in [-(P-1), M + T + P - 3]; the kernels
+  // wrap that range without division (holds for every M >= 8 with P <= M)
+  if (pl->T + pl->prm.P - 3 >= 2 * pl->prm.M) {
+    const int T = pl->T;
+    delete pl;
+    return fail(SE_ERR_GRID, "tile edge %d with support %d needs a larger grid than M=%d", T,
+                prm->P, prm->M);
+  }
   hipError_t e = hipGetDevice(&pl->device);
   if (e != hipSuccess) {
     delete pl;
@@ -345,10 +354,11 @@ se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_p
   if (e == hipSuccess)
     e = pl->prm.dtype == SE_FP64 ? upload_twiddles<double>(*pl) : upload_twiddles<float>(*pl);
   pl->timing = (pl->prm.flags & SE_FLAG_TIMING) != 0;
-  for (int i = 0; i < SE_NUM_STAGES && pl->timing && e == hipSuccess; ++i) {
-    e = hipEventCreate(&pl->ev_begin[i]);
-    if (e == hipSuccess) e = hipEventCreate(&pl->ev_end[i]);
-  }
+  for (int i = 0; i < SE_NUM_STAGES && pl->timing && e == hipSuccess; ++i)
+    for (int k = 0; k < sek::kTimingSlots && e == hipSuccess; ++k) {
+      e = hipEventCreate(&pl->timers[i].begin[k]);
+      if (e == hipSuccess) e = hipEventCreate(&pl->timers[i].end[k]);
+    }
   if (e == hipSuccess) e = hipMemset(pl->buf.counts, 0, sz.counts);
   if (e == hipSuccess) {
     const auto lists = cover_lists(M, pl->T, pl->prm.P, stencil_offset(pl->prm));
@@ -392,14 +402,15 @@ se_status se_plan_eta(const se_plan *plan, double *eta) {
 se_status se_plan_stage_times(se_plan *plan, double *ms, int n) {
   if (!plan || (!ms && n > 0) || n < 0) return fail(SE_ERR_ARG, "bad arguments");
   if (!plan->timing) return fail(SE_ERR_STATE, "plan was created without SE_FLAG_TIMING");
-  for (int i = 0; i < n && i < SE_NUM_STAGES; ++i) {
-    ms[i] = -1.0;
-    if (!plan->ev_used[i]) continue;
-    hipError_t e = hipEventSynchronize(plan->ev_end[i]);
-    float t = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&t, plan->ev_begin[i], plan->ev_end[i]);
-    if (e != hipSuccess) return hip_fail(e, "stage timing");
-    ms[i] = t;
+  for (int i = 0; i < SE_NUM_STAGES; ++i) {
+    sek::StageTimer &t = plan->timers[i];
+    while (t.harvested < t.issued) {
+      hipError_t e = sek::harvest_oldest(t);
+      if (e != hipSuccess) return hip_fail(e, "stage timing");
+    }
+    if (i < n) ms[i] = t.count > 0 ? t.sum_ms / static_cast<double>(t.count) : -1.0;
+    t.sum_ms = 0.0;
+    t.count = 0;
   }
   for (int i = SE_NUM_STAGES; i < n; ++i) ms[i] = -1.0;
   return SE_OK;

@@ -38,11 +38,13 @@ __device__ inline int fast_div(int n, unsigned magic) {
   return static_cast<int>(__umulhi(static_cast<unsigned>(n), magic));
 }
 
-// v mod M for v in a few periods of [0, M) (no division).
-__device__ inline int wrap_index(int v, int M) {
-  while (v < 0) v += M;
-  while (v >= M) v -= M;
-  return v;
+// v mod M for v in [-M, 3M), branch-free.  Every grid index of a staged tile
+// block lies in [-(S-1), M + T + S - 3], inside that range whenever S <= M and
+// T + S - 3 < 2M (the plan checks both).
+__device__ inline int wrap_near(int v, int M) {
+  v = v < 0 ? v + M : v;
+  v = v >= M ? v - M : v;
+  return v >= M ? v - M : v;
 }
 
 struct FftPlan {
@@ -65,6 +67,34 @@ struct FoldTables {
   int TS;            // tile block edge T + S - 1
   int ntx;           // tiles per axis
 };
+
+// Event pairs around the launches of one stage (plans with SE_FLAG_TIMING).
+// A ring of kTimingSlots pairs: when it is full, the oldest pair is waited for
+// and its duration added to sum_ms before the pair is reused, so every launch
+// is counted while up to kTimingSlots launches stay in flight.
+constexpr int kTimingSlots = 16;
+struct StageTimer {
+  hipEvent_t begin[kTimingSlots] = {};
+  hipEvent_t end[kTimingSlots] = {};
+  long long issued = 0;     // launches recorded
+  long long harvested = 0;  // launches whose duration is in sum_ms
+  double sum_ms = 0.0;      // durations harvested since the last read
+  long long count = 0;      // launches in sum_ms
+};
+
+// Wait for the oldest unharvested launch of a stage and add its duration.
+inline hipError_t harvest_oldest(StageTimer &t) {
+  const int slot = static_cast<int>(t.harvested % kTimingSlots);
+  hipError_t e = hipEventSynchronize(t.end[slot]);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.begin[slot], t.end[slot]);
+  ++t.harvested;
+  if (e == hipSuccess) {
+    t.sum_ms += ms;
+    ++t.count;
+  }
+  return e;
+}
 
 struct DeviceBuffers {
   void *grid = nullptr;       // M^3 real: the scaled grid Phi (input of gathering)
@@ -119,9 +149,7 @@ struct se_plan {
 
   // optional per-kernel timing (SE_FLAG_TIMING)
   bool timing;
-  hipEvent_t ev_begin[SE_NUM_STAGES];
-  hipEvent_t ev_end[SE_NUM_STAGES];
-  bool ev_used[SE_NUM_STAGES];
+  sek::StageTimer timers[SE_NUM_STAGES];
 };
 
 namespace sek {
@@ -136,13 +164,16 @@ hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode,
 
 // Event pair around one kernel launch when the plan records timings.
 inline void stage_begin(se_plan &p, int stage) {
-  if (p.timing) (void)hipEventRecord(p.ev_begin[stage], p.stream);
+  if (!p.timing) return;
+  StageTimer &t = p.timers[stage];
+  if (t.issued - t.harvested == kTimingSlots) (void)harvest_oldest(t);
+  (void)hipEventRecord(t.begin[t.issued % kTimingSlots], p.stream);
 }
 inline void stage_end(se_plan &p, int stage) {
-  if (p.timing) {
-    (void)hipEventRecord(p.ev_end[stage], p.stream);
-    p.ev_used[stage] = true;
-  }
+  if (!p.timing) return;
+  StageTimer &t = p.timers[stage];
+  (void)hipEventRecord(t.end[t.issued % kTimingSlots], p.stream);
+  ++t.issued;
 }
 
 // LDS bytes a spreading / gathering work-group needs (tile edge T, support S).

@@ -78,17 +78,32 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
 
   for (int i = tid; i < TS3; i += kThreads) blk[i] = A(0);
 
-  // fixed-point scale of this tile
+  // Fixed-point scale of this tile, from a bound on sum |q| that does not
+  // depend on the order of the particles (the order inside a tile comes from
+  // atomics): qmax = max |q| is exact, each particle contributes the integer
+  // u = ceil(|q| / qmax * 2^20) >= |q| / qmax * 2^20, and integer sums are
+  // exact, so qmax * sum(u) / 2^20 >= sum |q| is the same on every run.
   double scale = 1.0, inv_scale = 1.0;
   if constexpr (FIXED) {
-    double s = 0.0;
-    for (int p = start + tid; p < end; p += kThreads) s += fabs(static_cast<double>(sorted[p].q));
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if ((tid & 63) == 0) red[tid >> 6] = s;
+    double m = 0.0;
+    for (int p = start + tid; p < end; p += kThreads) m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((tid & 63) == 0) red[tid >> 6] = m;
     __syncthreads();
-    double qsum = 0.0;
-    for (int w = 0; w < NWAVES; ++w) qsum += red[w];
-    const double bound = wmax * qsum;
+    double qmax = 0.0;
+    for (int w = 0; w < NWAVES; ++w) qmax = fmax(qmax, red[w]);
+    long long u = 0;
+    if (qmax > 0.0)
+      for (int p = start + tid; p < end; p += kThreads)
+        u += static_cast<long long>(ceil(fabs(static_cast<double>(sorted[p].q)) / qmax * 1048576.0));
+    for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
+    __syncthreads();  // every wave has read red[]
+    long long *ured = reinterpret_cast<long long *>(red);
+    if ((tid & 63) == 0) ured[tid >> 6] = u;
+    __syncthreads();
+    long long usum = 0;
+    for (int w = 0; w < NWAVES; ++w) usum += ured[w];
+    const double bound = wmax * qmax * (static_cast<double>(usum) / 1048576.0);
     if (bound > 0.0) {
       scale = 1073741824.0 / bound;  // 2^30
       inv_scale = bound / 1073741824.0;

@@ -1,0 +1,43 @@
+"""Per-kernel timing plans (SE_FLAG_TIMING): every launch is counted, the
+ring of event pairs wraps without losing launches, and timing changes no
+result."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, to_dev
+from paper_1712_04718_amd import SEPlan, _lib
+
+pytestmark = pytest.mark.gpu
+
+
+def test_stage_means_cover_every_launch_and_reset():
+    print("[timing] N=3000 L=20 M=40 P=8 fp32, 40 steps", flush=True)
+    rng = np.random.default_rng(11)
+    x = rng.random((3000, 3)) * 20.0
+    q = rng.standard_normal(3000)
+    q -= q.mean()
+    xt, qt = to_dev(x, q, torch.float32)
+    ref = SEPlan(40, 8, 20.0, 0.6, dtype=torch.float32, n_max=3000)
+    tim = SEPlan(40, 8, 20.0, 0.6, dtype=torch.float32, n_max=3000, timing=True)
+    E0, phi0, F0 = ref.kspace(xt, qt)
+    for _ in range(40):  # more launches than the ring of event pairs holds
+        E1, phi1, F1 = tim.kspace(xt, qt)
+    times = tim.stage_times()
+    assert set(times) == set(_lib.STAGES)
+    assert all(v > 0 for v in times.values()), times
+    # nothing launched since the read: every stage reports "not launched"
+    assert tim.stage_times() == {}
+    # the FP32 spread is order-independent, so timing changes no bit
+    torch.cuda.synchronize()
+    assert E0.item() == E1.item()
+    assert torch.equal(phi0, phi1) and torch.equal(F0, F1)
+    for p in (ref, tim):
+        p.close()
+
+
+def test_stage_times_needs_timing_plan():
+    plan = SEPlan(16, 4, 10.0, 0.5, dtype=torch.float32, n_max=10)
+    with pytest.raises(_lib.SeError, match="SE_ERR_STATE"):
+        plan.stage_times()
+    plan.close()
