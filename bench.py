@@ -294,6 +294,27 @@ def run(args):
         log(f"{tag}: eager {ms_eager * 1e3:.1f} us/step (median "
             f"{percentile(per_step, 0.5) * 1e3:.1f}), graph {ms_graph * 1e3:.1f} us/step")
 
+        # the autograd form: E = SEEnergy(x, q), then E.backward() (the
+        # adjoint gather on the stored grid gives dE/dx and dE/dq)
+        from paper_1712_04718_amd import SEEnergy
+        xg = xt.clone().requires_grad_(True)
+        qg = qt.clone().requires_grad_(True)
+
+        def fwd_bwd():
+            xg.grad = None
+            qg.grad = None
+            SEEnergy.apply(xg, qg, plan).backward()
+
+        for _ in range(args.warmup):
+            fwd_bwd()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            fwd_bwd()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_autograd = e0.elapsed_time(e1) / args.steps
+
         # per-kernel durations: a plan that records a HIP event pair around
         # every launch on its stream, over a timed region of K steps
         tplan = SEPlan(M, P, L, xi, window=window, dtype=dtype, n_max=N, device=dev,
@@ -327,6 +348,7 @@ def run(args):
         err_F = O.rel_rms(Fg, Fo)
         err_E = abs(E.item() - Eo) / abs(Eo)
         out[tag] = dict(ms_eager=ms_eager, ms_graph=ms_graph, per_step=per_step,
+                        ms_autograd=ms_autograd,
                         ms_timed_eager=ms_timed_eager, err_F=err_F, err_E=err_E,
                         stages_ms=stages)
         for t in (plan, tplan):
@@ -410,6 +432,9 @@ def run(args):
         "rms_force_err_vs_fp64_oracle": f32["err_F"],
         "energy_rel_err_vs_fp64_oracle": f32["err_E"],
         "graph": {"ms_per_step": f32["ms_graph"], "value": N / (f32["ms_graph"] * 1e-3)},
+        "autograd": {"ms_per_step": f32["ms_autograd"],
+                     "value": N / (f32["ms_autograd"] * 1e-3),
+                     "step": "SEEnergy forward + backward (dE/dx, dE/dq)"},
         "stages_us": {k: round(v * 1e3, 2) for k, v in stages.items()},
         "stages_region_ms_per_step": f32["ms_timed_eager"],
         "grid_pass_hbm_frac": hbm_frac,
@@ -421,6 +446,7 @@ def run(args):
         f64 = out["f64"]
         res["fp64"] = {"value": N / (f64["ms_eager"] * 1e-3), "ms_per_step": f64["ms_eager"],
                        "graph_ms_per_step": f64["ms_graph"],
+                       "autograd_ms_per_step": f64["ms_autograd"],
                        "step_ms_median": percentile(f64["per_step"], 0.5),
                        "rms_force_err_vs_fp64_oracle": f64["err_F"],
                        "stages_us": {k: round(v * 1e3, 2) for k, v in f64["stages_ms"].items()}}

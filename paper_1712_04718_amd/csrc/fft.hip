@@ -30,7 +30,7 @@ namespace {
 extern __shared__ __align__(16) unsigned char f_smem[];
 
 // Complex elements per thread when a work-group loads its B pencils
-// (M * B <= 16 * threads for every plan, see fft_batch_of).
+// (M * B <= 16 * threads for every plan, see fft_lgb).
 constexpr int kMaxPerThread = 16;
 
 template <typename C> __device__ inline C cmul(C a, C b) {
@@ -501,44 +501,49 @@ k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R>
 
 template <typename R, int MC>
 hipError_t fft_run(se_plan &p, double *E_dev) {
-  constexpr int LGBC = MC > 0 ? fft_lgb(MC, sizeof(R)) : 0;
+  // compiled pencils per work-group of each pass (ignored for MC = 0)
+  constexpr int LX = MC > 0 ? fft_lgb(MC, sizeof(R), kPassX) : 0;
+  constexpr int LY = MC > 0 ? fft_lgb(MC, sizeof(R), kPassY) : 0;
+  constexpr int LZ = MC > 0 ? fft_lgb(MC, sizeof(R), kPassZ) : 0;
   using C = cplx_t<R>;
-  const int M = p.prm.M, K = M / 2 + 1, B = p.fft_batch;
-  int lgB = 0;
-  while ((1 << lgB) < B) ++lgB;
-  // The compiled kernels assume this M and batch; the grids below assume B.
-  if (MC > 0 && (MC != M || LGBC != lgB || p.fft_threads != kThreads)) return hipErrorInvalidValue;
-  const size_t lds = sizeof(C) * (2 * M * B + M);
+  const int M = p.prm.M, K = M / 2 + 1;
+  const int lx = p.fft_lgb[kPassX], ly = p.fft_lgb[kPassY], lz = p.fft_lgb[kPassZ];
+  // The compiled kernels assume this M and these batches; the grids below
+  // are sized from the plan's.
+  if (MC > 0 && (MC != M || LX != lx || LY != ly || LZ != lz || p.fft_threads != kThreads))
+    return hipErrorInvalidValue;
+  const int Bx = 1 << lx, By = 1 << ly;
+  const auto lds_of = [M](int lg) { return sizeof(C) * (2 * M * (1 << lg) + M); };
   C *spec = static_cast<C *>(p.buf.spec);
   const C *tw = static_cast<const C *>(p.buf.twiddle);
-  const int xblocks = (M * M + 2 * B - 1) / (2 * B);
+  const int xblocks = (M * M + 2 * Bx - 1) / (2 * Bx);
   hipError_t e = hipSuccess;
   stage_begin(p, SE_STAGE_FFT_X);
-  k_fft_x_r2c<R, MC, LGBC><<<xblocks, p.fft_threads, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec,
-                                                     p.fft, lgB, tw);
+  k_fft_x_r2c<R, MC, LX><<<xblocks, p.fft_threads, lds_of(lx), p.stream>>>(
+      static_cast<const R *>(p.buf.grid), spec, p.fft, lx, tw);
   stage_end(p, SE_STAGE_FFT_X);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const dim3 yg((K + B - 1) / B, M);
+  const dim3 yg((K + By - 1) / By, M);
   const EnergyOut none{nullptr, 0, nullptr, 0.0, nullptr};
   stage_begin(p, SE_STAGE_FFT_Y);
-  k_fft_y<R, MC, LGBC, false><<<yg, p.fft_threads, lds, p.stream>>>(spec, p.fft, lgB, tw, none);
+  k_fft_y<R, MC, LY, false><<<yg, p.fft_threads, lds_of(ly), p.stream>>>(spec, p.fft, ly, tw, none);
   stage_end(p, SE_STAGE_FFT_Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   stage_begin(p, SE_STAGE_FFT_Z_SCALE);
-  k_fft_z_scale<R, MC, LGBC><<<p.zfft_blocks, p.fft_threads, lds, p.stream>>>(
-      spec, p.fft, lgB, tw, static_cast<const double *>(p.buf.axis_f),
+  k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_of(lz), p.stream>>>(
+      spec, p.fft, lz, tw, static_cast<const double *>(p.buf.axis_f),
       static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks);
   stage_end(p, SE_STAGE_FFT_Z_SCALE);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double self_coef = (p.prm.flags & SE_FLAG_ADD_SELF) ? -p.prm.xi / sqrt(M_PI) : 0.0;
   const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.qsq, self_coef, E_dev};
   stage_begin(p, SE_STAGE_IFFT_Y);
-  k_fft_y<R, MC, LGBC, true><<<yg, p.fft_threads, lds, p.stream>>>(spec, p.fft, lgB, tw, eo);
+  k_fft_y<R, MC, LY, true><<<yg, p.fft_threads, lds_of(ly), p.stream>>>(spec, p.fft, ly, tw, eo);
   stage_end(p, SE_STAGE_IFFT_Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   stage_begin(p, SE_STAGE_IFFT_X);
-  k_fft_x_c2r<R, MC, LGBC><<<xblocks, p.fft_threads, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), p.fft,
-                                                     lgB, tw);
+  k_fft_x_c2r<R, MC, LX><<<xblocks, p.fft_threads, lds_of(lx), p.stream>>>(
+      spec, static_cast<R *>(p.buf.grid), p.fft, lx, tw);
   stage_end(p, SE_STAGE_IFFT_X);
   return hipGetLastError();
 }

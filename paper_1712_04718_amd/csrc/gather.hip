@@ -36,11 +36,12 @@ template <typename R> struct Kahan {
   __device__ inline R value() const { return s - c; }
 };
 
-// particles per phase-A round: one per thread, fewer when the factor table
-// would exceed 32 KB
+// particles per phase-A round: one per thread, fewer (down to a wave) while
+// the factor table would exceed 32 KB
 constexpr int gather_chunk(int real_size, int rec) {
-  return (real_size * rec * kThreads <= 32768) ? kThreads
-         : (real_size * rec * (kThreads / 2) <= 32768) ? kThreads / 2 : kThreads / 4;
+  int c = kTileThreads;
+  while (c > 64 && real_size * rec * c > 32768) c /= 2;
+  return c;
 }
 constexpr int gather_rec(int window, int S) { return window == kGauss ? 3 * S + 4 : 6 * S + 1; }
 
@@ -51,14 +52,15 @@ template <typename R, int WIN, int S, int T> struct GatherLds {
   static constexpr int REC = gather_rec(WIN, S);
   static constexpr int CHUNK = gather_chunk(sizeof(R), REC);
   static constexpr size_t BLK = sizeof(R) * ((TS * TS * TS + 3) & ~3);
-  static constexpr size_t RED = sizeof(R) * kThreads * 4;
+  // lane partials, only for supports that are not a power of two
+  static constexpr size_t RED = (S & (S - 1)) ? sizeof(R) * kTileThreads * 4 : 0;
   static constexpr size_t FAC = sizeof(R) * CHUNK * REC;
   static constexpr size_t IDX = 2 * sizeof(int) * CHUNK;
   static constexpr size_t TOTAL = BLK + RED + FAC + IDX;
 };
 
 template <typename R, int WIN, int S, int T>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kTileThreads)
 k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ sorted,
          const int2 *__restrict__ meta, const int *__restrict__ offsets, int M, int ntx,
          WindowConsts wc, const double *__restrict__ gscale, int mode, R self_coef,
@@ -67,7 +69,7 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
   constexpr int TS = L::TS, REC = L::REC, CHUNK = L::CHUNK;
   constexpr int GROUPS = 64 / S;
   constexpr int OFF = Stencil<WIN, S>::OFF;
-  constexpr int NWAVES = kThreads / 64;
+  constexpr int NWAVES = kTileThreads / 64;
   constexpr bool POW2 = (S & (S - 1)) == 0;
 
   const int tile = blockIdx.x;
@@ -88,14 +90,14 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
   const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
   const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
   constexpr int TS3 = TS * TS * TS;
-  constexpr int NST = (TS3 + kThreads - 1) / kThreads;  // elements per thread
+  constexpr int NST = (TS3 + kTileThreads - 1) / kTileThreads;  // elements per thread
   constexpr int BATCH = sizeof(R) == 4 ? 16 : 8;
 #pragma unroll
   for (int k0 = 0; k0 < NST; k0 += BATCH) {
     R v[BATCH];
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
-      const int i = tid + (k0 + k) * kThreads;
+      const int i = tid + (k0 + k) * kTileThreads;
       if (k0 + k < NST && i < TS3) {
         const int lz = i / (TS * TS), rem = i - lz * (TS * TS);
         const int ly = rem / TS, lx = rem - ly * TS;
@@ -105,7 +107,7 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
     }
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
-      const int i = tid + (k0 + k) * kThreads;
+      const int i = tid + (k0 + k) * kTileThreads;
       if (k0 + k < NST && i < TS3) blk[i] = v[k];
     }
   }
@@ -282,7 +284,7 @@ hipError_t gather_one(se_plan &p, const double *gscale, int mode, void *pot, voi
     if (e != hipSuccess) return e;
   }
   stage_begin(p, SE_STAGE_GATHER);
-  k_gather<R, WIN, S, T><<<p.ntiles, kThreads, lds, p.stream>>>(
+  k_gather<R, WIN, S, T><<<p.ntiles, kTileThreads, lds, p.stream>>>(
       static_cast<const R *>(p.buf.grid), static_cast<const SortedParticle<R> *>(p.buf.sorted),
       p.buf.meta, p.buf.offsets, p.prm.M, p.ntx, wc, gscale, mode, static_cast<R>(self),
       static_cast<R *>(pot), static_cast<R *>(vec));
@@ -328,8 +330,9 @@ size_t gather_lds_bytes(int real_size, int window, int S, int T) {
   const int win = window == SE_WINDOW_GAUSSIAN ? kGauss : kBspline;
   const size_t rec = gather_rec(win, S);
   const size_t chunk = gather_chunk(real_size, static_cast<int>(rec));
-  return real_size * ((ts * ts * ts + 3) & ~static_cast<size_t>(3)) +
-         static_cast<size_t>(real_size) * kThreads * 4 + real_size * chunk * rec + 2 * 4 * chunk;
+  const size_t red = (S & (S - 1)) ? static_cast<size_t>(real_size) * kTileThreads * 4 : 0;
+  return real_size * ((ts * ts * ts + 3) & ~static_cast<size_t>(3)) + red +
+         real_size * chunk * rec + 2 * 4 * chunk;
 }
 
 hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode, void *out_pot,

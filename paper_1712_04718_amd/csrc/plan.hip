@@ -60,10 +60,9 @@ int choose_tile(const se_params &p) {
     const long long nt = (p.M + T - 1) / T;
     if (nt * nt * nt >= 512 && fits(T)) return T;
   }
-  return 8;
+  return fits(8) ? 8 : 0;  // 0: no tile edge fits (the plan is refused)
 }
 
-int fft_batch_of(const se_params &p) { return 1 << sek::fft_lgb(p.M, real_size(p)); }
 
 sek::FftPlan radix_plan(int M) {
   sek::FftPlan pl{};
@@ -204,13 +203,14 @@ void derive(se_plan &pl) {
     pl.eta = pl.a = pl.cg = pl.beta = 0.0;
   }
   pl.T = choose_tile(p);
-  pl.ntx = (p.M + pl.T - 1) / pl.T;
+  pl.ntx = pl.T > 0 ? (p.M + pl.T - 1) / pl.T : 0;
   pl.ntiles = pl.ntx * pl.ntx * pl.ntx;
   pl.bin_blocks = (pl.n_max + sek::kThreads - 1) / sek::kThreads;
   if (pl.bin_blocks < 1) pl.bin_blocks = 1;
-  pl.fft_batch = fft_batch_of(p);
+  for (int pass = 0; pass < 3; ++pass) pl.fft_lgb[pass] = sek::fft_lgb(p.M, real_size(p), pass);
   pl.fft_threads = sek::kThreads;
-  pl.zfft_blocks = (p.M * (p.M / 2 + 1) + pl.fft_batch - 1) / pl.fft_batch;
+  const int bz = 1 << pl.fft_lgb[sek::kPassZ];
+  pl.zfft_blocks = (p.M * (p.M / 2 + 1) + bz - 1) / bz;
   pl.fft = radix_plan(p.M);
 }
 
@@ -277,6 +277,9 @@ se_status se_plan_workspace_size(const se_params *prm, int n_max, size_t *bytes)
   tmp.prm = *prm;
   tmp.n_max = n_max;
   derive(tmp);
+  if (tmp.T == 0)
+    return fail(SE_ERR_UNSUPPORTED, "support %d in this precision needs more LDS than a CU has",
+                prm->P);
   *bytes = sizes_of(*prm, n_max, tmp.ntiles, tmp.bin_blocks, tmp.zfft_blocks, tmp.T).total;
   return SE_OK;
 }
@@ -296,6 +299,11 @@ se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_p
   pl->stream = static_cast<hipStream_t>(hip_stream);
   pl->last_N = -1;
   derive(*pl);
+  if (pl->T == 0) {
+    delete pl;
+    return fail(SE_ERR_UNSUPPORTED, "support %d in this precision needs more LDS than a CU has",
+                prm->P);
+  }
   // staged tile blocks index the grid in [-(P-1), M + T + P - 3]; the kernels
   // wrap that range without division (holds for every M >= 8 with P <= M)
   if (pl->T + pl->prm.P - 3 >= 2 * pl->prm.M) {

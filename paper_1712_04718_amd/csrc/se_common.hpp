@@ -137,7 +137,7 @@ struct se_plan {
   int ntiles;      // ntx^3
   int bin_blocks;  // blocks of the binning kernel for n_max
   int zfft_blocks; // blocks of the z-pass (energy partials)
-  int fft_batch;   // pencils per FFT work-group
+  int fft_lgb[3];  // log2 pencils per FFT work-group of the x, y and z passes
   int fft_threads; // threads per FFT work-group
 
   sek::FftPlan fft;
@@ -185,13 +185,21 @@ constexpr size_t kMaxLds = 160 * 1024;
 constexpr int kGatherPotentialForce = 0;  // out_pot = phi, out_vec = F
 constexpr int kGatherAdjoint = 1;         // out_pot = gE phi, out_vec = -gE F
 
-constexpr int kThreads = 256;  // work-group size of every kernel
+constexpr int kThreads = 256;      // work-group size of the binning, fold and FFT kernels
+constexpr int kTileThreads = 512;  // work-group size of the tile spread and gather kernels
 
-// Pencils per FFT work-group, as log2: B a power of two, at most 16, with
-// M * B <= 16 * kThreads (elements per thread when loading) and two LDS
-// buffers of M x B complex plus the M twiddles within 64 KB.
-constexpr int fft_lgb(int M, int real_size) {
-  int B = 16;
+// Most pencils per FFT work-group, per pass.  The x passes read and write
+// whole rows, so fewer pencils (more work-groups in flight) pay off; the y
+// pass reads B consecutive kx per row and wants B = 16 for whole cache lines.
+enum FftPass { kPassX = 0, kPassY = 1, kPassZ = 2 };
+constexpr int kFftBatchCap[3] = {8, 16, 8};
+
+// Pencils per FFT work-group of one pass, as log2: B a power of two, at most
+// kFftBatchCap[pass], with M * B <= 16 * kThreads (elements per thread when
+// loading) and two LDS buffers of M x B complex plus the M twiddles within
+// 64 KB.
+constexpr int fft_lgb(int M, int real_size, int pass) {
+  int B = kFftBatchCap[pass];
   while (B > 1 && (M * B > 16 * kThreads || (2 * M * B + M) * 2 * real_size > 65536)) B >>= 1;
   int lg = 0;
   while ((1 << lg) < B) ++lg;

@@ -34,40 +34,105 @@ template <typename R> struct Acc;
 template <> struct Acc<float> { using T = int; };      // fixed point
 template <> struct Acc<double> { using T = double; };  // floating point
 
-// particles per phase-A round: one per thread, fewer when the factor table
-// would exceed 32 KB
+// particles per phase-A round: one per thread, fewer (down to a wave) while
+// the factor table would exceed 32 KB
 constexpr int spread_chunk(int real_size, int S) {
-  return (real_size * 3 * S * kThreads <= 32768) ? kThreads
-         : (real_size * 3 * S * (kThreads / 2) <= 32768) ? kThreads / 2 : kThreads / 4;
+  int c = kTileThreads;
+  while (c > 64 && real_size * 3 * S * c > 32768) c /= 2;
+  return c;
+}
+
+// Lanes of phase B: each particle gets PAIRS = S^2 lanes (jx, jy), pair
+// p = jy S + jx, that loop over jz; S^2 <= 32 packs 64 / S^2 particles into a
+// wave, larger S^2 takes ceil(S^2 / 64) passes of a whole wave.
+constexpr int spread_groups(int S) { return S * S <= 32 ? 64 / (S * S) : 1; }
+constexpr int spread_passes(int S) { return S * S <= 32 ? 1 : (S * S + 63) / 64; }
+
+// Whether the lanes of each pass (of the first particle group when a wave
+// holds several) fall in distinct bank slots with row stride SY: slot =
+// (jx + SY jy) mod `slots`, over the whole wave or over each 32-lane half.
+constexpr bool spread_lanes_distinct(int S, int SY, int slots, bool halves) {
+  const int lanes = S * S <= 32 ? S * S : 64;
+  for (int pass = 0; pass < spread_passes(S); ++pass) {
+    unsigned long long seen[2] = {0ull, 0ull};
+    for (int a = 0; a < lanes; ++a) {
+      const int p = pass * 64 + a;
+      if (p >= S * S) break;
+      const int slot = (p % S + SY * (p / S)) % slots;
+      const int h = (halves && a >= 32) ? 1 : 0;
+      if ((seen[h] >> slot) & 1ull) return false;
+      seen[h] |= 1ull << slot;
+    }
+  }
+  return true;
+}
+
+// Row stride (elements) of the LDS block: the smallest SY >= TS that keeps
+// the lanes of a phase-B instruction in distinct banks (64 banks of 4 bytes:
+// a 4-byte accumulator wants distinct slots mod 64 over the wave and mod 32
+// over each half; an 8-byte one covers two banks and wants distinct slots
+// mod 32 over each half), padding at most to 2 TS and only while the block
+// stays within 64 KB; else TS.
+constexpr int spread_row_stride(int S, int TS, int acc_size) {
+  const auto fits = [TS, acc_size](int sy) {
+    return static_cast<long long>(TS) * TS * sy * acc_size <= 65536;
+  };
+  if (acc_size == 4) {
+    for (int sy = TS; sy <= 2 * TS; ++sy)
+      if (fits(sy) && spread_lanes_distinct(S, sy, 64, false) && spread_lanes_distinct(S, sy, 32, true))
+        return sy;
+    for (int sy = TS; sy <= 2 * TS; ++sy)
+      if (fits(sy) && spread_lanes_distinct(S, sy, 64, false)) return sy;
+  } else {
+    for (int sy = TS; sy <= 2 * TS; ++sy)
+      if (fits(sy) && spread_lanes_distinct(S, sy, 32, true)) return sy;
+  }
+  return TS;
+}
+
+constexpr size_t spread_lds_total(int real_size, int S, int T) {
+  const int TS = T + S - 1, acc = real_size == 4 ? 4 : 8;
+  const int SY = spread_row_stride(S, TS, acc);
+  const size_t chunk = spread_chunk(real_size, S);
+  return static_cast<size_t>(acc) * ((static_cast<size_t>(TS) * TS * SY + 3) & ~static_cast<size_t>(3)) +
+         static_cast<size_t>(real_size) * chunk * 3 * S + 4 * chunk + 128;
 }
 
 template <typename R, int S, int T> struct SpreadLds {
+  using A = typename Acc<R>::T;
   static constexpr int TS = T + S - 1;
+  static constexpr int SY = spread_row_stride(S, TS, sizeof(A));  // row stride
+  static constexpr int SP = TS * SY;                               // plane stride
+  static constexpr int NBLK = TS * SP;
   static constexpr int REC = 3 * S;
   static constexpr int CHUNK = spread_chunk(sizeof(R), S);
-  static constexpr size_t BLK = sizeof(typename Acc<R>::T) * ((TS * TS * TS + 3) & ~3);
+  static constexpr size_t BLK = sizeof(A) * ((NBLK + 3) & ~3);
   static constexpr size_t FAC = sizeof(R) * CHUNK * REC;
   static constexpr size_t ANC = sizeof(int) * CHUNK;
-  static constexpr size_t TOTAL = BLK + FAC + ANC + 64;
+  static constexpr size_t TOTAL = BLK + FAC + ANC + 128;
+  static_assert(TOTAL == spread_lds_total(sizeof(R), S, T), "LDS size mismatch");
 };
 
 template <typename R, int WIN, int S, int T>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kTileThreads)
 k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ meta,
          const int *__restrict__ offsets, WindowConsts wc, double wmax, R *__restrict__ ghost) {
   using L = SpreadLds<R, S, T>;
   using A = typename Acc<R>::T;
-  constexpr int TS = L::TS, REC = L::REC, TS3 = TS * TS * TS, kChunk = L::CHUNK;
-  constexpr int GROUPS = 64 / S;
-  constexpr int NWAVES = kThreads / 64;
+  constexpr int TS = L::TS, SY = L::SY, SP = L::SP, REC = L::REC, TS3 = TS * TS * TS;
+  constexpr int kChunk = L::CHUNK;
+  constexpr int PAIRS = S * S, GROUPS = spread_groups(S), PASSES = spread_passes(S);
+  constexpr int NWAVES = kTileThreads / 64;
   constexpr bool FIXED = sizeof(R) == 4;
+  static_assert(NWAVES * 8 <= 128, "per-wave partials must fit the reduction area");
+  static_assert(kChunk <= kTileThreads, "phase A holds one particle per thread");
 
   const int tile = blockIdx.x;
   const int start = offsets[tile], end = offsets[tile + 1];
   const int tid = threadIdx.x;
   R *out = ghost + static_cast<long long>(tile) * TS3;
   if (start == end) {  // uniform across the work-group
-    for (int i = tid; i < TS3; i += kThreads) out[i] = R(0);
+    for (int i = tid; i < TS3; i += kTileThreads) out[i] = R(0);
     return;
   }
 
@@ -76,7 +141,16 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
   int *anc = reinterpret_cast<int *>(g_smem + L::BLK + L::FAC);
   double *red = reinterpret_cast<double *>(g_smem + L::BLK + L::FAC + L::ANC);
 
-  for (int i = tid; i < TS3; i += kThreads) blk[i] = A(0);
+  // The tile's first kTileThreads particles are read once, into registers;
+  // they serve the charge bound and the first round of phase A.
+  const int n = end - start;
+  SortedParticle<R> mine{};
+  int mine_anchor = 0;
+  if (tid < n) {
+    mine = sorted[start + tid];
+    mine_anchor = meta[start + tid].x;
+  }
+  for (int i = tid; i < L::NBLK; i += kTileThreads) blk[i] = A(0);
 
   // Fixed-point scale of this tile, from a bound on sum |q| that does not
   // depend on the order of the particles (the order inside a tile comes from
@@ -85,17 +159,20 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
   // exact, so qmax * sum(u) / 2^20 >= sum |q| is the same on every run.
   double scale = 1.0, inv_scale = 1.0;
   if constexpr (FIXED) {
-    double m = 0.0;
-    for (int p = start + tid; p < end; p += kThreads) m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
+    double m = tid < n ? fabs(static_cast<double>(mine.q)) : 0.0;
+    for (int p = start + kTileThreads + tid; p < end; p += kTileThreads)
+      m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
     if ((tid & 63) == 0) red[tid >> 6] = m;
     __syncthreads();
     double qmax = 0.0;
     for (int w = 0; w < NWAVES; ++w) qmax = fmax(qmax, red[w]);
     long long u = 0;
-    if (qmax > 0.0)
-      for (int p = start + tid; p < end; p += kThreads)
+    if (qmax > 0.0) {
+      if (tid < n) u = static_cast<long long>(ceil(fabs(static_cast<double>(mine.q)) / qmax * 1048576.0));
+      for (int p = start + kTileThreads + tid; p < end; p += kTileThreads)
         u += static_cast<long long>(ceil(fabs(static_cast<double>(sorted[p].q)) / qmax * 1048576.0));
+    }
     for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
     __syncthreads();  // every wave has read red[]
     long long *ured = reinterpret_cast<long long *>(red);
@@ -110,14 +187,34 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
     }
   }
 
+  // this lane's (jx, jy) in each pass, as an LDS offset, and its group
   const int wave = tid >> 6, lane = tid & 63;
-  const int grp = lane / S, jx = lane - grp * S;
+  const int grp = GROUPS > 1 ? lane / PAIRS : 0;
+  int loff[PASSES], lx[PASSES], ly[PASSES];
+  bool lon[PASSES];
+#pragma unroll
+  for (int ps = 0; ps < PASSES; ++ps) {
+    const int pp = ps * 64 + (GROUPS > 1 ? lane - grp * PAIRS : lane);
+    lon[ps] = grp < GROUPS && pp < PAIRS;
+    ly[ps] = lon[ps] ? pp / S : 0;
+    lx[ps] = lon[ps] ? pp - ly[ps] * S : 0;
+    loff[ps] = ly[ps] * SY + lx[ps];
+  }
+
   for (int base = start; base < end; base += kChunk) {
     const int nval = min(kChunk, end - base);
     __syncthreads();  // previous round done with fac / anc; blk zeroed
-    // phase A: factors of particle base + tid
+    // phase A: factors of particle base + tid (charge and scale in the x factors)
     if (tid < nval) {
-      const SortedParticle<R> sp = sorted[base + tid];
+      SortedParticle<R> sp;
+      int a;
+      if (base == start) {
+        sp = mine;
+        a = mine_anchor;
+      } else {
+        sp = sorted[base + tid];
+        a = meta[base + tid].x;
+      }
       R g[S], unused[S];
       R *f = fac + tid * REC;
       const R qs = static_cast<R>(static_cast<double>(sp.q) * scale);
@@ -130,43 +227,42 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
       window_axis<R, WIN, S, false>(sp.dz, wc, g, unused);
 #pragma unroll
       for (int j = 0; j < S; ++j) f[2 * S + j] = g[j];
-      anc[tid] = meta[base + tid].x;
+      anc[tid] = a;
     }
     __syncthreads();
-    // phase B
-    if (grp < GROUPS) {
-      for (int c = wave * GROUPS + grp; c < nval; c += NWAVES * GROUPS) {
-        const R *f = fac + c * REC;
-        const int packed = anc[c];
-        const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
-        const R wq = f[jx];
-        R gy[S], gz[S];
+    // phase B: lane (jx, jy) of a particle adds its S products along z
+    for (int c = wave * GROUPS + grp; c < nval; c += NWAVES * GROUPS) {
+      const R *f = fac + c * REC;
+      const int packed = anc[c];
+      const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
+      A *corner = blk + az * SP + ay * SY + ax;
+      R gz[S];
 #pragma unroll
-        for (int j = 0; j < S; ++j) {
-          gy[j] = f[S + j];
-          gz[j] = f[2 * S + j];
-        }
-        A *row = blk + (az * TS + ay) * TS + ax + jx;
+      for (int j = 0; j < S; ++j) gz[j] = f[2 * S + j];
+#pragma unroll
+      for (int ps = 0; ps < PASSES; ++ps) {
+        if (!lon[ps]) continue;
+        const R wxy = f[lx[ps]] * f[S + ly[ps]];
+        A *col = corner + loff[ps];
 #pragma unroll
         for (int jz = 0; jz < S; ++jz) {
-          const R wz = wq * gz[jz];
-#pragma unroll
-          for (int jy = 0; jy < S; ++jy) {
-            if constexpr (FIXED)
-              atomicAdd(row + (jz * TS + jy) * TS, __float2int_rn(wz * gy[jy]));
-            else
-              unsafeAtomicAdd(row + (jz * TS + jy) * TS, wz * gy[jy]);
-          }
+          if constexpr (FIXED)
+            atomicAdd(col + jz * SP, __float2int_rn(wxy * gz[jz]));
+          else
+            unsafeAtomicAdd(col + jz * SP, wxy * gz[jz]);
         }
       }
     }
   }
   __syncthreads();
-  for (int i = tid; i < TS3; i += kThreads) {
+  for (int i = tid; i < TS3; i += kTileThreads) {
+    const int z = i / (TS * TS), rem = i - z * (TS * TS);
+    const int y = rem / TS, x = rem - y * TS;
+    const A v = blk[z * SP + y * SY + x];
     if constexpr (FIXED)
-      out[i] = static_cast<R>(static_cast<double>(blk[i]) * inv_scale);
+      out[i] = static_cast<R>(static_cast<double>(v) * inv_scale);
     else
-      out[i] = blk[i];
+      out[i] = v;
   }
 }
 
@@ -204,54 +300,51 @@ k_fold(const R *__restrict__ ghost, FoldTables ft, int M, R *__restrict__ grid) 
 }
 
 // Tiles partition the grid (M = ntx T) and no block wraps onto itself
-// (T + S - 1 <= M): work-group t writes the T^3 points starting at t T + OFF.
+// (T + S - 1 <= M): tile t owns the T^3 points starting at t T + OFF.
 // Along each axis a point with local index l gets block t at l, block t-1 at
 // l + T, block t-2 at l + 2T, while the local index stays inside the block.
-// Every candidate is loaded (clamped to a valid address) before any is used,
-// so the loads overlap; consecutive threads read consecutive x.
+// One thread per owned point (the tile's points are spread over gridDim.y
+// work-groups); only the candidates inside a block are loaded, and all of
+// them are issued before the first is used.
 template <typename R, int WIN, int S, int T>
 __global__ void __launch_bounds__(kThreads)
 k_fold_tiles(const R *__restrict__ ghost, int M, int ntx, R *__restrict__ grid) {
   constexpr int TS = T + S - 1, TS3 = TS * TS * TS, T3 = T * T * T;
   constexpr int MAXK = (TS + T - 1) / T;
   constexpr int OFF = Stencil<WIN, S>::OFF;
+  const int i = static_cast<int>(blockIdx.y) * kThreads + static_cast<int>(threadIdx.x);
+  if (i >= T3) return;
   const int tile = blockIdx.x;
   const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
-  int sz[MAXK], sy[MAXK], sx[MAXK];
+  const int lz = i / (T * T), ly = (i / T) % T, lx = i % T;
+  R v[MAXK][MAXK][MAXK];
 #pragma unroll
-  for (int k = 0; k < MAXK; ++k) {
-    sz[k] = tz - k + (tz < k ? ntx : 0);
-    sy[k] = ty - k + (ty < k ? ntx : 0);
-    sx[k] = tx - k + (tx < k ? ntx : 0);
-  }
-  for (int i = threadIdx.x; i < T3; i += kThreads) {
-    const int lz = i / (T * T), ly = (i / T) % T, lx = i % T;
-    R v[MAXK][MAXK][MAXK];
+  for (int kz = 0; kz < MAXK; ++kz)
 #pragma unroll
-    for (int kz = 0; kz < MAXK; ++kz)
+    for (int ky = 0; ky < MAXK; ++ky)
 #pragma unroll
-      for (int ky = 0; ky < MAXK; ++ky)
-#pragma unroll
-        for (int kx = 0; kx < MAXK; ++kx) {
-          const int cz = min(lz + kz * T, TS - 1), cy = min(ly + ky * T, TS - 1);
-          const int cx = min(lx + kx * T, TS - 1);
-          v[kz][ky][kx] = ghost[static_cast<long long>((sz[kz] * ntx + sy[ky]) * ntx + sx[kx]) * TS3 +
+      for (int kx = 0; kx < MAXK; ++kx) {
+        v[kz][ky][kx] = R(0);
+        const int cz = lz + kz * T, cy = ly + ky * T, cx = lx + kx * T;
+        if (cz < TS && cy < TS && cx < TS) {
+          const int sz = tz - kz + (tz < kz ? ntx : 0), sy = ty - ky + (ty < ky ? ntx : 0);
+          const int sx = tx - kx + (tx < kx ? ntx : 0);
+          v[kz][ky][kx] = ghost[static_cast<long long>((sz * ntx + sy) * ntx + sx) * TS3 +
                                 (cz * TS + cy) * TS + cx];
         }
-    R s = R(0);
+      }
+  R s = R(0);
 #pragma unroll
-    for (int kz = 0; kz < MAXK; ++kz)
+  for (int kz = 0; kz < MAXK; ++kz)
 #pragma unroll
-      for (int ky = 0; ky < MAXK; ++ky)
+    for (int ky = 0; ky < MAXK; ++ky)
 #pragma unroll
-        for (int kx = 0; kx < MAXK; ++kx)
-          if (lz + kz * T < TS && ly + ky * T < TS && lx + kx * T < TS) s += v[kz][ky][kx];
-    int gz = tz * T + OFF + lz, gy = ty * T + OFF + ly, gx = tx * T + OFF + lx;
-    gz += gz < 0 ? M : 0;
-    gy += gy < 0 ? M : 0;
-    gx += gx < 0 ? M : 0;
-    grid[(static_cast<long long>(gz) * M + gy) * M + gx] = s;
-  }
+      for (int kx = 0; kx < MAXK; ++kx) s += v[kz][ky][kx];
+  int gz = tz * T + OFF + lz, gy = ty * T + OFF + ly, gx = tx * T + OFF + lx;
+  gz += gz < 0 ? M : 0;
+  gy += gy < 0 ? M : 0;
+  gx += gx < 0 ? M : 0;
+  grid[(static_cast<long long>(gz) * M + gy) * M + gx] = s;
 }
 
 template <typename R, int WIN, int S, int T>
@@ -266,7 +359,7 @@ hipError_t spread_one(se_plan &p) {
     if (e != hipSuccess) return e;
   }
   stage_begin(p, SE_STAGE_SPREAD);
-  k_spread<R, WIN, S, T><<<p.ntiles, kThreads, lds, p.stream>>>(
+  k_spread<R, WIN, S, T><<<p.ntiles, kTileThreads, lds, p.stream>>>(
       static_cast<const SortedParticle<R> *>(p.buf.sorted), p.buf.meta, p.buf.offsets, wc, wmax,
       static_cast<R *>(p.buf.ghost));
   stage_end(p, SE_STAGE_SPREAD);
@@ -275,7 +368,8 @@ hipError_t spread_one(se_plan &p) {
   const int M = p.prm.M;
   stage_begin(p, SE_STAGE_FOLD);
   if (p.fold_by_tiles) {
-    k_fold_tiles<R, WIN, S, T><<<p.ntiles, kThreads, 0, p.stream>>>(
+    const dim3 fg(p.ntiles, (T * T * T + kThreads - 1) / kThreads);
+    k_fold_tiles<R, WIN, S, T><<<fg, kThreads, 0, p.stream>>>(
         static_cast<const R *>(p.buf.ghost), M, p.ntx, static_cast<R *>(p.buf.grid));
   } else {
     const long long ngrid = static_cast<long long>(M) * M * M;
@@ -317,13 +411,7 @@ hipError_t spread_dispatch(se_plan &p) {
 
 }  // namespace
 
-size_t spread_lds_bytes(int real_size, int S, int T) {
-  const size_t ts = T + S - 1;
-  const size_t acc = real_size == 4 ? 4 : 8;
-  const size_t chunk = spread_chunk(real_size, S);
-  return acc * ((ts * ts * ts + 3) & ~static_cast<size_t>(3)) +
-         static_cast<size_t>(real_size) * chunk * 3 * S + 4 * chunk + 64;
-}
+size_t spread_lds_bytes(int real_size, int S, int T) { return spread_lds_total(real_size, S, T); }
 
 hipError_t launch_spread(se_plan &plan) {
   return plan.prm.dtype == SE_FP64 ? spread_dispatch<double>(plan)

@@ -34,16 +34,6 @@ template <int WIN, int S> struct Stencil {
   static constexpr int OFF = (WIN == kGauss) ? -(S / 2 - 1) : -(S - 1);
 };
 
-// Particles per wave and round in the spreading/gathering kernels: a
-// multiple of the 64/S particle groups of a wave, about 32, at most 64 (one
-// lane per particle while computing factors).
-template <int S> struct Chunk {
-  static constexpr int GROUPS = 64 / S;
-  static constexpr int ROUNDS = (32 + GROUPS - 1) / GROUPS;
-  static constexpr int CH = GROUPS * ROUNDS;
-  static_assert(CH <= 64, "chunk larger than a wave");
-};
-
 struct WindowConsts {
   double cg;     // Gaussian exponent in grid units (SE)
   double beta;   // per-axis Gaussian normalisation (SE)
