@@ -39,6 +39,7 @@ KERNEL_SOURCES = {
     "spread": ("spread.hip", "window.hpp", "se_common.hpp"),
     "fold": ("spread.hip", "se_common.hpp"),
     "bin_count": ("bin.hip", "se_common.hpp"),
+    "bin_scan": ("bin.hip", "se_common.hpp"),
     "bin_scatter": ("bin.hip", "se_common.hpp"),
 }
 for _st in ("fft_x", "fft_y", "fft_z_scale", "ifft_y", "ifft_x"):
@@ -47,7 +48,8 @@ for _st in ("fft_x", "fft_y", "fft_z_scale", "ifft_y", "ifft_x"):
 
 # kernel names of each stage in a rocprofv3 trace (FP32 instantiations)
 STAGE_KERNEL_RE = {
-    "bin_count": r"k_bin_count<float>", "bin_scatter": r"k_bin_scatter<float>",
+    "bin_count": r"k_bin_count_(lds|run)<float", "bin_scan": r"k_bin_scan",
+    "bin_scatter": r"k_bin_scatter<float>",
     "spread": r"k_spread<float,", "fold": r"k_fold(_tiles)?<float",
     "fft_x": r"k_fft_x_r2c<float,", "fft_y": r"k_fft_y<float, -?\d+, \d+, false>",
     "fft_z_scale": r"k_fft_z_scale<float,", "ifft_y": r"k_fft_y<float, -?\d+, \d+, true>",
@@ -83,8 +85,11 @@ def kernel_work(stage, N, M, P, rs, window):
     K = M // 2 + 1
     grid, spec = M ** 3 * rs, M * M * K * 2 * rs
     T = tile_edge(M, P, window, rs)
+    ntiles = ((M + T - 1) // T) ** 3
     if stage == "bin_count":
         return "bytes", N * 4 * rs + N * 8                  # x, q in; keys out
+    if stage == "bin_scan":
+        return "bytes", ntiles * 12                        # counts in and reset; offsets out
     if stage == "bin_scatter":
         return "bytes", N * 4 * rs + N * 8 + N * (4 * rs + 8)  # x, q, keys in; sorted, meta out
     if stage == "spread":

@@ -73,7 +73,8 @@ typedef enum { SE_FP32 = 0, SE_FP64 = 1 } se_dtype;
 
 /* Kernel stages of one evaluation, in launch order (se_plan_stage_times). */
 enum {
-    SE_STAGE_BIN_COUNT = 0,  /* zero grid, tile histogram, tile offsets       */
+    SE_STAGE_BIN_COUNT = 0,  /* tile of each particle, its rank in the tile  */
+    SE_STAGE_BIN_SCAN,       /* tile offsets (exclusive scan of the counts)  */
     SE_STAGE_BIN_SCATTER,    /* write particles in tile order                */
     SE_STAGE_SPREAD,         /* step 2 (tile blocks)                          */
     SE_STAGE_FOLD,           /* step 2, tile blocks summed into the grid      */

@@ -18,8 +18,8 @@ SE_FP32 = 0
 SE_FP64 = 1
 SE_FLAG_ADD_SELF = 1
 SE_FLAG_TIMING = 2
-STAGES = ("bin_count", "bin_scatter", "spread", "fold", "fft_x", "fft_y", "fft_z_scale",
-          "ifft_y", "ifft_x", "gather")
+STAGES = ("bin_count", "bin_scan", "bin_scatter", "spread", "fold", "fft_x", "fft_y",
+          "fft_z_scale", "ifft_y", "ifft_x", "gather")
 
 STATUS_NAMES = {
     0: "SE_OK", 1: "SE_ERR_ARG", 2: "SE_ERR_GRID", 3: "SE_ERR_ETA",

@@ -6,16 +6,29 @@
 // tile touch one (T+S-1)^3 block of the grid.  Spreading and gathering then
 // run one work-group per tile with that block staged in LDS.
 //
-// k_bin_count: each particle's tile and its rank inside the tile (atomic
-//   counter), and per-block sums of q^2;
+// Counting: each particle gets its tile and its rank among the particles of
+// that tile from an atomic add on the tile's counter (one cache line per
+// counter).  Returning global atomics are the cost here, so they are
+// aggregated:
+//   k_bin_count_lds: a work-group takes 256 PPT particles, ranks them per
+//     tile with LDS atomics, then adds each touched tile's count to the
+//     global counter once and hands the returned base to its particles;
+//     PPT = 8 when tiles hold many particles (far fewer global atomics),
+//     PPT = 1 otherwise;
+//   k_bin_count_run: for grids with more tiles than the LDS tables hold,
+//     one atomic per run of equal tiles among neighbouring lanes of a wave
+//     (the atoms of a molecule are usually adjacent in the input).
+// Both also write per-block sums of q^2 (for the self energy).
 // k_bin_scan: one work-group turns the tile counts into offsets (exclusive
-//   scan), resets the counts for the next call and totals q^2;
+//   scan) and resets the counts for the next call;
 // k_bin_scatter: write the particles in tile order as (offsets from the
 //   anchor in grid units, q) plus (packed local anchor, original index).
 #include "se_common.hpp"
 
 namespace sek {
 namespace {
+
+constexpr int kLdsTilesMax = 8192;  // tiles the LDS tables of k_bin_count_lds hold
 
 __device__ inline long long floor_div_mod(double u, int M, double *frac) {
   double fl = floor(u);
@@ -24,26 +37,116 @@ __device__ inline long long floor_div_mod(double u, int M, double *frac) {
   return i < 0 ? i + M : i;
 }
 
+// Tile of a particle at (x0, x1, x2).
+template <typename R>
+__device__ inline int tile_of(R x0, R x1, R x2, double h, int M, int T, int ntx) {
+  double frac;
+  const int ax = static_cast<int>(floor_div_mod(static_cast<double>(x0) / h, M, &frac));
+  const int ay = static_cast<int>(floor_div_mod(static_cast<double>(x1) / h, M, &frac));
+  const int az = static_cast<int>(floor_div_mod(static_cast<double>(x2) / h, M, &frac));
+  return ((az / T) * ntx + ay / T) * ntx + ax / T;
+}
+
+// Tile of particle n (and q_n^2).
+template <typename R>
+__device__ inline int particle_tile(const R *__restrict__ x, const R *__restrict__ q, int n,
+                                    double h, int M, int T, int ntx, double *qq) {
+  const double qn = static_cast<double>(q[n]);
+  *qq = qn * qn;
+  return tile_of(x[3 * n + 0], x[3 * n + 1], x[3 * n + 2], h, M, T, ntx);
+}
+
+// Sum of a per-thread double over the work-group, written by thread 0.
+__device__ inline void block_sum_to(double v, double *out) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __shared__ double red[kThreads / 64];
+  const int tid = threadIdx.x;
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    *out = s;
+  }
+}
+
+template <typename R, int PPT>
+__global__ void __launch_bounds__(kThreads)
+k_bin_count_lds(int N, const R *__restrict__ x, const R *__restrict__ q, double h, int M,
+                int T, int ntx, int ntiles, int *__restrict__ counts, int2 *__restrict__ key,
+                double *__restrict__ qsq_part) {
+  extern __shared__ int lds_tiles[];
+  int *lcnt = lds_tiles, *lbase = lds_tiles + ntiles;
+  const int tid = threadIdx.x;
+  const int n0 = blockIdx.x * (kThreads * PPT);
+  for (int t = tid; t < ntiles; t += kThreads) lcnt[t] = 0;
+  // all PPT particles are read before the first is used (the index is
+  // clamped into [0, N), N >= 1, so the loads need no branch)
+  R px[PPT][3], pq[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int nc = min(n0 + k * kThreads + tid, N - 1);  // consecutive threads, consecutive particles
+    px[k][0] = x[3 * nc + 0];
+    px[k][1] = x[3 * nc + 1];
+    px[k][2] = x[3 * nc + 2];
+    pq[k] = q[nc];
+  }
+  int tile[PPT], rank[PPT];
+  double qq = 0.0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int n = n0 + k * kThreads + tid;
+    tile[k] = -1;
+    rank[k] = 0;
+    if (n < N) {
+      tile[k] = tile_of(px[k][0], px[k][1], px[k][2], h, M, T, ntx);
+      qq += static_cast<double>(pq[k]) * static_cast<double>(pq[k]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PPT; ++k)
+    if (tile[k] >= 0) rank[k] = atomicAdd(&lcnt[tile[k]], 1);
+  __syncthreads();
+  // one global atomic per touched tile; a thread issues a batch of them
+  // before it needs any of the returned bases
+  constexpr int kAtomicBatch = 8;
+  for (int t0 = tid; t0 < ntiles; t0 += kThreads * kAtomicBatch) {
+    int c[kAtomicBatch], b[kAtomicBatch];
+#pragma unroll
+    for (int k = 0; k < kAtomicBatch; ++k) {
+      const int t = t0 + k * kThreads;
+      c[k] = t < ntiles ? lcnt[t] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kAtomicBatch; ++k)
+      b[k] = c[k] > 0 ? atomicAdd(&counts[(t0 + k * kThreads) * kCountStride], c[k]) : 0;
+#pragma unroll
+    for (int k = 0; k < kAtomicBatch; ++k) {
+      const int t = t0 + k * kThreads;
+      if (t < ntiles) lbase[t] = b[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int n = n0 + k * kThreads + tid;
+    if (tile[k] >= 0) key[n] = make_int2(tile[k], lbase[tile[k]] + rank[k]);
+  }
+  block_sum_to(qq, &qsq_part[blockIdx.x]);
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kThreads)
-k_bin_count(int N, const R *__restrict__ x, const R *__restrict__ q, double h, int M, int T,
-            int ntx, int *__restrict__ counts, int2 *__restrict__ key,
-            double *__restrict__ qsq_part) {
+k_bin_count_run(int N, const R *__restrict__ x, const R *__restrict__ q, double h, int M, int T,
+                int ntx, int *__restrict__ counts, int2 *__restrict__ key,
+                double *__restrict__ qsq_part) {
   const int tid = threadIdx.x;
-  const int n = blockIdx.x * blockDim.x + tid;
+  const int n = blockIdx.x * kThreads + tid;
   double qq = 0.0;
   int tile = -1;
-  if (n < N) {
-    double frac;
-    const int ax = static_cast<int>(floor_div_mod(static_cast<double>(x[3 * n + 0]) / h, M, &frac));
-    const int ay = static_cast<int>(floor_div_mod(static_cast<double>(x[3 * n + 1]) / h, M, &frac));
-    const int az = static_cast<int>(floor_div_mod(static_cast<double>(x[3 * n + 2]) / h, M, &frac));
-    tile = ((az / T) * ntx + ay / T) * ntx + ax / T;
-    const double qn = static_cast<double>(q[n]);
-    qq = qn * qn;
-  }
-  // Runs of equal tiles among neighbouring lanes (the atoms of a molecule are
-  // usually adjacent in the input) take one atomic per run.
+  if (n < N) tile = particle_tile(x, q, n, h, M, T, ntx, &qq);
+  // one atomic per run of equal tiles among neighbouring lanes
   const int lane = tid & 63;
   const int prev = __shfl_up(tile, 1);
   const bool head = lane == 0 || tile != prev;
@@ -56,55 +159,46 @@ k_bin_count(int N, const R *__restrict__ x, const R *__restrict__ q, double h, i
   if (head && tile >= 0) base = atomicAdd(&counts[tile * kCountStride], run_end - lane);
   base = __shfl(base, run0);
   if (tile >= 0) key[n] = make_int2(tile, base + lane - run0);
-  for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o);
-  __shared__ double red[kThreads / 64];
-  if ((tid & 63) == 0) red[tid >> 6] = qq;
-  __syncthreads();
-  if (tid == 0) {
-    double s = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
-    qsq_part[blockIdx.x] = s;
-  }
+  block_sum_to(qq, &qsq_part[blockIdx.x]);
 }
 
-// One work-group: exclusive scan of the tile counts into offsets, counts reset
-// for the next call, and the total of q^2 (fixed order, deterministic).
-__global__ void __launch_bounds__(kThreads)
-k_bin_scan(int *__restrict__ counts, int *__restrict__ offsets, int ntiles,
-           const double *__restrict__ qsq_part, int nparts, double *__restrict__ qsq_total) {
+// One work-group: exclusive scan of the tile counts into offsets, and the
+// counts reset for the next call.  Each thread requests its whole chunk of
+// counts before using any.
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 32;  // counts per thread held in registers
+__global__ void __launch_bounds__(kScanThreads)
+k_bin_scan(int *__restrict__ counts, int *__restrict__ offsets, int ntiles) {
   const int tid = threadIdx.x;
-  const int chunk = (ntiles + kThreads - 1) / kThreads;
+  const int chunk = (ntiles + kScanThreads - 1) / kScanThreads;
   const int lo = min(tid * chunk, ntiles), hi = min(lo + chunk, ntiles);
+  int v[kScanPer];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) v[k] = (lo + k < hi) ? counts[(lo + k) * kCountStride] : 0;
   int local = 0;
-  for (int t = lo; t < hi; ++t) local += counts[t * kCountStride];
-  __shared__ int scan[kThreads];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) local += v[k];
+  for (int t = lo + kScanPer; t < hi; ++t) local += counts[t * kCountStride];  // > 32K tiles
+  __shared__ int scan[kScanThreads];
   scan[tid] = local;
   __syncthreads();
-  for (int s = 1; s < kThreads; s <<= 1) {  // inclusive Hillis-Steele scan
-    const int v = tid >= s ? scan[tid - s] : 0;
+  for (int s = 1; s < kScanThreads; s <<= 1) {  // inclusive Hillis-Steele scan
+    const int u = tid >= s ? scan[tid - s] : 0;
     __syncthreads();
-    scan[tid] += v;
+    scan[tid] += u;
     __syncthreads();
   }
   int run = scan[tid] - local;
-  for (int t = lo; t < hi; ++t) {
-    const int c = counts[t * kCountStride];
+  const auto emit = [&](int t, int c) {
     offsets[t] = run;
     run += c;
     counts[t * kCountStride] = 0;
-  }
-  if (tid == kThreads - 1) offsets[ntiles] = scan[kThreads - 1];
-
-  __shared__ double red[kThreads];
-  double s = 0.0;
-  for (int b = tid; b < nparts; b += kThreads) s += qsq_part[b];
-  red[tid] = s;
-  __syncthreads();
-  for (int st = kThreads / 2; st > 0; st >>= 1) {
-    if (tid < st) red[tid] += red[tid + st];
-    __syncthreads();
-  }
-  if (tid == 0) *qsq_total = red[0];
+  };
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k)
+    if (lo + k < hi) emit(lo + k, v[k]);
+  for (int t = lo + kScanPer; t < hi; ++t) emit(t, counts[t * kCountStride]);
+  if (tid == kScanThreads - 1) offsets[ntiles] = scan[kScanThreads - 1];
 }
 
 template <typename R>
@@ -133,27 +227,41 @@ k_bin_scatter(int N, const R *__restrict__ x, const R *__restrict__ q, double h,
 template <typename R>
 hipError_t bin_impl(se_plan &p, int N, const void *x, const void *q) {
   const int M = p.prm.M;
-  const int blocks = N > 0 ? (N + kThreads - 1) / kThreads : 0;
+  const R *xr = static_cast<const R *>(x), *qr = static_cast<const R *>(q);
+  const int blocks1 = N > 0 ? (N + kThreads - 1) / kThreads : 0;
   hipError_t e = hipSuccess;
   stage_begin(p, SE_STAGE_BIN_COUNT);
-  if (blocks > 0) {
-    k_bin_count<R><<<blocks, kThreads, 0, p.stream>>>(
-        N, static_cast<const R *>(x), static_cast<const R *>(q), p.h, M, p.T, p.ntx,
-        p.buf.counts, p.buf.key, p.buf.part);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) {
-    k_bin_scan<<<1, kThreads, 0, p.stream>>>(p.buf.counts, p.buf.offsets, p.ntiles, p.buf.part,
-                                           blocks, p.buf.qsq);
+  p.bin_parts = 0;  // q^2 partials written by this call (count work-groups)
+  if (N > 0) {
+    if (p.ntiles <= kLdsTilesMax) {
+      const size_t lds = sizeof(int) * 2 * static_cast<size_t>(p.ntiles);
+      if (static_cast<long long>(N) >= 256LL * p.ntiles) {
+        constexpr int PPT = 8;
+        p.bin_parts = (N + kThreads * PPT - 1) / (kThreads * PPT);
+        k_bin_count_lds<R, PPT><<<p.bin_parts, kThreads, lds, p.stream>>>(
+            N, xr, qr, p.h, M, p.T, p.ntx, p.ntiles, p.buf.counts, p.buf.key, p.buf.part);
+      } else {
+        p.bin_parts = blocks1;
+        k_bin_count_lds<R, 1><<<p.bin_parts, kThreads, lds, p.stream>>>(
+            N, xr, qr, p.h, M, p.T, p.ntx, p.ntiles, p.buf.counts, p.buf.key, p.buf.part);
+      }
+    } else {
+      p.bin_parts = blocks1;
+      k_bin_count_run<R><<<p.bin_parts, kThreads, 0, p.stream>>>(
+          N, xr, qr, p.h, M, p.T, p.ntx, p.buf.counts, p.buf.key, p.buf.part);
+    }
     e = hipGetLastError();
   }
   stage_end(p, SE_STAGE_BIN_COUNT);
-  if (e != hipSuccess || N == 0) return e;
+  if (e != hipSuccess) return e;
+  stage_begin(p, SE_STAGE_BIN_SCAN);
+  k_bin_scan<<<1, kScanThreads, 0, p.stream>>>(p.buf.counts, p.buf.offsets, p.ntiles);
+  stage_end(p, SE_STAGE_BIN_SCAN);
+  if ((e = hipGetLastError()) != hipSuccess || N == 0) return e;
   stage_begin(p, SE_STAGE_BIN_SCATTER);
-  k_bin_scatter<R><<<blocks, kThreads, 0, p.stream>>>(
-      N, static_cast<const R *>(x), static_cast<const R *>(q), p.h, M, p.T,
-      p.buf.key, p.buf.offsets, static_cast<SortedParticle<R> *>(p.buf.sorted),
-      p.buf.meta);
+  k_bin_scatter<R><<<blocks1, kThreads, 0, p.stream>>>(
+      N, xr, qr, p.h, M, p.T, p.buf.key, p.buf.offsets,
+      static_cast<SortedParticle<R> *>(p.buf.sorted), p.buf.meta);
   stage_end(p, SE_STAGE_BIN_SCATTER);
   return hipGetLastError();
 }

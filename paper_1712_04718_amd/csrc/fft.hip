@@ -1,12 +1,13 @@
 // Steps 3-5 of Algorithm 1: forward 3D FFT of the real grid, multiplication
 // by the influence function with the k-space energy, inverse 3D FFT.
 //
-// Five passes over a half spectrum C[z][y][kx], kx = 0..M/2 (row length
-// K = M/2 + 1), all built on one batched Stockham FFT held in LDS:
+// Five passes over a half spectrum stored as C[z][kx][y], kx = 0..M/2
+// (K = M/2 + 1 values), y contiguous, all built on one batched Stockham FFT
+// held in LDS:
 //   x_r2c : pairs of real rows packed as one complex row, transformed, and
-//           split into two half spectra;
-//   y_fwd : FFT along y of B adjacent kx columns of one z-plane;
-//   z     : FFT along z of B adjacent (y,kx) pencils, scale by the
+//           split into two half spectra, written as runs along y;
+//   y_fwd : FFT of B contiguous y pencils (consecutive (z, kx));
+//   z     : FFT along z of B adjacent (kx, ky) pencils, scale by the
 //           influence function w(k) (eq. 4.6 for SE, eq. 6.2 for SPME)
 //           times 4 pi / L^3, accumulate the energy
 //             E = 1/2 sum_k mu(kx) w(k) |G^(k)|^2   (FP64),
@@ -42,6 +43,11 @@ template <typename C> __device__ inline C cmul(C a, C b) {
 template <typename C> __device__ inline C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
 template <typename C> __device__ inline C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
 template <typename C> __device__ inline C cconj(C a) { a.y = -a.y; return a; }
+// Two adjacent complex values, moved as one 16- or 32-byte access.
+template <typename R> struct alignas(4 * sizeof(R)) C2 {
+  cplx_t<R> a, b;
+};
+
 // multiply by -i
 template <typename C> __device__ inline C cmul_mi(C a) { C r; r.x = a.y; r.y = -a.x; return r; }
 
@@ -235,15 +241,11 @@ __device__ inline cplx_t<R> *fft_any(cplx_t<R> *buf0, cplx_t<R> *buf1, int lgB, 
     return fft_batch<R>(buf0, buf1, lgB, pl, tw);
 }
 
-// i / M and i / (M/2+1): constant divisors when M is known at compile time,
-// else the plan's magic multipliers.
+// i / M: a constant divisor when M is known at compile time, else the
+// plan's magic multiplier.
 template <int MC> __device__ inline int div_M(int i, const FftPlan &pl) {
   if constexpr (MC > 0) return i / MC;
   else return fast_div(i, pl.m_magic);
-}
-template <int MC> __device__ inline int div_K(int i, const FftPlan &pl) {
-  if constexpr (MC > 0) return i / (MC / 2 + 1);
-  else return fast_div(i, pl.k_magic);
 }
 
 // ---------------------------------------------------------------- x passes
@@ -261,7 +263,7 @@ k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl
   C *twl = b1 + M * B;  // twiddles staged in LDS
   for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
   const long long nrows = static_cast<long long>(M) * M;
-  const long long row0 = static_cast<long long>(blockIdx.x) * 2 * B;
+  const long long row0 = static_cast<long long>(xcd_local(blockIdx.x, gridDim.x)) * 2 * B;
   // row r of the batch goes to pencil r/2, real part for even r, imag for odd;
   // all loads are issued before the first LDS store
   R v[2 * kMaxPerThread];
@@ -281,20 +283,22 @@ k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl
   }
   __syncthreads();
   const C *Z = fft_any<R, MC, LGBC>(b0, b1, lgb, pl, twl);
-  // Z = FFT(r1 + i r2): R1[k] = (Z[k] + conj Z[M-k]) / 2, R2[k] = (Z[k] - conj Z[M-k]) / 2i
+  // Z = FFT(r1 + i r2): R1[k] = (Z[k] + conj Z[M-k]) / 2, R2[k] = (Z[k] - conj Z[M-k]) / 2i.
+  // Rows 2b and 2b+1 are (z, y) and (z, y+1) with y even (M is even), so the
+  // two half spectra land side by side in C[z][k][y]: one 2-element store.
   for (int i = threadIdx.x; i < B * K; i += kThreads) {
-    const int b = div_K<MC>(i, pl), k = i - b * K;
+    const int k = i >> lgb, b = i & (B - 1);
     const long long gr = row0 + 2 * b;
     if (gr >= nrows) continue;
     const C zk = Z[k * B + b];
     const C zm = Z[(k == 0 ? 0 : M - k) * B + b];
-    C r1, r2;
-    r1.x = R(0.5) * (zk.x + zm.x);
-    r1.y = R(0.5) * (zk.y - zm.y);
-    r2.x = R(0.5) * (zk.y + zm.y);
-    r2.y = R(-0.5) * (zk.x - zm.x);
-    spec[gr * K + k] = r1;
-    spec[(gr + 1) * K + k] = r2;
+    C2<R> r;
+    r.a.x = R(0.5) * (zk.x + zm.x);
+    r.a.y = R(0.5) * (zk.y - zm.y);
+    r.b.x = R(0.5) * (zk.y + zm.y);
+    r.b.y = R(-0.5) * (zk.x - zm.x);
+    const int z = div_M<MC>(static_cast<int>(gr), pl), y = static_cast<int>(gr) - z * M;
+    *reinterpret_cast<C2<R> *>(&spec[(static_cast<long long>(z) * K + k) * M + y]) = r;
   }
 }
 
@@ -311,16 +315,19 @@ k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl
   C *twl = b1 + M * B;  // twiddles staged in LDS
   for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
   const long long nrows = static_cast<long long>(M) * M;
-  const long long row0 = static_cast<long long>(blockIdx.x) * 2 * B;
+  const long long row0 = static_cast<long long>(xcd_local(blockIdx.x, gridDim.x)) * 2 * B;
   // Z[k] = R1[k] + i R2[k] on 0..M/2 and conj(R1[M-k]) + i conj(R2[M-k]) above;
   // stored conjugated for the inverse transform.
   for (int i = threadIdx.x; i < B * K; i += kThreads) {
-    const int b = div_K<MC>(i, pl), k = i - b * K;
+    const int k = i >> lgb, b = i & (B - 1);
     const long long gr = row0 + 2 * b;
     C r1, r2;
     if (gr < nrows) {
-      r1 = spec[gr * K + k];
-      r2 = spec[(gr + 1) * K + k];
+      const int z = div_M<MC>(static_cast<int>(gr), pl), y = static_cast<int>(gr) - z * M;
+      const C2<R> r =
+          *reinterpret_cast<const C2<R> *>(&spec[(static_cast<long long>(z) * K + k) * M + y]);
+      r1 = r.a;
+      r2 = r.b;
     } else {
       r1.x = r1.y = r2.x = r2.y = R(0);
     }
@@ -351,10 +358,11 @@ k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl
 // For the inverse pass, work-group (0,0) also adds the energy partials of
 // the z pass in a fixed order and writes E (plus the self energy if asked).
 struct EnergyOut {
-  const double *part;
+  const double *part;      // energy partials of the z pass
   int nparts;
-  const double *qsq;
-  double self_coef;
+  const double *qsq_part;  // per-block sums of q^2 from binning
+  int nq;
+  double self_coef;        // -xi / sqrt(pi) with the self term, else 0
   double *E;
 };
 
@@ -370,16 +378,17 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
   C *twl = b1 + M * B;  // twiddles staged in LDS
   for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
-  const int kx0 = blockIdx.x * B;
-  const long long zoff = static_cast<long long>(blockIdx.y) * M * K;
+  // B consecutive (z, kx) pencils, each M contiguous values along y
+  const int npen = M * K;
+  const int c0 = xcd_local(blockIdx.x, gridDim.x) * B;
   {
     C v[kMaxPerThread];
 #pragma unroll
     for (int k = 0; k < kMaxPerThread; ++k) {
       const int i = threadIdx.x + k * kThreads;
       const int y = i >> lgb, b = i & (B - 1);
-      if (i < M * B && kx0 + b < K) {
-        v[k] = spec[zoff + static_cast<long long>(y) * K + kx0 + b];
+      if (i < M * B && c0 + b < npen) {
+        v[k] = spec[static_cast<long long>(c0 + b) * M + y];
         if (INV) v[k] = cconj(v[k]);
       } else {
         v[k].x = v[k].y = R(0);
@@ -395,27 +404,29 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
   const C *Z = fft_any<R, MC, LGBC>(b0, b1, lgb, pl, twl);
   for (int i = threadIdx.x; i < M * B; i += kThreads) {
     const int y = i >> lgb, b = i & (B - 1);
-    if (kx0 + b < K) {
+    if (c0 + b < npen) {
       C v = Z[i];
       if (INV) v = cconj(v);
-      spec[zoff + static_cast<long long>(y) * K + kx0 + b] = v;
+      spec[static_cast<long long>(c0 + b) * M + y] = v;
     }
   }
-  if (INV && blockIdx.x == 0 && blockIdx.y == 0) {
-    __shared__ double red[kThreads];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < eo.nparts; b += blockDim.x) s += eo.part[b];
-    red[threadIdx.x] = s;
+  if (INV && blockIdx.x == 0) {
+    __shared__ double red[kThreads], redq[kThreads];
+    double se = 0.0, sq = 0.0;
+    for (int b = threadIdx.x; b < eo.nparts; b += kThreads) se += eo.part[b];
+    if (eo.self_coef != 0.0)
+      for (int b = threadIdx.x; b < eo.nq; b += kThreads) sq += eo.qsq_part[b];
+    red[threadIdx.x] = se;
+    redq[threadIdx.x] = sq;
     __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    for (int st = kThreads / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) {
+        red[threadIdx.x] += red[threadIdx.x + st];
+        redq[threadIdx.x] += redq[threadIdx.x + st];
+      }
       __syncthreads();
     }
-    if (threadIdx.x == 0) {
-      double E = red[0];
-      if (eo.self_coef != 0.0) E += eo.self_coef * (*eo.qsq);
-      *eo.E = E;
-    }
+    if (threadIdx.x == 0) *eo.E = red[0] + eo.self_coef * redq[0];
   }
 }
 
@@ -435,7 +446,7 @@ k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R>
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
   C *twl = b1 + M * B;  // twiddles staged in LDS
   for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
-  const int c0 = blockIdx.x * B;
+  const int c0 = xcd_local(blockIdx.x, gridDim.x) * B;  // pencils c = kx M + ky, contiguous in a z plane
   const long long zs = static_cast<long long>(M) * K;
   {
     C v[kMaxPerThread];
@@ -465,7 +476,7 @@ k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R>
     const int c = c0 + b;
     C v = Z[i];
     if (c < npen) {
-      const int ky = div_K<MC>(c, pl), kx = c - ky * K;
+      const int kx = div_M<MC>(c, pl), ky = c - kx * M;
       const double k2 = axis_k2[kx] + axis_k2[ky] + axis_k2[kz];
       const double w = (kx == 0 && ky == 0 && kz == 0)
                            ? 0.0
@@ -523,8 +534,8 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
       static_cast<const R *>(p.buf.grid), spec, p.fft, lx, tw);
   stage_end(p, SE_STAGE_FFT_X);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const dim3 yg((K + By - 1) / By, M);
-  const EnergyOut none{nullptr, 0, nullptr, 0.0, nullptr};
+  const unsigned yg = static_cast<unsigned>((M * K + By - 1) / By);
+  const EnergyOut none{nullptr, 0, nullptr, 0, 0.0, nullptr};
   stage_begin(p, SE_STAGE_FFT_Y);
   k_fft_y<R, MC, LY, false><<<yg, p.fft_threads, lds_of(ly), p.stream>>>(spec, p.fft, ly, tw, none);
   stage_end(p, SE_STAGE_FFT_Y);
@@ -536,7 +547,8 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
   stage_end(p, SE_STAGE_FFT_Z_SCALE);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double self_coef = (p.prm.flags & SE_FLAG_ADD_SELF) ? -p.prm.xi / sqrt(M_PI) : 0.0;
-  const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.qsq, self_coef, E_dev};
+  const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.part, p.bin_parts, self_coef,
+                     E_dev};
   stage_begin(p, SE_STAGE_IFFT_Y);
   k_fft_y<R, MC, LY, true><<<yg, p.fft_threads, lds_of(ly), p.stream>>>(spec, p.fft, ly, tw, eo);
   stage_end(p, SE_STAGE_IFFT_Y);
@@ -560,10 +572,20 @@ hipError_t fft_impl(se_plan &p, double *E_dev) {
     case 64: return fft_run<R, 64>(p, E_dev);
     case 80: return fft_run<R, 80>(p, E_dev);
     case 96: return fft_run<R, 96>(p, E_dev);
+    case 120: return fft_run<R, 120>(p, E_dev);
     case 128: return fft_run<R, 128>(p, E_dev);
+    case 144: return fft_run<R, 144>(p, E_dev);
     case 160: return fft_run<R, 160>(p, E_dev);
     case 192: return fft_run<R, 192>(p, E_dev);
+    case 216: return fft_run<R, 216>(p, E_dev);
+    case 240: return fft_run<R, 240>(p, E_dev);
     case 256: return fft_run<R, 256>(p, E_dev);
+    case 288: return fft_run<R, 288>(p, E_dev);
+    case 320: return fft_run<R, 320>(p, E_dev);
+    case 384: return fft_run<R, 384>(p, E_dev);
+    case 432: return fft_run<R, 432>(p, E_dev);
+    case 480: return fft_run<R, 480>(p, E_dev);
+    case 512: return fft_run<R, 512>(p, E_dev);
     default: return fft_run<R, 0>(p, E_dev);
   }
 }

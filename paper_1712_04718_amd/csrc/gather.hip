@@ -72,10 +72,7 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
   constexpr int NWAVES = kTileThreads / 64;
   constexpr bool POW2 = (S & (S - 1)) == 0;
 
-  const int tile = blockIdx.x;
-  const int start = offsets[tile], end = offsets[tile + 1];
-  if (start == end) return;
-
+  const int tile = xcd_local(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   R *blk = reinterpret_cast<R *>(h_smem);
@@ -86,15 +83,16 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
 
   // Stage the block: loads are issued in unrolled batches into registers and
   // only then written to LDS, so a thread has a batch of loads in flight
-  // instead of waiting for each one in turn.
+  // instead of waiting for each one in turn.  The block depends only on the
+  // tile index, so the first batch goes out before the tile's particle range
+  // is known, and the first round of particles is read while it is in
+  // flight: the three reads overlap instead of following one another.
   const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
   const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
   constexpr int TS3 = TS * TS * TS;
   constexpr int NST = (TS3 + kTileThreads - 1) / kTileThreads;  // elements per thread
   constexpr int BATCH = sizeof(R) == 4 ? 16 : 8;
-#pragma unroll
-  for (int k0 = 0; k0 < NST; k0 += BATCH) {
-    R v[BATCH];
+  const auto load_batch = [&](int k0, R (&v)[BATCH]) {
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
       const int i = tid + (k0 + k) * kTileThreads;
@@ -105,11 +103,30 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
         v[k] = phi_grid[(gz * M + gy) * M + gx];
       }
     }
+  };
+  const auto store_batch = [&](int k0, const R (&v)[BATCH]) {
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
       const int i = tid + (k0 + k) * kTileThreads;
       if (k0 + k < NST && i < TS3) blk[i] = v[k];
     }
+  };
+  R v0[BATCH];
+  load_batch(0, v0);
+  const int start = offsets[tile], end = offsets[tile + 1];
+  SortedParticle<R> sp0{};
+  int2 mt0 = make_int2(0, 0);
+  if (tid < min(CHUNK, end - start)) {
+    sp0 = sorted[start + tid];
+    mt0 = meta[start + tid];
+  }
+  if (start == end) return;  // uniform across the work-group
+  store_batch(0, v0);
+#pragma unroll
+  for (int k0 = BATCH; k0 < NST; k0 += BATCH) {
+    R v[BATCH];
+    load_batch(k0, v);
+    store_batch(k0, v);
   }
 
   const R scale = gscale ? static_cast<R>(*gscale) : R(1);
@@ -120,8 +137,8 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
     __syncthreads();  // grid block staged; previous round done with the factors
     // phase A: factors of particle base + tid
     if (tid < nval) {
-      const SortedParticle<R> sp = sorted[base + tid];
-      const int2 mt = meta[base + tid];
+      const SortedParticle<R> sp = base == start ? sp0 : sorted[base + tid];
+      const int2 mt = base == start ? mt0 : meta[base + tid];
       R *f = fac + tid * REC;
       R g[S], dg[S];
       const R dd[3] = {sp.dx, sp.dy, sp.dz};
@@ -275,7 +292,7 @@ template <typename R, int WIN, int S, int T>
 hipError_t gather_one(se_plan &p, const double *gscale, int mode, void *pot, void *vec) {
   const size_t lds = GatherLds<R, WIN, S, T>::TOTAL;
   const double dcoef = (WIN == kGauss) ? 2.0 * p.a * p.h : 1.0 / p.h;
-  WindowConsts wc{p.cg, p.beta, exp(-2.0 * p.cg), dcoef};
+  const WindowConsts wc = window_consts(p.cg, p.beta, dcoef);
   const double self = (p.prm.flags & SE_FLAG_ADD_SELF) ? -2.0 * p.prm.xi / sqrt(M_PI) : 0.0;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gather<R, WIN, S, T>),

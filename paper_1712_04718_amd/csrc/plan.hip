@@ -82,7 +82,6 @@ sek::FftPlan radix_plan(int M) {
     ns *= pl.radix[s];
   }
   pl.m_magic = sek::div_magic(M);
-  pl.k_magic = sek::div_magic(M / 2 + 1);
   return pl;
 }
 
@@ -135,7 +134,7 @@ se_status check_params(const se_params *prm, double *eta_out) {
 }
 
 struct Sizes {
-  size_t grid, ghost, cover, cover_count, spec, sorted, meta, key, counts, offsets, part, qsq, tw,
+  size_t grid, ghost, cover, cover_count, spec, sorted, meta, key, counts, offsets, part, tw,
       f, k2, total;
 };
 
@@ -181,12 +180,11 @@ Sizes sizes_of(const se_params &p, int n_max, int ntiles, int bin_blocks, int zb
   s.counts = al(static_cast<size_t>(ntiles) * sek::kCountStride * 4);
   s.offsets = al((ntiles + 1) * 4);
   s.part = al((bin_blocks + zblocks) * 8);
-  s.qsq = al(8);
   s.tw = al(M * 2 * rs);
   s.f = al(M * 8);
   s.k2 = al(M * 8);
   s.total = s.grid + s.ghost + s.cover + s.cover_count + s.spec + s.sorted + s.meta + s.key +
-            s.counts + s.offsets + s.part + s.qsq + s.tw + s.f + s.k2;
+            s.counts + s.offsets + s.part + s.tw + s.f + s.k2;
   return s;
 }
 
@@ -240,7 +238,7 @@ void free_all(se_plan &pl) {
   destroy_events(pl);
   void *ptrs[] = {pl.buf.grid, pl.buf.ghost, pl.buf.cover, pl.buf.cover_count, pl.buf.spec,
                   pl.buf.sorted, pl.buf.meta, pl.buf.key, pl.buf.counts, pl.buf.offsets,
-                  pl.buf.part, pl.buf.qsq, pl.buf.twiddle, pl.buf.axis_f, pl.buf.axis_k2};
+                  pl.buf.part, pl.buf.twiddle, pl.buf.axis_f, pl.buf.axis_k2};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   pl.buf = sek::DeviceBuffers{};
@@ -329,7 +327,6 @@ se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_p
       {reinterpret_cast<void **>(&pl->buf.counts), sz.counts},
       {reinterpret_cast<void **>(&pl->buf.offsets), sz.offsets},
       {reinterpret_cast<void **>(&pl->buf.part), sz.part},
-      {reinterpret_cast<void **>(&pl->buf.qsq), sz.qsq},
       {&pl->buf.twiddle, sz.tw},    {&pl->buf.axis_f, sz.f},
       {&pl->buf.axis_k2, sz.k2}};
   for (auto &a : allocs) {

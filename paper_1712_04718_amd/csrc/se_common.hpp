@@ -38,6 +38,18 @@ __device__ inline int fast_div(int n, unsigned magic) {
   return static_cast<int>(__umulhi(static_cast<unsigned>(n), magic));
 }
 
+// Work-groups are dealt to the 8 XCDs round-robin (work-group b runs on XCD
+// b mod 8), and each XCD has its own L2.  Renumbering b so that every XCD
+// gets a contiguous range of work items keeps neighbouring tiles and
+// pencils, which share cache lines and halo data, in one L2.  Bijective on
+// [0, G): the first 8 floor(G/8) work-groups are permuted, the rest keep
+// their number.
+constexpr int kXcds = 8;
+__device__ inline int xcd_local(int b, int G) {
+  const int q = G / kXcds;
+  return b < q * kXcds ? (b % kXcds) * q + b / kXcds : b;
+}
+
 // v mod M for v in [-M, 3M), branch-free.  Every grid index of a staged tile
 // block lies in [-(S-1), M + T + S - 3], inside that range whenever S <= M and
 // T + S - 3 < 2M (the plan checks both).
@@ -55,7 +67,6 @@ struct FftPlan {
   unsigned ns_magic[kMaxRadixStages];  // div_magic(ns[s])
   int tstep[kMaxRadixStages];   // M / (ns[s] * radix[s]): twiddle index step
   unsigned m_magic;             // div_magic(M)
-  unsigned k_magic;             // div_magic(M / 2 + 1)
 };
 
 // Which tile blocks of the ghost array cover each grid index along one axis
@@ -105,10 +116,9 @@ struct DeviceBuffers {
   void *sorted = nullptr;     // n_max SortedParticle<R>
   int2 *meta = nullptr;       // n_max (packed local anchor, original index)
   int2 *key = nullptr;        // n_max (tile, rank within tile)
-  int *counts = nullptr;      // ntiles, one per kCountStride ints (own cache line)
-  int *offsets = nullptr;     // ntiles + 1
-  double *part = nullptr;     // per-block partial sums (q^2 and energy)
-  double *qsq = nullptr;      // sum q^2 of the last forward
+  int *counts = nullptr;      // ntiles counters, kCountStride ints apart (own cache line)
+  int *offsets = nullptr;     // ntiles + 1: first sorted index of each tile, then N
+  double *part = nullptr;     // per-block partial sums: bin_blocks of q^2, then energy
   void *twiddle = nullptr;    // M complex: e^{-2 pi i j / M}
   void *axis_f = nullptr;     // M real: per-axis factor of the influence function
   void *axis_k2 = nullptr;    // M real: k_n^2 per axis
@@ -136,6 +146,7 @@ struct se_plan {
   int ntx;         // tiles per axis, ceil(M/T)
   int ntiles;      // ntx^3
   int bin_blocks;  // blocks of the binning kernel for n_max
+  int bin_parts;   // q^2 partials written by the last binning (its block count)
   int zfft_blocks; // blocks of the z-pass (energy partials)
   int fft_lgb[3];  // log2 pencils per FFT work-group of the x, y and z passes
   int fft_threads; // threads per FFT work-group
@@ -188,11 +199,12 @@ constexpr int kGatherAdjoint = 1;         // out_pot = gE phi, out_vec = -gE F
 constexpr int kThreads = 256;      // work-group size of the binning, fold and FFT kernels
 constexpr int kTileThreads = 512;  // work-group size of the tile spread and gather kernels
 
-// Most pencils per FFT work-group, per pass.  The x passes read and write
-// whole rows, so fewer pencils (more work-groups in flight) pay off; the y
-// pass reads B consecutive kx per row and wants B = 16 for whole cache lines.
+// Most pencils per FFT work-group, per pass.  Lanes run over the B pencils
+// fastest, so a wave reads 64 / B consecutive elements of each pencil: the
+// y pencils are contiguous and B = 4 gives whole 128-byte lines with many
+// work-groups in flight; x rows and z columns take B = 8.
 enum FftPass { kPassX = 0, kPassY = 1, kPassZ = 2 };
-constexpr int kFftBatchCap[3] = {8, 16, 8};
+constexpr int kFftBatchCap[3] = {8, 4, 8};
 
 // Pencils per FFT work-group of one pass, as log2: B a power of two, at most
 // kFftBatchCap[pass], with M * B <= 16 * kThreads (elements per thread when

@@ -14,7 +14,10 @@
 //         (beta^3 for the Gaussian, 1 for B-splines): no partial sum can leave
 //         (-2^31, 2^31), each contribution is rounded once, and the result
 //         does not depend on the order of the additions.  (Integer LDS atomics
-//         run far faster than floating-point ones on this chip.)
+//         run far faster than floating-point ones on this chip.)  A
+//         contribution is an FP32 product with 24 significant bits while the
+//         fixed point spans 30, so exact halves are common: they round to
+//         even, which keeps the sum unbiased (rounding halves up would not).
 //   FP64: LDS double atomics.
 // Work split: the tile's particles are taken in chunks of one per thread;
 //   phase A: each thread computes its particle's 3S window factors (charge
@@ -42,71 +45,19 @@ constexpr int spread_chunk(int real_size, int S) {
   return c;
 }
 
-// Lanes of phase B: each particle gets PAIRS = S^2 lanes (jx, jy), pair
-// p = jy S + jx, that loop over jz; S^2 <= 32 packs 64 / S^2 particles into a
-// wave, larger S^2 takes ceil(S^2 / 64) passes of a whole wave.
-constexpr int spread_groups(int S) { return S * S <= 32 ? 64 / (S * S) : 1; }
-constexpr int spread_passes(int S) { return S * S <= 32 ? 1 : (S * S + 63) / 64; }
-
-// Whether the lanes of each pass (of the first particle group when a wave
-// holds several) fall in distinct bank slots with row stride SY: slot =
-// (jx + SY jy) mod `slots`, over the whole wave or over each 32-lane half.
-constexpr bool spread_lanes_distinct(int S, int SY, int slots, bool halves) {
-  const int lanes = S * S <= 32 ? S * S : 64;
-  for (int pass = 0; pass < spread_passes(S); ++pass) {
-    unsigned long long seen[2] = {0ull, 0ull};
-    for (int a = 0; a < lanes; ++a) {
-      const int p = pass * 64 + a;
-      if (p >= S * S) break;
-      const int slot = (p % S + SY * (p / S)) % slots;
-      const int h = (halves && a >= 32) ? 1 : 0;
-      if ((seen[h] >> slot) & 1ull) return false;
-      seen[h] |= 1ull << slot;
-    }
-  }
-  return true;
-}
-
-// Row stride (elements) of the LDS block: the smallest SY >= TS that keeps
-// the lanes of a phase-B instruction in distinct banks (64 banks of 4 bytes:
-// a 4-byte accumulator wants distinct slots mod 64 over the wave and mod 32
-// over each half; an 8-byte one covers two banks and wants distinct slots
-// mod 32 over each half), padding at most to 2 TS and only while the block
-// stays within 64 KB; else TS.
-constexpr int spread_row_stride(int S, int TS, int acc_size) {
-  const auto fits = [TS, acc_size](int sy) {
-    return static_cast<long long>(TS) * TS * sy * acc_size <= 65536;
-  };
-  if (acc_size == 4) {
-    for (int sy = TS; sy <= 2 * TS; ++sy)
-      if (fits(sy) && spread_lanes_distinct(S, sy, 64, false) && spread_lanes_distinct(S, sy, 32, true))
-        return sy;
-    for (int sy = TS; sy <= 2 * TS; ++sy)
-      if (fits(sy) && spread_lanes_distinct(S, sy, 64, false)) return sy;
-  } else {
-    for (int sy = TS; sy <= 2 * TS; ++sy)
-      if (fits(sy) && spread_lanes_distinct(S, sy, 32, true)) return sy;
-  }
-  return TS;
-}
-
 constexpr size_t spread_lds_total(int real_size, int S, int T) {
-  const int TS = T + S - 1, acc = real_size == 4 ? 4 : 8;
-  const int SY = spread_row_stride(S, TS, acc);
+  const size_t TS = T + S - 1, acc = real_size == 4 ? 4 : 8;
   const size_t chunk = spread_chunk(real_size, S);
-  return static_cast<size_t>(acc) * ((static_cast<size_t>(TS) * TS * SY + 3) & ~static_cast<size_t>(3)) +
-         static_cast<size_t>(real_size) * chunk * 3 * S + 4 * chunk + 128;
+  return acc * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) + real_size * chunk * 3 * S +
+         4 * chunk + 128;
 }
 
 template <typename R, int S, int T> struct SpreadLds {
   using A = typename Acc<R>::T;
   static constexpr int TS = T + S - 1;
-  static constexpr int SY = spread_row_stride(S, TS, sizeof(A));  // row stride
-  static constexpr int SP = TS * SY;                               // plane stride
-  static constexpr int NBLK = TS * SP;
   static constexpr int REC = 3 * S;
   static constexpr int CHUNK = spread_chunk(sizeof(R), S);
-  static constexpr size_t BLK = sizeof(A) * ((NBLK + 3) & ~3);
+  static constexpr size_t BLK = sizeof(A) * ((TS * TS * TS + 3) & ~3);
   static constexpr size_t FAC = sizeof(R) * CHUNK * REC;
   static constexpr size_t ANC = sizeof(int) * CHUNK;
   static constexpr size_t TOTAL = BLK + FAC + ANC + 128;
@@ -119,15 +70,15 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
          const int *__restrict__ offsets, WindowConsts wc, double wmax, R *__restrict__ ghost) {
   using L = SpreadLds<R, S, T>;
   using A = typename Acc<R>::T;
-  constexpr int TS = L::TS, SY = L::SY, SP = L::SP, REC = L::REC, TS3 = TS * TS * TS;
+  constexpr int TS = L::TS, REC = L::REC, TS3 = TS * TS * TS;
   constexpr int kChunk = L::CHUNK;
-  constexpr int PAIRS = S * S, GROUPS = spread_groups(S), PASSES = spread_passes(S);
+  constexpr int GROUPS = 64 / S;
   constexpr int NWAVES = kTileThreads / 64;
   constexpr bool FIXED = sizeof(R) == 4;
   static_assert(NWAVES * 8 <= 128, "per-wave partials must fit the reduction area");
   static_assert(kChunk <= kTileThreads, "phase A holds one particle per thread");
 
-  const int tile = blockIdx.x;
+  const int tile = xcd_local(blockIdx.x, gridDim.x);
   const int start = offsets[tile], end = offsets[tile + 1];
   const int tid = threadIdx.x;
   R *out = ghost + static_cast<long long>(tile) * TS3;
@@ -150,7 +101,7 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
     mine = sorted[start + tid];
     mine_anchor = meta[start + tid].x;
   }
-  for (int i = tid; i < L::NBLK; i += kTileThreads) blk[i] = A(0);
+  for (int i = tid; i < TS3; i += kTileThreads) blk[i] = A(0);
 
   // Fixed-point scale of this tile, from a bound on sum |q| that does not
   // depend on the order of the particles (the order inside a tile comes from
@@ -187,20 +138,8 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
     }
   }
 
-  // this lane's (jx, jy) in each pass, as an LDS offset, and its group
   const int wave = tid >> 6, lane = tid & 63;
-  const int grp = GROUPS > 1 ? lane / PAIRS : 0;
-  int loff[PASSES], lx[PASSES], ly[PASSES];
-  bool lon[PASSES];
-#pragma unroll
-  for (int ps = 0; ps < PASSES; ++ps) {
-    const int pp = ps * 64 + (GROUPS > 1 ? lane - grp * PAIRS : lane);
-    lon[ps] = grp < GROUPS && pp < PAIRS;
-    ly[ps] = lon[ps] ? pp / S : 0;
-    lx[ps] = lon[ps] ? pp - ly[ps] * S : 0;
-    loff[ps] = ly[ps] * SY + lx[ps];
-  }
-
+  const int grp = lane / S, jx = lane - grp * S;
   for (int base = start; base < end; base += kChunk) {
     const int nval = min(kChunk, end - base);
     __syncthreads();  // previous round done with fac / anc; blk zeroed
@@ -230,35 +169,37 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
       anc[tid] = a;
     }
     __syncthreads();
-    // phase B: lane (jx, jy) of a particle adds its S products along z
-    for (int c = wave * GROUPS + grp; c < nval; c += NWAVES * GROUPS) {
-      const R *f = fac + c * REC;
-      const int packed = anc[c];
-      const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
-      A *corner = blk + az * SP + ay * SY + ax;
-      R gz[S];
+    // phase B: lane (group, jx) of 64/S particle groups adds its S^2 products
+    if (grp < GROUPS) {
+      for (int c = wave * GROUPS + grp; c < nval; c += NWAVES * GROUPS) {
+        const R *f = fac + c * REC;
+        const int packed = anc[c];
+        const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
+        A *row = blk + (az * TS + ay) * TS + ax + jx;
+        const R wq = f[jx];
+        R gy[S], gz[S];
 #pragma unroll
-      for (int j = 0; j < S; ++j) gz[j] = f[2 * S + j];
-#pragma unroll
-      for (int ps = 0; ps < PASSES; ++ps) {
-        if (!lon[ps]) continue;
-        const R wxy = f[lx[ps]] * f[S + ly[ps]];
-        A *col = corner + loff[ps];
+        for (int j = 0; j < S; ++j) {
+          gy[j] = f[S + j];
+          gz[j] = f[2 * S + j];
+        }
 #pragma unroll
         for (int jz = 0; jz < S; ++jz) {
-          if constexpr (FIXED)
-            atomicAdd(col + jz * SP, __float2int_rn(wxy * gz[jz]));
-          else
-            unsafeAtomicAdd(col + jz * SP, wxy * gz[jz]);
+          const R wz = wq * gz[jz];
+#pragma unroll
+          for (int jy = 0; jy < S; ++jy) {
+            if constexpr (FIXED)
+              atomicAdd(row + (jz * TS + jy) * TS, __float2int_rn(wz * gy[jy]));
+            else
+              unsafeAtomicAdd(row + (jz * TS + jy) * TS, wz * gy[jy]);
+          }
         }
       }
     }
   }
   __syncthreads();
   for (int i = tid; i < TS3; i += kTileThreads) {
-    const int z = i / (TS * TS), rem = i - z * (TS * TS);
-    const int y = rem / TS, x = rem - y * TS;
-    const A v = blk[z * SP + y * SY + x];
+    const A v = blk[i];
     if constexpr (FIXED)
       out[i] = static_cast<R>(static_cast<double>(v) * inv_scale);
     else
@@ -314,7 +255,7 @@ k_fold_tiles(const R *__restrict__ ghost, int M, int ntx, R *__restrict__ grid) 
   constexpr int OFF = Stencil<WIN, S>::OFF;
   const int i = static_cast<int>(blockIdx.y) * kThreads + static_cast<int>(threadIdx.x);
   if (i >= T3) return;
-  const int tile = blockIdx.x;
+  const int tile = xcd_local(blockIdx.x, gridDim.x);
   const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
   const int lz = i / (T * T), ly = (i / T) % T, lx = i % T;
   R v[MAXK][MAXK][MAXK];
@@ -350,7 +291,7 @@ k_fold_tiles(const R *__restrict__ ghost, int M, int ntx, R *__restrict__ grid) 
 template <typename R, int WIN, int S, int T>
 hipError_t spread_one(se_plan &p) {
   const size_t lds = SpreadLds<R, S, T>::TOTAL;
-  WindowConsts wc{p.cg, p.beta, exp(-2.0 * p.cg), 0.0};
+  const WindowConsts wc = window_consts(p.cg, p.beta, 0.0);
   const double wmax = (WIN == kGauss) ? p.beta * p.beta * p.beta : 1.0;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_spread<R, WIN, S, T>),

@@ -12,7 +12,8 @@
 // FP64 factors follow the fast Gaussian gridding recurrence of eqs.
 // (4.10)-(4.11): g_{j+1} = g_j r_j with r_j = exp(-cg (2 t_j + 1)) and
 // r_{j+1} = r_j exp(-2 cg), i.e. two exponentials per axis instead of P.
-// FP32 factors are evaluated one by one (see window_axis).  The derivative
+// FP32 factors use three exponentials per axis around the anchor (see
+// window_axis).  The derivative
 // factor used for forces is the derivative with respect to the particle
 // coordinate, d/dx_m W(x_j - x_m) = 2 a (x_j - x_m) W, i.e. per axis
 // dg_j = 2 a h t_j g_j.
@@ -25,6 +26,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 namespace sek {
 
 constexpr int kGauss = 0;
@@ -34,12 +37,22 @@ template <int WIN, int S> struct Stencil {
   static constexpr int OFF = (WIN == kGauss) ? -(S / 2 - 1) : -(S - 1);
 };
 
+constexpr int kMaxHalfSupport = 8;  // S / 2 for the largest Gaussian support
+
 struct WindowConsts {
   double cg;     // Gaussian exponent in grid units (SE)
   double beta;   // per-axis Gaussian normalisation (SE)
   double kap;    // exp(-2 cg), ratio of successive recurrence factors (SE)
   double dcoef;  // SE: 2 a h; SPME: 1/h   (derivative scale)
+  float ck[kMaxHalfSupport + 1];  // exp(-cg k^2), k = 0..S/2 (SE, FP32)
 };
+
+inline WindowConsts window_consts(double cg, double beta, double dcoef) {
+  WindowConsts wc{cg, beta, std::exp(-2.0 * cg), dcoef, {}};
+  for (int k = 0; k <= kMaxHalfSupport; ++k)
+    wc.ck[k] = static_cast<float>(std::exp(-cg * static_cast<double>(k) * k));
+  return wc;
+}
 
 // All S factors of one axis (and optionally their derivatives).
 //
@@ -55,11 +68,31 @@ __device__ inline void window_axis(R d, const WindowConsts &wc, R (&g)[S], R (&d
     const R cg = static_cast<R>(wc.cg);
     const R beta = static_cast<R>(wc.beta);
     if constexpr (sizeof(R) == 4) {
+      // With k = j + OFF (k = 0 at the anchor), t_j = k - d and
+      //   g_j = beta e^{-cg (k - d)^2} = A B^k C_k,
+      //   A = beta e^{-cg d^2},  B = e^{2 cg d},  C_k = e^{-cg k^2} (a table),
+      // so an axis needs three exponentials; the powers of B (or of 1/B for
+      // k < 0) are built outward from the anchor, where the factors are
+      // largest, and gain about one rounding per step.
+      constexpr int J0 = -OFF;  // index of the anchor point
+      const R A = beta * expf(-cg * d * d);
+      const R Bu = expf(R(2) * cg * d), Bd = expf(R(-2) * cg * d);
+      g[J0] = A;
+      R p = A;
 #pragma unroll
-      for (int j = 0; j < S; ++j) {
-        const R t = static_cast<R>(OFF + j) - d;
-        g[j] = beta * expf(-cg * t * t);
-        if constexpr (DERIV) dg[j] = static_cast<R>(wc.dcoef) * t * g[j];
+      for (int k = 1; J0 + k < S; ++k) {
+        p *= Bu;
+        g[J0 + k] = p * wc.ck[k];
+      }
+      p = A;
+#pragma unroll
+      for (int k = 1; k <= J0; ++k) {
+        p *= Bd;
+        g[J0 - k] = p * wc.ck[k];
+      }
+      if constexpr (DERIV) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) dg[j] = static_cast<R>(wc.dcoef) * (static_cast<R>(OFF + j) - d) * g[j];
       }
     } else {
       const R t0 = static_cast<R>(OFF) - d;

@@ -69,6 +69,33 @@ def test_grid_sizes(M):
     _parity(x, q, L, M / (4 * L), M, 4 if M < 12 else 6, torch.float32)
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("M", [216, 288, 432, 512])
+def test_large_grid_sizes(M):
+    """Large compiled FFT sizes up to the largest supported grid (M = 512):
+    both precisions against one oracle evaluation (inputs rounded to FP32
+    first, so all three see the same values); xi = M / 4L.  The charge count
+    keeps N / (xi L)^3 fixed (as at M = 64 with 300 charges): much sparser
+    charges leave each force as the small remainder of its own Gaussian's
+    nearly symmetric gradient, which FP32 cannot resolve to 1e-5."""
+    L, P = 10.0, 6
+    N = int(0.07 * (M / 4) ** 3)
+    x, q = _rand(N, L, 900 + M)
+    x = x.astype(np.float32).astype(np.float64)
+    q = q.astype(np.float32).astype(np.float64)
+    print(f"[parity] large grid N={N} L={L} M={M} P={P}", flush=True)
+    ref = oracle_kspace("gaussian", x, q, L, M / (4 * L), M, P)
+    errs = {}
+    for dtype in (torch.float32, torch.float64):
+        out, plan, _, _ = gpu_kspace(x, q, L, M / (4 * L), M, P, dtype)
+        plan.close()
+        errs[dtype] = errors(out, ref)
+        torch.cuda.empty_cache()
+    print(f"[parity] large grid M={M} errors {errs}", flush=True)
+    for dtype, e in errs.items():
+        assert max(e) < TOL[dtype], (M, dtype, e)
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_positions_on_edges(dtype):
     """Particles on grid points, at 0, just below L, outside [0, L) (wrapped)."""
@@ -208,3 +235,12 @@ def test_full_water_L100(P, dtype):
 @pytest.mark.parametrize("window,P", [("gaussian", 8), ("bspline", 4), ("bspline", 6)])
 def test_full_ions_1M(window, P):
     _sampled_parity("ions_1M", P, torch.float32, window=window)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("window,P,M", [("gaussian", 10, 192), ("bspline", 4, 432)])
+def test_full_ions_1M_tuned(window, P, M):
+    """The 10^6-ion workload at the parameters that reach a relative rms
+    k-space force error of 1e-4 (tests/golden/spme_tuned_grid.json; SPME
+    p = 6 at M = 192 is test_full_ions_1M), in the FP32 form that is timed."""
+    _sampled_parity("ions_1M", P, torch.float32, window=window, M=M)
