@@ -166,6 +166,37 @@ se_status se_kspace(se_plan *plan, int N, const void *x, const void *q,
 se_status se_backward(se_plan *plan, const double *gE_dev, void *grad_x,
                       void *grad_q);
 
+/* ------------------------------------------------------------------------
+ * Real-space part of the Ewald sums (section 1, eqs. 1.5-1.7, the erfc
+ * terms), truncated at |r| < rc with the nearest periodic image:
+ *     phi_m = sum_{n != m} q_n erfc(xi r)/r,
+ *     F_m   = q_m sum_{n != m} q_n (2 xi/sqrt(pi) e^{-xi^2 r^2} + erfc(xi r)/r) r_vec/r^2,
+ *     E     = 1/2 sum_m q_m phi_m,        r_vec = x_m - x_n.
+ * The total Ewald sum is this plus se_forward/se_gather (k-space) plus the
+ * self terms (SE_FLAG_ADD_SELF).  Same conventions as above (device arrays
+ * x[N][3], q[N], phi[N], F[N][3] of the plan's dtype; E one device double;
+ * asynchronous on the plan's stream; arguments checked on the host).
+ * ------------------------------------------------------------------------ */
+typedef struct se_rs_plan se_rs_plan;
+
+/* A real-space plan on the current device for up to n_max particles in a
+ * cube of side L: cell list with cells of edge >= rc.  Requires
+ * 0 < rc <= L/3 (SE_ERR_ARG otherwise), so at most one image of a pair lies
+ * within rc.  The plan owns its workspace. */
+se_status se_rs_plan_create(double L, double xi, double rc, int dtype, int n_max,
+                            void *hip_stream, se_rs_plan **out);
+
+/* Change the stream later calls enqueue on. */
+se_status se_rs_plan_set_stream(se_rs_plan *plan, void *hip_stream);
+
+/* E_dev, phi (device [N], may be NULL) and F (device [N][3], may be NULL)
+ * of the real-space sum; 0 <= N <= n_max, N = 0 gives E = 0. */
+se_status se_rs_eval(se_rs_plan *plan, int N, const void *x, const void *q,
+                     double *E_dev, void *phi, void *F);
+
+/* Release the plan (synchronises its stream first). */
+se_status se_rs_plan_destroy(se_rs_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

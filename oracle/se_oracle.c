@@ -355,3 +355,42 @@ void or_ewald_real(int N, const double *x, const double *q, double L, double xi,
     if (E)
         *E = e;
 }
+
+/* Real-space sums of or_ewald_real for the nt target particles idx[0..nt)
+ * only (the sources are all N particles): phi[t], F[3t..3t+2] for
+ * particle idx[t]. */
+void or_ewald_real_targets(int N, const double *x, const double *q, double L, double xi,
+                           double rc, int nt, const int *idx, double *phi, double *F)
+{
+    const int np = (int)ceil(rc / L) + 1;
+#pragma omp parallel for schedule(dynamic)
+    for (int t = 0; t < nt; ++t) {
+        const int m = idx[t];
+        double pm = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int n = 0; n < N; ++n)
+            for (int pz = -np; pz <= np; ++pz)
+                for (int py = -np; py <= np; ++py)
+                    for (int px = -np; px <= np; ++px) {
+                        if (n == m && px == 0 && py == 0 && pz == 0)
+                            continue;
+                        double rx = x[3 * m] - x[3 * n] + px * L;
+                        double ry = x[3 * m + 1] - x[3 * n + 1] + py * L;
+                        double rz = x[3 * m + 2] - x[3 * n + 2] + pz * L;
+                        double r2 = rx * rx + ry * ry + rz * rz;
+                        if (r2 > rc * rc)
+                            continue;
+                        double r = sqrt(r2);
+                        double ec = erfc(xi * r) / r;
+                        pm += q[n] * ec;
+                        double fr = q[n] *
+                                    (2.0 * xi / sqrt(M_PI) * exp(-xi * xi * r2) + ec) / r2;
+                        fx += fr * rx;
+                        fy += fr * ry;
+                        fz += fr * rz;
+                    }
+        phi[t] = pm;
+        F[3 * t] = q[m] * fx;
+        F[3 * t + 1] = q[m] * fy;
+        F[3 * t + 2] = q[m] * fz;
+    }
+}

@@ -263,6 +263,23 @@ def ewald_real(x, q, L, xi, rc):
     return float(E[0]), phi, F
 
 
+def ewald_real_targets(x, q, L, xi, rc, idx):
+    """phi[len(idx)], F[len(idx), 3] of ewald_real for the particles idx
+    only (all N particles are sources)."""
+    x = _f64(x, (-1, 3))
+    q = _f64(q)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    phi = np.empty(len(idx))
+    F = np.empty((len(idx), 3))
+    lib = _load()
+    lib.or_ewald_real_targets.argtypes = [
+        ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+        ctypes.c_int, np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS"), _dp, _dp]
+    lib.or_ewald_real_targets(len(q), x, q, float(L), float(xi), float(rc), len(idx), idx,
+                              phi, F)
+    return phi, F
+
+
 def ewald_self(q, xi):
     """Self terms of eqs. (1.5)-(1.6): phi = -2 xi q / sqrt(pi),
     E = -(xi / sqrt(pi)) sum q^2."""

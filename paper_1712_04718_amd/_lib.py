@@ -31,6 +31,7 @@ EXPORTS = (
     "se_status_string", "se_last_error", "se_params_check", "se_plan_workspace_size",
     "se_plan_create", "se_plan_set_stream", "se_plan_eta", "se_plan_destroy",
     "se_forward", "se_gather", "se_kspace", "se_backward", "se_plan_stage_times",
+    "se_rs_plan_create", "se_rs_plan_set_stream", "se_rs_eval", "se_rs_plan_destroy",
 )
 
 
@@ -95,6 +96,14 @@ def load() -> ctypes.CDLL:
     lib.se_backward.argtypes = [vp, vp, vp, vp]
     lib.se_plan_stage_times.restype = i
     lib.se_plan_stage_times.argtypes = [vp, ctypes.POINTER(d), i]
+    lib.se_rs_plan_create.restype = i
+    lib.se_rs_plan_create.argtypes = [d, d, d, i, i, vp, ctypes.POINTER(vp)]
+    lib.se_rs_plan_set_stream.restype = i
+    lib.se_rs_plan_set_stream.argtypes = [vp, vp]
+    lib.se_rs_eval.restype = i
+    lib.se_rs_eval.argtypes = [vp, i, vp, vp, vp, vp, vp]
+    lib.se_rs_plan_destroy.restype = i
+    lib.se_rs_plan_destroy.argtypes = [vp]
     _lib = lib
     return lib
 

@@ -138,6 +138,69 @@ class SEPlan:
             pass
 
 
+class RealSpacePlan:
+    """The real-space (erfc) part of the Ewald sums for up to ``n_max``
+    particles in a cube of side L, truncated at rc <= L/3 (cell list on the
+    GPU).  ``eval(x, q)`` returns (E, phi, F); the total Ewald sum is this
+    plus the k-space part of an SEPlan created with ``add_self=True``."""
+
+    def __init__(self, L, xi, rc, dtype=torch.float32, n_max=1 << 20, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("RealSpacePlan needs a GPU (no HIP device visible)")
+        if dtype not in _DTYPES:
+            raise TypeError(f"dtype must be float32 or float64, got {dtype}")
+        self.lib = _lib.load()
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.L, self.xi, self.rc, self.dtype, self.n_max = float(L), float(xi), float(rc), dtype, int(n_max)
+        self._plan = ctypes.c_void_p(None)
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            _lib.check(self.lib.se_rs_plan_create(self.L, self.xi, self.rc, _DTYPES[dtype],
+                                                  self.n_max, ctypes.c_void_p(stream),
+                                                  ctypes.byref(self._plan)))
+
+    def eval(self, x, q, want_phi=True, want_F=True):
+        if x.device != self.device or q.device != self.device:
+            raise ValueError(f"x and q must be on {self.device}")
+        if x.dtype != self.dtype or q.dtype != self.dtype:
+            raise TypeError(f"x and q must be {self.dtype}")
+        if x.dim() != 2 or x.shape[1] != 3 or q.dim() != 1 or q.shape[0] != x.shape[0]:
+            raise ValueError("expected x [N,3] and q [N]")
+        x, q = x.contiguous(), q.contiguous()
+        N = int(x.shape[0])
+        E = torch.empty((), dtype=torch.float64, device=self.device)
+        phi = torch.empty(N, dtype=self.dtype, device=self.device) if want_phi else None
+        F = torch.empty(N, 3, dtype=self.dtype, device=self.device) if want_F else None
+        with torch.cuda.device(self.device):
+            s = torch.cuda.current_stream(self.device).cuda_stream
+            _lib.check(self.lib.se_rs_plan_set_stream(self._plan, ctypes.c_void_p(s)))
+            _lib.check(self.lib.se_rs_eval(self._plan, N, _ptr(x), _ptr(q), _ptr(E), _ptr(phi),
+                                           _ptr(F)))
+        self._keep = (x, q)
+        return E, phi, F
+
+    def close(self):
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            _lib.check(self.lib.se_rs_plan_destroy(self._plan))
+            self._plan = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ewald_total(x, q, kplan: SEPlan, rplan: RealSpacePlan):
+    """(E, phi, F) of the total Ewald sum: real space + k space + self terms
+    (the k-space plan must have been created with ``add_self=True``)."""
+    Ek, phik, Fk = kplan.kspace(x, q)
+    Er, phir, Fr = rplan.eval(x, q)
+    return Ek + Er, phik + phir, Fk + Fr
+
+
 def se_kspace(x, q, plan: SEPlan):
     """(E, phi[N], F[N,3]) of the k-space sum on ``plan``."""
     return plan.kspace(x, q)

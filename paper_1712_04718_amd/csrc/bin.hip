@@ -225,52 +225,74 @@ k_bin_scatter(int N, const R *__restrict__ x, const R *__restrict__ q, double h,
 }
 
 template <typename R>
-hipError_t bin_impl(se_plan &p, int N, const void *x, const void *q) {
-  const int M = p.prm.M;
-  const R *xr = static_cast<const R *>(x), *qr = static_cast<const R *>(q);
+hipError_t bin_impl(const BinJob &j, se_plan *timing) {
+  const R *xr = static_cast<const R *>(j.x), *qr = static_cast<const R *>(j.q);
+  const int N = j.N;
   const int blocks1 = N > 0 ? (N + kThreads - 1) / kThreads : 0;
   hipError_t e = hipSuccess;
-  stage_begin(p, SE_STAGE_BIN_COUNT);
-  p.bin_parts = 0;  // q^2 partials written by this call (count work-groups)
+  if (timing) stage_begin(*timing, SE_STAGE_BIN_COUNT);
+  int parts = 0;
   if (N > 0) {
-    if (p.ntiles <= kLdsTilesMax) {
-      const size_t lds = sizeof(int) * 2 * static_cast<size_t>(p.ntiles);
-      if (static_cast<long long>(N) >= 256LL * p.ntiles) {
+    if (j.ncells <= kLdsTilesMax) {
+      const size_t lds = sizeof(int) * 2 * static_cast<size_t>(j.ncells);
+      if (static_cast<long long>(N) >= 256LL * j.ncells) {
         constexpr int PPT = 8;
-        p.bin_parts = (N + kThreads * PPT - 1) / (kThreads * PPT);
-        k_bin_count_lds<R, PPT><<<p.bin_parts, kThreads, lds, p.stream>>>(
-            N, xr, qr, p.h, M, p.T, p.ntx, p.ntiles, p.buf.counts, p.buf.key, p.buf.part);
+        parts = (N + kThreads * PPT - 1) / (kThreads * PPT);
+        k_bin_count_lds<R, PPT><<<parts, kThreads, lds, j.stream>>>(
+            N, xr, qr, j.h, j.M, j.T, j.ntx, j.ncells, j.counts, j.key, j.qsq_part);
       } else {
-        p.bin_parts = blocks1;
-        k_bin_count_lds<R, 1><<<p.bin_parts, kThreads, lds, p.stream>>>(
-            N, xr, qr, p.h, M, p.T, p.ntx, p.ntiles, p.buf.counts, p.buf.key, p.buf.part);
+        parts = blocks1;
+        k_bin_count_lds<R, 1><<<parts, kThreads, lds, j.stream>>>(
+            N, xr, qr, j.h, j.M, j.T, j.ntx, j.ncells, j.counts, j.key, j.qsq_part);
       }
     } else {
-      p.bin_parts = blocks1;
-      k_bin_count_run<R><<<p.bin_parts, kThreads, 0, p.stream>>>(
-          N, xr, qr, p.h, M, p.T, p.ntx, p.buf.counts, p.buf.key, p.buf.part);
+      parts = blocks1;
+      k_bin_count_run<R><<<parts, kThreads, 0, j.stream>>>(
+          N, xr, qr, j.h, j.M, j.T, j.ntx, j.counts, j.key, j.qsq_part);
     }
     e = hipGetLastError();
   }
-  stage_end(p, SE_STAGE_BIN_COUNT);
+  if (j.qsq_parts) *j.qsq_parts = parts;
+  if (timing) stage_end(*timing, SE_STAGE_BIN_COUNT);
   if (e != hipSuccess) return e;
-  stage_begin(p, SE_STAGE_BIN_SCAN);
-  k_bin_scan<<<1, kScanThreads, 0, p.stream>>>(p.buf.counts, p.buf.offsets, p.ntiles);
-  stage_end(p, SE_STAGE_BIN_SCAN);
+  if (timing) stage_begin(*timing, SE_STAGE_BIN_SCAN);
+  k_bin_scan<<<1, kScanThreads, 0, j.stream>>>(j.counts, j.offsets, j.ncells);
+  if (timing) stage_end(*timing, SE_STAGE_BIN_SCAN);
   if ((e = hipGetLastError()) != hipSuccess || N == 0) return e;
-  stage_begin(p, SE_STAGE_BIN_SCATTER);
-  k_bin_scatter<R><<<blocks1, kThreads, 0, p.stream>>>(
-      N, xr, qr, p.h, M, p.T, p.buf.key, p.buf.offsets,
-      static_cast<SortedParticle<R> *>(p.buf.sorted), p.buf.meta);
-  stage_end(p, SE_STAGE_BIN_SCATTER);
+  if (timing) stage_begin(*timing, SE_STAGE_BIN_SCATTER);
+  k_bin_scatter<R><<<blocks1, kThreads, 0, j.stream>>>(
+      N, xr, qr, j.h, j.M, j.T, j.key, j.offsets, static_cast<SortedParticle<R> *>(j.sorted),
+      j.meta);
+  if (timing) stage_end(*timing, SE_STAGE_BIN_SCATTER);
   return hipGetLastError();
 }
 
 }  // namespace
 
+hipError_t launch_bin_job(const BinJob &job, se_plan *timing) {
+  return job.fp64 ? bin_impl<double>(job, timing) : bin_impl<float>(job, timing);
+}
+
 hipError_t launch_bin(se_plan &plan, int N, const void *x, const void *q) {
-  return plan.prm.dtype == SE_FP64 ? bin_impl<double>(plan, N, x, q)
-                                   : bin_impl<float>(plan, N, x, q);
+  BinJob j;
+  j.N = N;
+  j.x = x;
+  j.q = q;
+  j.fp64 = plan.prm.dtype == SE_FP64;
+  j.h = plan.h;
+  j.M = plan.prm.M;
+  j.T = plan.T;
+  j.ntx = plan.ntx;
+  j.ncells = plan.ntiles;
+  j.counts = plan.buf.counts;
+  j.key = plan.buf.key;
+  j.offsets = plan.buf.offsets;
+  j.sorted = plan.buf.sorted;
+  j.meta = plan.buf.meta;
+  j.qsq_part = plan.buf.part;
+  j.qsq_parts = &plan.bin_parts;
+  j.stream = plan.stream;
+  return launch_bin_job(j, &plan);
 }
 
 }  // namespace sek

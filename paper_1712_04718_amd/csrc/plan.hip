@@ -246,6 +246,13 @@ void free_all(se_plan &pl) {
 
 }  // namespace
 
+namespace sek {
+se_status report(se_status s, const char *msg) {
+  g_last_error = msg;
+  return s;
+}
+}  // namespace sek
+
 extern "C" {
 
 const char *se_status_string(se_status s) {

@@ -165,6 +165,32 @@ struct se_plan {
 
 namespace sek {
 
+// Binning of N particles into cells of a regular grid: cell edge T points
+// of spacing h on an M^3 grid with ntx cells per axis (the k-space tiles, or
+// T = 1 for the real-space cell list).  Produces per-cell offsets (ncells +
+// 1), particles in cell order (offsets from their grid point in units of h,
+// and q) and (packed local grid point, original index); counts must be zero
+// on entry and are left zero.
+struct BinJob {
+  int N = 0;
+  const void *x = nullptr, *q = nullptr;
+  bool fp64 = false;
+  double h = 0.0;
+  int M = 0, T = 1, ntx = 0, ncells = 0;
+  int *counts = nullptr;
+  int2 *key = nullptr;
+  int *offsets = nullptr;
+  void *sorted = nullptr;
+  int2 *meta = nullptr;
+  double *qsq_part = nullptr;  // per-block q^2 sums (at least ceil(N/256) entries)
+  int *qsq_parts = nullptr;    // out: number of partials written
+  hipStream_t stream = nullptr;
+};
+hipError_t launch_bin_job(const BinJob &job, se_plan *timing);
+
+// Record msg as the calling thread's last error (se_last_error) and return s.
+se_status report(se_status s, const char *msg);
+
 // Launch wrappers (one per translation unit); each enqueues on plan.stream
 // and returns the launch status.
 hipError_t launch_bin(se_plan &plan, int N, const void *x, const void *q);

@@ -80,3 +80,23 @@ def test_workspace_size():
     assert st == 0 and b64 > b
     st, _ = _lib.workspace_size(prm, 0)
     assert st == 1  # SE_ERR_ARG
+
+
+@pytest.mark.parametrize("L,xi,rc,dtype,n_max", [
+    (10.0, 1.0, 4.0, _lib.SE_FP32, 10),      # rc > L/3: more than one image within rc
+    (10.0, 1.0, 0.0, _lib.SE_FP32, 10),      # rc = 0
+    (-1.0, 1.0, 0.2, _lib.SE_FP32, 10),      # L <= 0
+    (10.0, 0.0, 2.0, _lib.SE_FP32, 10),      # xi = 0
+    (10.0, 1.0, 2.0, 7, 10),                 # unknown dtype
+    (10.0, 1.0, 2.0, _lib.SE_FP64, 0),       # n_max < 1
+])
+def test_realspace_plan_rejects_bad_arguments(L, xi, rc, dtype, n_max):
+    """The real-space plan checks its arguments on the host before touching
+    the device (so this runs without a GPU)."""
+    import ctypes
+    lib = _lib.load()
+    out = ctypes.c_void_p(None)
+    st = lib.se_rs_plan_create(L, xi, rc, dtype, n_max, None, ctypes.byref(out))
+    assert _lib.STATUS_NAMES.get(st) == "SE_ERR_ARG", st
+    assert out.value is None
+    assert lib.se_last_error().decode()

@@ -1,0 +1,122 @@
+"""Real-space (erfc) part of the Ewald sums on the GPU vs the FP64 oracle,
+and the total Ewald sum (k space + real space + self) on crystals.
+
+Bar: relative rms error of E, phi and F <= 1e-5 in FP32 and <= 1e-9 in FP64
+against the oracle's real-space sum with the same cutoff."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, TOL, as_oracle_inputs, cached_system, to_dev
+from oracle import se_oracle as O
+from paper_1712_04718_amd import RealSpacePlan, SEPlan, _lib, ewald_total
+from workloads import nacl_lattice
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float32, torch.float64]
+
+
+def _rs(x, q, L, xi, rc, dtype):
+    xt, qt = to_dev(x, q, dtype)
+    plan = RealSpacePlan(L, xi, rc, dtype=dtype, n_max=max(1, len(q)))
+    E, phi, F = plan.eval(xt, qt)
+    torch.cuda.synchronize()
+    out = (E.item(), phi.double().cpu().numpy(), F.double().cpu().numpy())
+    plan.close()
+    return out, xt, qt
+
+
+def _errors(gpu, ref):
+    (E, phi, F), (Eo, phio, Fo) = gpu, ref
+    return (abs(E - Eo) / abs(Eo), O.rel_rms(phi, phio), O.rel_rms(F, Fo))
+
+
+def _parity(x, q, L, xi, rc, dtype):
+    print(f"[realspace] N={len(q)} L={L} xi={xi} rc={rc} {dtype}", flush=True)
+    out, xt, qt = _rs(x, q, L, xi, rc, dtype)
+    xo, qo = as_oracle_inputs(xt, qt)
+    e = _errors(out, O.ewald_real(xo, qo, L, xi, rc))
+    assert max(e) < TOL[dtype], e
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_ions_1k(dtype):
+    """1000 ions in L = 10, xi = 1.5, rc = 2.4 (4 cells per side)."""
+    x, q, spec = cached_system("ions_1k")
+    _parity(x, q, spec.L, spec.xi, 2.4, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_water_L40(dtype):
+    """6411-atom water, xi = 0.3, rc = 9 (4 cells per side, molecules split
+    across cells)."""
+    x, q, spec = cached_system("water_L40")
+    _parity(x, q, spec.L, spec.xi, 9.0, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_minimum_cells_and_crowded_cell(dtype):
+    """Three cells per side (rc = L/3: every cell is everyone's neighbour)
+    and 700 particles in one cell (more than a work-group holds at once)."""
+    rng = np.random.default_rng(3)
+    L = 12.0
+    x = np.concatenate([rng.random((700, 3)) * 1.5 + 2.0, rng.random((200, 3)) * L])
+    q = rng.standard_normal(900)
+    _parity(x, q, L, 0.8, L / 3, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_empty_and_single(dtype):
+    """N = 0 gives E = 0; a lone charge has no partner within rc <= L/3."""
+    plan = RealSpacePlan(10.0, 1.0, 3.0, dtype=dtype, n_max=4)
+    x = torch.zeros(0, 3, dtype=dtype, device=DEV)
+    q = torch.zeros(0, dtype=dtype, device=DEV)
+    E, _, _ = plan.eval(x, q)
+    assert E.item() == 0.0
+    x1, q1 = to_dev(np.array([[1.0, 2.0, 3.0]]), np.array([2.0]), dtype)
+    E, phi, F = plan.eval(x1, q1)
+    torch.cuda.synchronize()
+    assert E.item() == 0.0 and phi.item() == 0.0 and float(F.abs().max()) == 0.0
+    plan.close()
+
+
+def test_full_water_L100_sampled():
+    """100k-atom water, rc = 10, FP32, 2000 sampled atoms against the oracle."""
+    x, q, spec = cached_system("water_L100")
+    print(f"[realspace] water_L100 N={len(q)} rc=10", flush=True)
+    xt, qt = to_dev(x, q, torch.float32)
+    plan = RealSpacePlan(spec.L, spec.xi, 10.0, dtype=torch.float32, n_max=len(q))
+    E, phi, F = plan.eval(xt, qt)
+    torch.cuda.synchronize()
+    xo, qo = as_oracle_inputs(xt, qt)
+    idx = np.random.default_rng(8).choice(len(q), size=2000, replace=False)
+    phio, Fo = O.ewald_real_targets(xo, qo, spec.L, spec.xi, 10.0, idx)
+    ephi = O.rel_rms(phi.double().cpu().numpy()[idx], phio)
+    eF = O.rel_rms(F.double().cpu().numpy()[idx], Fo)
+    print(f"[realspace] water_L100: phi {ephi:.2e} F {eF:.2e}", flush=True)
+    assert max(ephi, eF) < TOL[torch.float32]
+    plan.close()
+
+
+def test_total_ewald_nacl_madelung():
+    """Total Ewald sum of a rock-salt crystal on the GPU (SE k space with the
+    self terms, P = 16, FP64, plus the real space) against the oracle's exact
+    total at the same xi and rc, and against the Madelung constant."""
+    x, q, L = nacl_lattice(3)          # 216 ions, nearest-neighbour distance 1
+    xi, rc = 2.4, L / 3                 # erfc(xi rc) ~ 1e-10
+    xt, qt = to_dev(x, q, torch.float64)
+    kplan = SEPlan(48, 16, L, xi, dtype=torch.float64, n_max=len(q), add_self=True)
+    rplan = RealSpacePlan(L, xi, rc, dtype=torch.float64, n_max=len(q))
+    E, phi, F = ewald_total(xt, qt, kplan, rplan)
+    torch.cuda.synchronize()
+    Eo, phio, Fo = O.ewald_total(x, q, L, xi, rc)
+    assert abs(E.item() - Eo) / abs(Eo) < 1e-8, (E.item(), Eo)
+    alpha = 1.7475645946331822
+    assert abs(E.item() / len(q) * 2 + alpha) < 1e-7
+    np.testing.assert_allclose(phi.cpu().numpy(), -q * alpha, rtol=0, atol=1e-7)
+    assert float(F.abs().max()) < 1e-7
+    for p in (kplan, rplan):
+        p.close()

@@ -382,3 +382,15 @@ def test_spme_force_is_minus_energy_gradient(oracle):
             xm = x.copy(); xm[m, d] -= dx
             g = -(oracle.spme_kspace(xp, q, L, xi, M, p)[0] - oracle.spme_kspace(xm, q, L, xi, M, p)[0]) / (2 * dx)
             assert abs(g - F[m, d]) < 1e-6 * max(1.0, np.abs(F).max())
+
+
+def test_real_space_targets_match_full_sum(oracle):
+    """The target-subset real-space sum equals the full one on the targets."""
+    rng = np.random.default_rng(21)
+    x = rng.random((300, 3)) * 8.0
+    q = rng.standard_normal(300)
+    E, phi, F = oracle.ewald_real(x, q, 8.0, 1.1, 2.5)
+    idx = np.array([0, 7, 150, 299, 42])
+    phit, Ft = oracle.ewald_real_targets(x, q, 8.0, 1.1, 2.5, idx)
+    np.testing.assert_allclose(phit, phi[idx], rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(Ft, F[idx], rtol=1e-13, atol=1e-14)
