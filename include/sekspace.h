@@ -197,6 +197,104 @@ se_status se_rs_eval(se_rs_plan *plan, int N, const void *x, const void *q,
 /* Release the plan (synchronises its stream first). */
 se_status se_rs_plan_destroy(se_rs_plan *plan);
 
+/* ------------------------------------------------------------------------
+ * Parameters from an error tolerance (host only; no device, no plan).
+ *
+ * Error estimates for the potential, the energy or the force (kind =
+ * SE_EST_POTENTIAL, SE_EST_ENERGY, SE_EST_FORCE), in the units of that
+ * quantity with the Coulomb constant 1, for N charges with Q = sum q_n^2 in a
+ * cube of side L.  The potential forms estimate the rms error per particle;
+ * the force forms (which carry Q, not q_n sqrt(Q)) estimate the root of the
+ * summed squared errors, sqrt(sum_n |dF_n|^2): divide by sqrt(N) for the
+ * rms per particle.  Sources:
+ *   - real-space truncation at rc: Kolafa-Perram, section 2.1 eq. 2.1;
+ *   - Fourier truncation at |k| <= 2 pi kinf / L: section 2.1 eq. 2.2;
+ *   - SE approximation error A e^{-pi P c^2/2} with A_phi = sqrt(Q xi L)/L,
+ *     A_E = Q sqrt(xi L)/L, A_F = 4 pi Q sqrt(xi^3/L): sections 5.1-5.3.
+ * The inversions solve an estimate = eps for xi (eq. 2.3) or kinf (eq. 2.4);
+ * Lambert W is evaluated by Newton's method on w + ln w = ln z (exact to
+ * rounding for every z > 0, no overflow for huge z).
+ * All return SE_ERR_ARG for a non-finite or non-positive argument or an
+ * unknown kind, and write the output only on success.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+  SE_EST_POTENTIAL = 0,
+  SE_EST_ENERGY = 1,
+  SE_EST_FORCE = 2
+} se_est_kind;
+
+se_status se_est_real_error(int kind, double Q, double L, double xi, double rc, double *err);
+se_status se_est_fourier_error(int kind, double Q, double L, double xi, double kinf,
+                               double *err);
+/* xi at which the real-space estimate equals eps (eq. 2.3).  For the force
+ * form SE_ERR_ARG also when eps exceeds the estimate's value at xi = 0
+ * (every xi meets such a tolerance). */
+se_status se_est_xi(int kind, double eps, double Q, double L, double rc, double *xi);
+/* kinf at which the Fourier estimate equals eps (eq. 2.4). */
+se_status se_est_kinf(int kind, double eps, double Q, double L, double xi, double *kinf);
+/* SE approximation-error estimate at support P >= 1 and shape constant c
+ * (c <= 0 selects 0.95). */
+se_status se_est_se_error(int kind, double Q, double L, double xi, int P, double c,
+                          double *err);
+/* Smallest even P >= 2 whose SE estimate is <= eps (P is rounded up to an even
+ * number, section 5.3); SE_ERR_ARG if none up to 64. */
+se_status se_est_se_support(int kind, double eps, double Q, double L, double xi, double c,
+                            int *P);
+
+/* Runtime model, the form of section 7 extended by the terms a GPU launch
+ * sequence has (seconds):
+ *   t_real   = real_fixed + real_atom N + real_pair N nbar + real_cell ncells
+ *              + real_test N ntest q,
+ *   t_kspace = k_fixed + k_atom N + k_window N P^3 + k_block nt^3 (T+P-1)^3
+ *              + k_grid M^3 + k_fft (M^3/2) ln(M^3/2),
+ * with nbar = (4/3) pi rc^3 N / L^3 (section 7.1); for se_rs_eval's cell list
+ * nc = min(floor(L/rc), 64), ncells = nc^3, ntest = 27 (L/nc)^3 N / L^3 the
+ * pairs it tests per particle and q = ceil(ncells/512) 512 / ncells the
+ * work-group rounds on a 256-CU device at two cells per CU; T the tile edge
+ * se_plan_create picks for (M, P, dtype) and nt = ceil(M/T) (the tile blocks
+ * that spread, fold and gather move).  The paper's CPU model is
+ * real_pair = c_real, k_window = c_sp-ga, k_grid = c_solve,
+ * k_fft = c_fft-ifft, the rest 0. */
+typedef struct {
+  double real_fixed, real_atom, real_pair, real_cell, real_test;
+  double k_fixed, k_atom, k_window, k_block, k_grid, k_fft;
+} se_cost_model;
+
+/* Constants fitted on an MI355X (one GPU, se_kspace with the SE window and
+ * se_rs_eval, inputs resident in HBM) for dtype SE_FP32 or SE_FP64. */
+se_status se_cost_model_mi355x(int dtype, se_cost_model *model);
+
+/* The model's times for one configuration (SE window, shape constant 0.95
+ * for the tile choice); SE_ERR_UNSUPPORTED when no tile edge fits (M, P) in
+ * this precision.  t_real or t_kspace may be NULL. */
+se_status se_cost_predict(const se_cost_model *model, int dtype, int N, double L, double rc,
+                          int M, int P, double *t_real, double *t_kspace);
+
+typedef struct {
+  double rc, xi, kinf; /* chosen cutoff, Ewald parameter, Fourier cut        */
+  int M, P;            /* grid size and Gaussian support for se_plan_create  */
+  double eta;          /* P L^2 xi^2 / (c^2 pi M^2)                          */
+  double t_real, t_kspace;                     /* model times (s)            */
+  double est_real, est_fourier, est_approx;    /* estimates at the choice    */
+} se_choice;
+
+/* Cheapest SE parameters meeting tolerance eps (absolute rms error of the
+ * kind) with each of the three error sources held to eps on its own: for
+ * each of n_rc cutoffs rc_i = rc_min + i (rc_max - rc_min)/(n_rc - 1)
+ * (rc_min alone when n_rc = 1), xi from eq. 2.3, kinf from eq. 2.4, M the
+ * smallest size this library accepts (even, 8..512, 2^a 3^b 5^c) with
+ * M >= 2 kinf (section 5.3) and eta <= 0.5 (the regime in which the
+ * approximation estimate holds: it is derived at M ~ 4 xi L, where
+ * eta = P/(16 pi c^2) < 0.36), P the smallest even support >= 4
+ * meeting the SE estimate (at most 16); the cutoff of least modelled
+ * t_real + t_kspace (se_cost_predict in precision dtype) wins (first on
+ * ties).  Cutoffs above L/3 (the real-space plan's limit) or needing M > 512,
+ * P > 16 or a tile that does not fit are skipped; SE_ERR_UNSUPPORTED if none
+ * is left.  c <= 0 selects 0.95. */
+se_status se_choose_params(int kind, double eps, int N, double Q, double L, double rc_min,
+                           double rc_max, int n_rc, double c, int dtype,
+                           const se_cost_model *model, se_choice *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,7 @@ The computation lives in libsekspace.so (HIP kernels for gfx950, C ABI in
 include/sekspace.h); this package only binds it to PyTorch tensors.
 """
 from ._lib import EXPORTS, LIB_PATH, SeError  # noqa: F401
+from . import tolerance  # noqa: F401  (host-only parameter selection)
 
 
 def __getattr__(name):

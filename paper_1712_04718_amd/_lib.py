@@ -32,7 +32,12 @@ EXPORTS = (
     "se_plan_create", "se_plan_set_stream", "se_plan_eta", "se_plan_destroy",
     "se_forward", "se_gather", "se_kspace", "se_backward", "se_plan_stage_times",
     "se_rs_plan_create", "se_rs_plan_set_stream", "se_rs_eval", "se_rs_plan_destroy",
+    "se_est_real_error", "se_est_fourier_error", "se_est_xi", "se_est_kinf",
+    "se_est_se_error", "se_est_se_support", "se_cost_model_mi355x", "se_cost_predict",
+    "se_choose_params",
 )
+
+EST_KINDS = {"potential": 0, "energy": 1, "force": 2}
 
 
 class SeParams(ctypes.Structure):
@@ -45,6 +50,22 @@ class SeParams(ctypes.Structure):
         ("window", ctypes.c_int),
         ("dtype", ctypes.c_int),
         ("flags", ctypes.c_uint),
+    ]
+
+
+class SeCostModel(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "real_fixed", "real_atom", "real_pair", "real_cell", "real_test",
+        "k_fixed", "k_atom", "k_window", "k_block", "k_grid", "k_fft")]
+
+
+class SeChoice(ctypes.Structure):
+    _fields_ = [
+        ("rc", ctypes.c_double), ("xi", ctypes.c_double), ("kinf", ctypes.c_double),
+        ("M", ctypes.c_int), ("P", ctypes.c_int), ("eta", ctypes.c_double),
+        ("t_real", ctypes.c_double), ("t_kspace", ctypes.c_double),
+        ("est_real", ctypes.c_double), ("est_fourier", ctypes.c_double),
+        ("est_approx", ctypes.c_double),
     ]
 
 
@@ -104,6 +125,21 @@ def load() -> ctypes.CDLL:
     lib.se_rs_eval.argtypes = [vp, i, vp, vp, vp, vp, vp]
     lib.se_rs_plan_destroy.restype = i
     lib.se_rs_plan_destroy.argtypes = [vp]
+    pd = ctypes.POINTER(d)
+    for name in ("se_est_real_error", "se_est_fourier_error", "se_est_xi", "se_est_kinf"):
+        getattr(lib, name).restype = i
+        getattr(lib, name).argtypes = [i, d, d, d, d, pd]
+    lib.se_est_se_error.restype = i
+    lib.se_est_se_error.argtypes = [i, d, d, d, i, d, pd]
+    lib.se_est_se_support.restype = i
+    lib.se_est_se_support.argtypes = [i, d, d, d, d, d, ctypes.POINTER(i)]
+    lib.se_cost_model_mi355x.restype = i
+    lib.se_cost_model_mi355x.argtypes = [i, ctypes.POINTER(SeCostModel)]
+    lib.se_cost_predict.restype = i
+    lib.se_cost_predict.argtypes = [ctypes.POINTER(SeCostModel), i, i, d, d, i, i, pd, pd]
+    lib.se_choose_params.restype = i
+    lib.se_choose_params.argtypes = [i, d, i, d, d, d, d, i, d, i, ctypes.POINTER(SeCostModel),
+                                     ctypes.POINTER(SeChoice)]
     _lib = lib
     return lib
 

@@ -1,7 +1,8 @@
 """Build libsekspace.so (the HIP library behind include/sekspace.h) for gfx950.
 
-Every .hip file under csrc/ is compiled with hipcc into an object under
-_build/ (in parallel), then linked into paper_1712_04718_amd/libsekspace.so.
+Every .hip file (device code) and .cpp file (host code) under csrc/ is
+compiled with hipcc into an object under _build/ (in parallel), then linked
+into paper_1712_04718_amd/libsekspace.so.
 """
 from __future__ import annotations
 
@@ -41,7 +42,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"

@@ -247,6 +247,10 @@ void free_all(se_plan &pl) {
 }  // namespace
 
 namespace sek {
+// Tile edge a plan with these parameters uses (0: none fits); the runtime
+// model of the parameter selection prices the tile blocks with it.
+int tile_edge_of(const se_params &p) { return choose_tile(p); }
+
 se_status report(se_status s, const char *msg) {
   g_last_error = msg;
   return s;

@@ -44,75 +44,198 @@ namespace sek {
 namespace {
 
 constexpr int kRsThreads = 256;
+constexpr int kQueue = 64;   // pair queue entries per thread (16-bit stage indices)
+constexpr int kBatch = 8;    // LDS reads issued together in the test and evaluation loops
 
 template <typename R> struct alignas(4 * sizeof(R)) Staged {
   R x, y, z, q;  // position relative to the home cell's corner (cell units), charge
 };
 
-template <typename R> __device__ inline R erfc_r(R v);
-template <> __device__ inline float erfc_r<float>(float v) { return erfcf(v); }
-template <> __device__ inline double erfc_r<double>(double v) { return erfc(v); }
-template <typename R> __device__ inline R exp_r(R v);
-template <> __device__ inline float exp_r<float>(float v) { return expf(v); }
-template <> __device__ inline double exp_r<double>(double v) { return exp(v); }
+// Staged neighbours per pass: 32 KB of LDS in either precision.
+template <typename R> constexpr int kStageCap = 32768 / sizeof(Staged<R>);
 
+// FP32 erfc(x) for x >= 0 from e2 = e^{-x^2}: e2 t sum a_i t^i, t = 1/(1 + p x)
+// (the form of Abramowitz-Stegun 7.1.26 with eight terms fitted for relative
+// accuracy 5.7e-8 on [0, 8]; coefficients printed by csrc/erfc_fit.py).
+__device__ inline float erfc_from_exp(float x, float e2) {
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+  float s = -1.445127714e-01f;
+  s = fmaf(s, t, 5.111943020e-01f);
+  s = fmaf(s, t, -4.318033468e-01f);
+  s = fmaf(s, t, 4.781717052e-01f);
+  s = fmaf(s, t, 1.147496118e-02f);
+  s = fmaf(s, t, 2.104277537e-01f);
+  s = fmaf(s, t, 1.799369890e-01f);
+  s = fmaf(s, t, 1.851103503e-01f);
+  return e2 * t * s;
+}
+
+// One pair in range: adds q_n erfc(xi r)/r to ph and
+// q_n (2 xi/sqrt(pi) e^{-xi^2 r^2} + erfc(xi r)/r) r_vec / r^2 to f.
+__device__ inline void pair_term(float rx, float ry, float rz, float r2, float qn, float xi,
+                                 float c2, float &ph, float &fx, float &fy, float &fz) {
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float x = xi * r2 * rinv;
+  const float e2 = __expf(-x * x);
+  const float ec = erfc_from_exp(x, e2) * rinv;
+  ph = fmaf(qn, ec, ph);
+  const float fr = qn * fmaf(c2, e2, ec) * rinv * rinv;
+  fx = fmaf(fr, rx, fx);
+  fy = fmaf(fr, ry, fy);
+  fz = fmaf(fr, rz, fz);
+}
+
+__device__ inline void pair_term(double rx, double ry, double rz, double r2, double qn, double xi,
+                                 double c2, double &ph, double &fx, double &fy, double &fz) {
+  const double r = sqrt(r2);
+  const double ec = erfc(xi * r) / r;
+  ph += qn * ec;
+  const double fr = qn * (c2 * exp(-xi * xi * r2) + ec) / r2;
+  fx += fr * rx;
+  fy += fr * ry;
+  fz += fr * rz;
+}
+
+// One work-group per cell.  The particles of the 27 neighbour cells (home
+// cell included) are staged in LDS, in passes of kStageCap.  Home particles
+// take nhp = min(nh, 256) lanes, and the other lanes take the same home
+// particles again: G = 256 / nhp slices of the staged range per home particle,
+// summed at the end.  Each thread first tests its candidates (distance only)
+// and queues the indices of the pairs in range in LDS; the wave evaluates the
+// queued pairs together once some lane's queue could overflow, so the erfc and
+// exp run on full waves instead of on every tested pair under a mask.
 template <typename R>
 __global__ void __launch_bounds__(kRsThreads)
 k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ meta,
            const int *__restrict__ offsets, int nc, R cs, R xi, R rc2, R *__restrict__ phi,
            R *__restrict__ F, double *__restrict__ epart) {
-  __shared__ Staged<R> stage[kRsThreads];
+  constexpr int CAP = kStageCap<R>;
+  __shared__ Staged<R> stage[CAP];
+  __shared__ unsigned short queue[kQueue * kRsThreads];
+  __shared__ int nb_src[27], nb_pre[28];
+  __shared__ R red[4][kRsThreads];
+  __shared__ double ered[kRsThreads / 64];
   const int tid = threadIdx.x;
   const int cell = xcd_local(blockIdx.x, gridDim.x);
   const int cz = cell / (nc * nc), cy = (cell / nc) % nc, cx = cell % nc;
-  const int h0 = offsets[cell], h1 = offsets[cell + 1];
+  if (tid < 27) {
+    const int oz = tid / 9 - 1, oy = (tid / 3) % 3 - 1, ox = tid % 3 - 1;
+    const int nz = cz + oz < 0 ? cz + oz + nc : (cz + oz >= nc ? cz + oz - nc : cz + oz);
+    const int ny = cy + oy < 0 ? cy + oy + nc : (cy + oy >= nc ? cy + oy - nc : cy + oy);
+    const int nx = cx + ox < 0 ? cx + ox + nc : (cx + ox >= nc ? cx + ox - nc : cx + ox);
+    const int nb = (nz * nc + ny) * nc + nx;
+    nb_src[tid] = offsets[nb];
+    nb_pre[tid + 1] = offsets[nb + 1] - offsets[nb];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    nb_pre[0] = 0;
+    for (int k = 0; k < 27; ++k) nb_pre[k + 1] += nb_pre[k];
+  }
+  __syncthreads();
+  const int S = nb_pre[27];
+  const int home0 = nb_pre[13];          // home cell (offset 0,0,0) in the staged order
+  const int nh = nb_pre[14] - home0;
+  const int hsrc = nb_src[13];
   const R c2 = static_cast<R>(1.1283791670955126) * xi;  // 2 xi / sqrt(pi)
   double e = 0.0;
-  for (int hb = h0; hb < h1; hb += kRsThreads) {  // uniform across the work-group
-    const int i = hb + tid;
-    const bool mine = i < h1;
-    SortedParticle<R> pi{};
-    if (mine) pi = sorted[i];
+
+  for (int hb = 0; hb < nh; hb += kRsThreads) {  // uniform across the work-group
+    const int nhp = min(kRsThreads, nh - hb);
+    const int G = kRsThreads / nhp;
+    const int hi = tid % nhp, sl = tid / nhp;
+    const bool active = sl < G;
+    const SortedParticle<R> pi = sorted[hsrc + hb + hi];
+    const int self = home0 + hb + hi;
     R ph = R(0), fx = R(0), fy = R(0), fz = R(0);
-    for (int oz = -1; oz <= 1; ++oz)
-      for (int oy = -1; oy <= 1; ++oy)
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int nz = cz + oz < 0 ? cz + oz + nc : (cz + oz >= nc ? cz + oz - nc : cz + oz);
-          const int ny = cy + oy < 0 ? cy + oy + nc : (cy + oy >= nc ? cy + oy - nc : cy + oy);
-          const int nx = cx + ox < 0 ? cx + ox + nc : (cx + ox >= nc ? cx + ox - nc : cx + ox);
-          const int nb = (nz * nc + ny) * nc + nx;
-          const int n0 = offsets[nb], n1 = offsets[nb + 1];
-          const bool home = oz == 0 && oy == 0 && ox == 0;
-          for (int nbb = n0; nbb < n1; nbb += kRsThreads) {
-            __syncthreads();  // previous batch consumed
-            const int j = nbb + tid;
-            if (j < n1) {
-              const SortedParticle<R> sj = sorted[j];
-              stage[tid] = Staged<R>{static_cast<R>(ox) + sj.dx, static_cast<R>(oy) + sj.dy,
-                                     static_cast<R>(oz) + sj.dz, sj.q};
-            }
-            __syncthreads();
-            const int cnt = min(kRsThreads, n1 - nbb);
-            if (mine) {
-              for (int k = 0; k < cnt; ++k) {
-                const Staged<R> s = stage[k];
-                const R rx = (pi.dx - s.x) * cs, ry = (pi.dy - s.y) * cs, rz = (pi.dz - s.z) * cs;
-                const R r2 = rx * rx + ry * ry + rz * rz;
-                if (r2 < rc2 && !(home && nbb + k == i)) {
-                  const R r = sqrt(r2);
-                  const R ec = erfc_r(xi * r) / r;
-                  ph += s.q * ec;
-                  const R fr = s.q * (c2 * exp_r(-xi * xi * r2) + ec) / r2;
-                  fx += fr * rx;
-                  fy += fr * ry;
-                  fz += fr * rz;
-                }
-              }
+    for (int c0 = 0; c0 < S; c0 += CAP) {
+      const int cn = min(CAP, S - c0);
+      __syncthreads();  // previous pass consumed
+      {
+        // stage this pass: all loads issued before the first LDS store
+        constexpr int PER = CAP / kRsThreads;
+        SortedParticle<R> buf[PER];
+        int kk[PER];
+        int k = 0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int j = c0 + tid + u * kRsThreads;
+          kk[u] = -1;
+          if (j < c0 + cn) {
+            while (nb_pre[k + 1] <= j) ++k;
+            kk[u] = k;
+            buf[u] = sorted[nb_src[k] + (j - nb_pre[k])];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          if (kk[u] >= 0) {
+            const int kc = kk[u];
+            stage[tid + u * kRsThreads] =
+                Staged<R>{static_cast<R>(kc % 3 - 1) + buf[u].dx,
+                          static_cast<R>((kc / 3) % 3 - 1) + buf[u].dy,
+                          static_cast<R>(kc / 9 - 1) + buf[u].dz, buf[u].q};
+          }
+        }
+      }
+      __syncthreads();
+      // this thread's slice of the pass
+      const int lo = active ? sl * cn / G : 0, hi_end = active ? (sl + 1) * cn / G : 0;
+      const int self_l = self - c0;
+      int qn = 0;
+      auto flush = [&]() {
+        for (int m0 = 0; __any(m0 < qn); m0 += kBatch) {
+          int idx[kBatch];
+#pragma unroll
+          for (int u = 0; u < kBatch; ++u)
+            idx[u] = queue[((m0 + u) >> 1) * (2 * kRsThreads) + 2 * tid + ((m0 + u) & 1)];
+          Staged<R> c[kBatch];
+#pragma unroll
+          for (int u = 0; u < kBatch; ++u) c[u] = stage[min(idx[u], cn - 1)];
+#pragma unroll
+          for (int u = 0; u < kBatch; ++u) {
+            if (m0 + u < qn) {
+              const R rx = (pi.dx - c[u].x) * cs, ry = (pi.dy - c[u].y) * cs,
+                      rz = (pi.dz - c[u].z) * cs;
+              pair_term(rx, ry, rz, rx * rx + ry * ry + rz * rz, c[u].q, xi, c2, ph, fx, fy, fz);
             }
           }
         }
-    if (mine) {
-      const int orig = meta[i].y;
+        qn = 0;
+      };
+      for (int k0 = lo; __any(k0 < hi_end); k0 += kBatch) {
+        Staged<R> c[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) c[u] = stage[min(k0 + u, cn - 1)];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const int idx = k0 + u;
+          const R rx = (pi.dx - c[u].x) * cs, ry = (pi.dy - c[u].y) * cs, rz = (pi.dz - c[u].z) * cs;
+          const R r2 = rx * rx + ry * ry + rz * rz;
+          const bool hit = idx < hi_end && r2 < rc2 && idx != self_l;
+          // the free slot qn is written either way; only a hit keeps it
+          queue[(qn >> 1) * (2 * kRsThreads) + 2 * tid + (qn & 1)] = static_cast<unsigned short>(idx);
+          qn += hit ? 1 : 0;
+        }
+        if (__any(qn > kQueue - kBatch)) flush();
+      }
+      flush();
+    }
+    // sum the slices of each home particle
+    __syncthreads();
+    red[0][tid] = ph;
+    red[1][tid] = fx;
+    red[2][tid] = fy;
+    red[3][tid] = fz;
+    __syncthreads();
+    if (sl == 0) {
+      for (int g = 1; g < G; ++g) {
+        ph += red[0][g * nhp + hi];
+        fx += red[1][g * nhp + hi];
+        fy += red[2][g * nhp + hi];
+        fz += red[3][g * nhp + hi];
+      }
+      const int orig = meta[hsrc + hb + hi].y;
       if (phi) phi[orig] = ph;
       if (F) {
         F[3 * orig + 0] = pi.q * fx;
@@ -124,12 +247,11 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
   }
   // energy partial of this cell (fixed order)
   for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
-  __shared__ double red[kRsThreads / 64];
-  if ((tid & 63) == 0) red[tid >> 6] = e;
+  if ((tid & 63) == 0) ered[tid >> 6] = e;
   __syncthreads();
   if (tid == 0) {
     double s = 0.0;
-    for (int w = 0; w < kRsThreads / 64; ++w) s += red[w];
+    for (int w = 0; w < kRsThreads / 64; ++w) s += ered[w];
     epart[cell] = s;
   }
 }

@@ -1,0 +1,265 @@
+"""Parameters from a tolerance: the oracle pinned against the paper, and the
+library's host functions (se_est_*, se_choose_params) against the oracle.
+
+CPU only: the estimate and selection functions are host code of the library
+(loading it needs no GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import se_tolerance as O
+
+KINDS = O.KINDS
+# section 7: 81,000 uniform charges of unit magnitude in a box of side 9.3222
+N81, L81 = 81_000, 9.3222
+Q81 = float(N81)
+
+
+# ------------------------------------------------------------- oracle pins
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("rc,eps", [(0.5, 1e-3), (1.0, 1e-8), (3.0, 1e-5), (0.9, 1e-12)])
+def test_xi_inversion_meets_real_estimate(kind, rc, eps):
+    """Eq. 2.3 inverts eq. 2.1: the real-space estimate at xi(eps) is eps."""
+    xi = O.xi_for(kind, eps, Q81, L81, rc)
+    assert abs(O.real_error(kind, Q81, L81, xi, rc) / eps - 1) < 1e-12
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("xi,eps", [(2.0, 1e-3), (6.75, 1e-5), (6.31, 1e-12), (0.3, 1e-8)])
+def test_kinf_inversion_meets_fourier_estimate(kind, xi, eps):
+    """Eq. 2.4 inverts eq. 2.2: the Fourier estimate at k_inf(eps) is eps."""
+    k = O.kinf_for(kind, eps, Q81, L81, xi)
+    assert abs(O.fourier_error(kind, Q81, L81, xi, k) / eps - 1) < 1e-11
+
+
+def test_printed_optimal_pairs_agree_with_force_estimate():
+    """Section 7 reports the cheapest (xi, rc) for 81,000 charges as
+    (6.75, 0.60) at a relative force error of 1e-5 and (6.31, 0.90) at 1e-12.
+    Both pairs lie on the real-space force estimate (eq. 2.1c) for one rms
+    force: the absolute tolerance implied by the first pair, scaled by 1e-7,
+    gives back xi = 6.31 at rc = 0.90 through eq. 2.3c (printed to 3 digits)."""
+    eps1 = O.real_error("force", Q81, L81, 6.75, 0.60)
+    xi2 = O.xi_for("force", eps1 * 1e-7, Q81, L81, 0.90)
+    assert abs(xi2 - 6.31) < 0.01
+    # and back: the pair's ratio of estimates is the ratio of the tolerances
+    eps2 = O.real_error("force", Q81, L81, 6.31, 0.90)
+    assert 0.9e7 < eps1 / eps2 < 1.1e7
+
+
+def test_ordering_stated_after_eq_2_4():
+    """For fixed rc and eps, xi_phi <= xi_E <= xi_F; for fixed xi and eps,
+    k_phi is the smallest of the three (section 2.1, after eq. 2.4)."""
+    for rc, eps in [(0.6, 5e-4), (0.9, 6e-11), (1.2, 1e-6)]:
+        xp, xe, xf = (O.xi_for(k, eps, Q81, L81, rc) for k in KINDS)
+        assert xp <= xe <= xf
+    for xi, eps in [(6.75, 5e-4), (6.31, 6e-11)]:
+        kp, ke, kf = (O.kinf_for(k, eps, Q81, L81, xi) for k in KINDS)
+        assert kp <= ke and kp <= kf
+
+
+def test_support_from_relative_error_remark():
+    """Closing remark of section 5.3: P = 10 and 20 bring the relative
+    approximation error e^{-pi P c^2/2} (c = 0.95) below 1e-6 and 1e-12.  For
+    1e-15 the remark's P = 24 gives 1.7e-15, so the even P meeting 1e-15
+    strictly is 26 (the remark rounds)."""
+    assert O.se_support_for_relative(1e-6) == 10
+    assert O.se_support_for_relative(1e-12) == 20
+    assert O.se_support_for_relative(1e-15) == 26
+    assert 1.0e-15 < math.exp(-math.pi * 24 * 0.95 ** 2 / 2) < 2e-15
+
+
+def test_force_amplitude_follows_from_potential_amplitude():
+    """Section 5.3 derives A_F from A_phi: (1/2) sqrt(Q) (m^2/w) A_phi with
+    m^2 = pi P c^2 -> pi P and w = P/(8 xi) gives 4 pi Q sqrt(xi^3/L)."""
+    for xi, L, Q in [(0.3, 100.0, 3.6e4), (6.75, 9.3222, 8.1e4)]:
+        P = 8
+        m2, w = math.pi * P, P / (8 * xi)
+        derived = 0.5 * math.sqrt(Q) * (m2 / w) * O.se_amplitude("potential", Q, L, xi)
+        assert abs(derived / O.se_amplitude("force", Q, L, xi) - 1) < 1e-12
+
+
+def _sizes():
+    out = []
+    for m in range(8, 513, 2):
+        r = m
+        for f in (2, 3, 5):
+            while r % f == 0:
+                r //= f
+        if r == 1:
+            out.append(m)
+    return out
+
+
+def test_choice_is_cheapest_feasible_by_exhaustive_search():
+    """The selection (eqs. 2.3-2.4, section 5, section 7 model) against a
+    search that uses only the forward estimates: for every cutoff and every xi
+    of a fine grid, the smallest M and P whose estimates meet eps; no
+    combination the search finds is cheaper than the selection."""
+    sizes = _sizes()
+    rcs = np.linspace(0.4, 1.6, 25)
+    for kind, eps in [("force", 5.5e-4), ("potential", 1e-6)]:
+        ch = O.choose(kind, eps, N81, Q81, L81, rcs, sizes, O.PAPER_CPU_MODEL, P_max=30)
+        assert ch is not None
+        best = math.inf
+        for rc in rcs:
+            for xi in np.linspace(1.0, 15.0, 1401):
+                if O.real_error(kind, Q81, L81, xi, rc) > eps:
+                    continue
+                P = next((p for p in range(4, 31, 2)
+                          if O.se_approx_error(kind, Q81, L81, xi, p) <= eps), None)
+                if P is None:
+                    continue
+                M = next((m for m in sizes
+                          if O.fourier_error(kind, Q81, L81, xi, m / 2) <= eps
+                          and P * L81 ** 2 * xi ** 2 / (0.95 ** 2 * math.pi * m * m) < 1), None)
+                if M is None:
+                    continue
+                best = min(best, sum(O.runtime_estimate(O.PAPER_CPU_MODEL, N81, L81, rc, M, P)))
+        t = ch["t_real"] + ch["t_fourier"]
+        assert best >= t * (1 - 1e-12)
+        assert best <= t * 1.05  # the xi grid lands next to the selection's xi
+
+
+# ------------------------------------------------ library host functions
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_1712_04718_amd import tolerance
+    return tolerance
+
+
+VALUES = [(Q, L, xi, r) for Q, L in [(8.1e4, 9.3222), (3.6e4, 100.0), (1e6, 220.0)]
+          for xi in (0.3, 2.0, 6.75) for r in (0.6, 3.0, 10.0)]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_library_estimates_match_oracle(T, kind):
+    for Q, L, xi, r in VALUES:
+        assert T.real_error(kind, Q, L, xi, r) == pytest.approx(
+            O.real_error(kind, Q, L, xi, r), rel=1e-13, abs=0)
+        kinf = r * 4
+        assert T.fourier_error(kind, Q, L, xi, kinf) == pytest.approx(
+            O.fourier_error(kind, Q, L, xi, kinf), rel=1e-13, abs=0)
+        for P in (4, 8, 16):
+            assert T.se_error(kind, Q, L, xi, P) == pytest.approx(
+                O.se_approx_error(kind, Q, L, xi, P), rel=1e-13)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_library_inversions_match_oracle(T, kind):
+    for Q, L, _, rc in VALUES:
+        for eps in (1e-2, 1e-5, 1e-9, 1e-14):
+            try:
+                xo = O.xi_for(kind, eps, Q, L, rc)
+            except ValueError:  # log of a negative number: any xi meets eps
+                continue
+            xi = T.xi_for(kind, eps, Q, L, rc)
+            assert xi == pytest.approx(xo, rel=1e-13)
+            assert T.kinf_for(kind, eps, Q, L, xi) == pytest.approx(
+                O.kinf_for(kind, eps, Q, L, xi), rel=1e-12)
+            assert T.se_support_for(kind, eps, Q, L, xi) == O.se_support_for(kind, eps, Q, L, xi)
+
+
+def test_library_lambert_w_far_beyond_double_range(T):
+    """W arguments formed in logarithms: eps = 1e-80 (argument ~1e330 for the
+    force k_inf) still meets eq. 2.2 exactly."""
+    Q, L, xi = 1e6, 220.0, 0.35
+    k = T.kinf_for("force", 1e-80, Q, L, xi)
+    assert T.fourier_error("force", Q, L, xi, k) == pytest.approx(1e-80, rel=1e-10)
+
+
+@pytest.mark.parametrize("kind,eps", [("force", 5.5e-4), ("force", 2e-3), ("potential", 1e-6),
+                                      ("energy", 1e-3)])
+def test_library_choice_matches_oracle_on_paper_model(T, kind, eps):
+    lo, hi, n = 0.4, 1.6, 97
+    ch = T.choose_params(kind, eps, N81, Q81, L81, (lo, hi), n_rc=n, model=T.paper_cpu_model())
+    ref = O.choose(kind, eps, N81, Q81, L81, np.linspace(lo, hi, n), _sizes(),
+                   O.PAPER_CPU_MODEL, eta_max=0.5)
+    assert (ch["M"], ch["P"]) == (ref["M"], ref["P"])
+    assert ch["rc"] == pytest.approx(ref["rc"], rel=1e-15)
+    assert ch["xi"] == pytest.approx(ref["xi"], rel=1e-13)
+    assert ch["t_real"] + ch["t_kspace"] == pytest.approx(ref["t_real"] + ref["t_fourier"],
+                                                          rel=1e-12)
+    assert ch["est_real"] <= eps * (1 + 1e-12)
+    assert ch["est_fourier"] <= eps and ch["est_approx"] <= eps
+    assert ch["eta"] <= 0.5
+
+
+def test_library_choice_with_gpu_terms(T):
+    """Fixed, per-atom and per-tested-pair terms: the choice is the argmin of
+    the model written out here over the same cutoffs."""
+    model = dict(real_fixed=2e-5, real_atom=1e-10, real_pair=0.0, real_cell=3e-8, real_test=2e-12,
+                 k_fixed=6e-5, k_atom=1e-10, k_window=5e-13, k_block=0.0, k_grid=1e-11,
+                 k_fft=2e-13)
+    N, L = 100_200, 100.0
+    Q = 33_400 * (0.8476 ** 2 + 2 * 0.4238 ** 2)
+    eps = 1e-2
+    ch = T.choose_params("force", eps, N, Q, L, (4.0, 30.0), n_rc=53, model=model)
+    best = None
+    for rc in np.linspace(4.0, 30.0, 53):
+        if 3 * rc > L:
+            continue
+        xi = O.xi_for("force", eps, Q, L, rc)
+        k = O.kinf_for("force", eps, Q, L, xi)
+        P = max(4, O.se_support_for("force", eps, Q, L, xi))
+        if P > 16:
+            continue
+        M = next((m for m in _sizes() if m >= 2 * k
+                  and P * L * L * xi * xi / (0.95 ** 2 * math.pi * m * m) <= 0.5), None)
+        if M is None:
+            continue
+        nc = min(math.floor(L / rc), 64)
+        ntest = 27 * (L / nc) ** 3 * N / L ** 3
+        q = math.ceil(nc ** 3 / 512) * 512 / nc ** 3
+        t = (model["real_fixed"] + model["real_atom"] * N + model["real_cell"] * nc ** 3
+             + model["real_test"] * N * ntest * q
+             + model["k_fixed"] + model["k_atom"] * N + model["k_window"] * N * P ** 3
+             + model["k_grid"] * M ** 3 + model["k_fft"] * M ** 3 / 2 * math.log(M ** 3 / 2))
+        if best is None or t < best[0]:
+            best = (t, rc, M, P)
+    assert ch["t_real"] + ch["t_kspace"] == pytest.approx(best[0], rel=1e-12)
+    assert (ch["rc"], ch["M"], ch["P"]) == (pytest.approx(best[1], rel=1e-14), best[2], best[3])
+
+
+def test_library_cost_terms(T):
+    """Each term of se_cost_predict alone, at water-like sizes: M = 96, P = 8
+    in FP32 uses 12^3 tiles of edge 12 (blocks of 19^3 points); rc = 10 in
+    L = 100 gives 10^3 cells of edge 10."""
+    N, L, rc, M, P = 100_200, 100.0, 10.0, 96, 8
+    names = [n for n, _ in __import__("paper_1712_04718_amd._lib", fromlist=["x"]).SeCostModel._fields_]
+    want = {"real_fixed": (1, 0), "real_atom": (N, 0),
+            "real_pair": (N * 4 / 3 * math.pi * rc ** 3 * N / L ** 3, 0),
+            "real_cell": (1000, 0), "real_test": (N * 27 * 1000 * N / L ** 3 * 1024 / 1000, 0),
+            "k_fixed": (0, 1), "k_atom": (0, N), "k_window": (0, N * 512),
+            "k_block": (0, 512 * 19 ** 3), "k_grid": (0, M ** 3),
+            "k_fft": (0, M ** 3 / 2 * math.log(M ** 3 / 2))}
+    for n in names:
+        unit = {k: 0.0 for k in names}
+        unit[n] = 1.0
+        tr, tk = T.predict(unit, "f32", N, L, rc, M, P)
+        assert (tr, tk) == (pytest.approx(want[n][0], rel=1e-12), pytest.approx(want[n][1], rel=1e-12)), n
+
+
+def test_library_argument_errors(T):
+    from paper_1712_04718_amd._lib import SeError
+    bad = [lambda: T.real_error("force", -1.0, 10.0, 1.0, 1.0),
+           lambda: T.fourier_error("force", 1.0, 10.0, 1.0, 0.0),
+           lambda: T.xi_for("force", 1e9, 1.0, 10.0, 1.0),  # tolerance above the xi = 0 estimate
+           lambda: T.kinf_for("energy", float("nan"), 1.0, 10.0, 1.0),
+           lambda: T.se_support_for("force", 1e-300, 1e6, 10.0, 5.0),  # needs P > 64
+           lambda: T.choose_params("force", 1e-3, 0, 1.0, 10.0, (1.0, 2.0)),
+           lambda: T.choose_params("force", 1e-3, 10, 1.0, 10.0, (2.0, 1.0))]
+    for f in bad:
+        with pytest.raises(SeError, match="SE_ERR_ARG"):
+            f()
+    with pytest.raises(SeError, match="SE_ERR_UNSUPPORTED"):  # every cutoff above L/3
+        T.choose_params("force", 1e-3, 1000, 1000.0, 10.0, (4.0, 5.0), n_rc=3,
+                        model=T.paper_cpu_model())
+    import ctypes
+    from paper_1712_04718_amd import _lib
+    mdl, ch = _lib.SeCostModel(), _lib.SeChoice()
+    st = _lib.load().se_choose_params(2, 1e-3, 1000, 1000.0, 10.0, 1.0, 2.0, 3, 0.95, 7,
+                                      ctypes.byref(mdl), ctypes.byref(ch))
+    assert _lib.STATUS_NAMES[st] == "SE_ERR_ARG"  # unknown dtype
