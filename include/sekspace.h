@@ -166,6 +166,21 @@ se_status se_kspace(se_plan *plan, int N, const void *x, const void *q,
 se_status se_backward(se_plan *plan, const double *gE_dev, void *grad_x,
                       void *grad_q);
 
+/* Evaluation at points that are not sources.  Reserve room for up to nt_max
+ * points (allocates; synchronises the plan's stream first).  SE_ERR_ARG if
+ * nt_max < 1. */
+se_status se_plan_reserve_targets(se_plan *plan, int nt_max);
+
+/* The k-space potential and field of the charges of the last se_forward at
+ * nt points xt (device [nt][3], plan dtype, wrapped periodically): a unit
+ * test charge at each point gathers phi_t = sum_j Phi_j W(x_j - xt) (eq. 4.9,
+ * no self term) and field_t = -grad phi_t (the force of eq. 4.12 per unit
+ * charge), with the window and grid of the plan.  phi_t (device [nt]) or
+ * field_t (device [nt][3]) may be NULL.  SE_ERR_STATE before the first
+ * se_forward; SE_ERR_ARG if nt exceeds the reserved count.  Sources, the
+ * stored grid and se_gather/se_backward are not affected. */
+se_status se_eval_targets(se_plan *plan, int nt, const void *xt, void *phi_t, void *field_t);
+
 /* ------------------------------------------------------------------------
  * Real-space part of the Ewald sums (section 1, eqs. 1.5-1.7, the erfc
  * terms), truncated at |r| < rc with the nearest periodic image:

@@ -31,6 +31,7 @@ EXPORTS = (
     "se_status_string", "se_last_error", "se_params_check", "se_plan_workspace_size",
     "se_plan_create", "se_plan_set_stream", "se_plan_eta", "se_plan_destroy",
     "se_forward", "se_gather", "se_kspace", "se_backward", "se_plan_stage_times",
+    "se_plan_reserve_targets", "se_eval_targets",
     "se_rs_plan_create", "se_rs_plan_set_stream", "se_rs_eval", "se_rs_plan_destroy",
     "se_est_real_error", "se_est_fourier_error", "se_est_xi", "se_est_kinf",
     "se_est_se_error", "se_est_se_support", "se_cost_model_mi355x", "se_cost_predict",
@@ -115,6 +116,10 @@ def load() -> ctypes.CDLL:
     lib.se_kspace.argtypes = [vp, i, vp, vp, vp, vp, vp]
     lib.se_backward.restype = i
     lib.se_backward.argtypes = [vp, vp, vp, vp]
+    lib.se_plan_reserve_targets.restype = i
+    lib.se_plan_reserve_targets.argtypes = [vp, i]
+    lib.se_eval_targets.restype = i
+    lib.se_eval_targets.argtypes = [vp, i, vp, vp, vp]
     lib.se_plan_stage_times.restype = i
     lib.se_plan_stage_times.argtypes = [vp, ctypes.POINTER(d), i]
     lib.se_rs_plan_create.restype = i

@@ -118,6 +118,26 @@ class SEPlan:
         self._keep_g = gE
         return gx, gq
 
+    def eval_targets(self, xt, want_phi=True, want_field=True):
+        """(phi [nt], field [nt,3]) of the charges of the last forward pass at
+        the points xt [nt,3] (unit test charges, no self term)."""
+        if self._N is None:
+            raise RuntimeError("eval_targets before forward")
+        if xt.device != self.device or xt.dtype != self.dtype or xt.dim() != 2 or xt.shape[1] != 3:
+            raise ValueError(f"xt must be [nt,3] {self.dtype} on {self.device}")
+        xt = xt.contiguous()
+        nt = int(xt.shape[0])
+        if nt > getattr(self, "_tcap", 0):
+            _lib.check(self.lib.se_plan_reserve_targets(self._plan, max(nt, 1)))
+            self._tcap = max(nt, 1)
+        phi = torch.empty(nt, dtype=self.dtype, device=self.device) if want_phi else None
+        field = torch.empty(nt, 3, dtype=self.dtype, device=self.device) if want_field else None
+        with torch.cuda.device(self.device):
+            self._bind_stream()
+            _lib.check(self.lib.se_eval_targets(self._plan, nt, _ptr(xt), _ptr(phi), _ptr(field)))
+        self._keep_t = xt
+        return phi, field
+
     def stage_times(self):
         """{stage: mean milliseconds per launch} over the launches since the
         previous call (plans created with ``timing=True``); waits for them."""

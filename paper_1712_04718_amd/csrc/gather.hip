@@ -293,19 +293,26 @@ hipError_t gather_one(se_plan &p, const double *gscale, int mode, void *pot, voi
   const size_t lds = GatherLds<R, WIN, S, T>::TOTAL;
   const double dcoef = (WIN == kGauss) ? 2.0 * p.a * p.h : 1.0 / p.h;
   const WindowConsts wc = window_consts(p.cg, p.beta, dcoef);
-  const double self = (p.prm.flags & SE_FLAG_ADD_SELF) ? -2.0 * p.prm.xi / sqrt(M_PI) : 0.0;
+  // evaluation points of se_eval_targets are unit test charges in their own
+  // tile order, without the self term
+  const bool tgt = mode == kGatherTargets;
+  const double self =
+      (!tgt && (p.prm.flags & SE_FLAG_ADD_SELF)) ? -2.0 * p.prm.xi / sqrt(M_PI) : 0.0;
+  const void *sorted = tgt ? p.tgt.sorted : p.buf.sorted;
+  const int2 *meta = tgt ? p.tgt.meta : p.buf.meta;
+  const int *offsets = tgt ? p.tgt.offsets : p.buf.offsets;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gather<R, WIN, S, T>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
-  stage_begin(p, SE_STAGE_GATHER);
+  if (!tgt) stage_begin(p, SE_STAGE_GATHER);
   k_gather<R, WIN, S, T><<<p.ntiles, kTileThreads, lds, p.stream>>>(
-      static_cast<const R *>(p.buf.grid), static_cast<const SortedParticle<R> *>(p.buf.sorted),
-      p.buf.meta, p.buf.offsets, p.prm.M, p.ntx, wc, gscale, mode, static_cast<R>(self),
-      static_cast<R *>(pot), static_cast<R *>(vec));
-  stage_end(p, SE_STAGE_GATHER);
+      static_cast<const R *>(p.buf.grid), static_cast<const SortedParticle<R> *>(sorted), meta,
+      offsets, p.prm.M, p.ntx, wc, gscale, tgt ? kGatherPotentialForce : mode,
+      static_cast<R>(self), static_cast<R *>(pot), static_cast<R *>(vec));
+  if (!tgt) stage_end(p, SE_STAGE_GATHER);
   return hipGetLastError();
 }
 

@@ -234,8 +234,17 @@ void destroy_events(se_plan &pl) {
     }
 }
 
+void free_targets(se_plan &pl) {
+  void *ptrs[] = {pl.tgt.counts, pl.tgt.offsets, pl.tgt.key, pl.tgt.meta, pl.tgt.sorted,
+                  pl.tgt.part, pl.tgt.ones};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  pl.tgt = sek::TargetBuffers{};
+}
+
 void free_all(se_plan &pl) {
   destroy_events(pl);
+  free_targets(pl);
   void *ptrs[] = {pl.buf.grid, pl.buf.ghost, pl.buf.cover, pl.buf.cover_count, pl.buf.spec,
                   pl.buf.sorted, pl.buf.meta, pl.buf.key, pl.buf.counts, pl.buf.offsets,
                   pl.buf.part, pl.buf.twiddle, pl.buf.axis_f, pl.buf.axis_k2};
@@ -466,6 +475,83 @@ se_status se_kspace(se_plan *plan, int N, const void *x, const void *q, double *
   se_status s = se_forward(plan, N, x, q, E_dev);
   if (s != SE_OK) return s;
   return se_gather(plan, phi, F);
+}
+
+se_status se_plan_reserve_targets(se_plan *plan, int nt_max) {
+  if (!plan) return fail(SE_ERR_ARG, "plan is NULL");
+  if (nt_max < 1) return fail(SE_ERR_ARG, "nt_max must be >= 1 (got %d)", nt_max);
+  hipError_t e = hipStreamSynchronize(plan->stream);  // earlier target work may use the old buffers
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  free_targets(*plan);
+  sek::TargetBuffers &t = plan->tgt;
+  const size_t rs = plan->prm.dtype == SE_FP64 ? 8 : 4;
+  const size_t n = static_cast<size_t>(nt_max);
+  struct { void **ptr; size_t bytes; } allocs[] = {
+      {reinterpret_cast<void **>(&t.counts), static_cast<size_t>(plan->ntiles) * sek::kCountStride * 4},
+      {reinterpret_cast<void **>(&t.offsets), static_cast<size_t>(plan->ntiles + 1) * 4},
+      {reinterpret_cast<void **>(&t.key), n * 8},
+      {reinterpret_cast<void **>(&t.meta), n * 8},
+      {&t.sorted, n * 4 * rs},
+      {reinterpret_cast<void **>(&t.part), ((n + sek::kThreads - 1) / sek::kThreads + 1) * 8},
+      {&t.ones, n * rs}};
+  for (auto &a : allocs) {
+    if ((e = hipMalloc(a.ptr, a.bytes)) != hipSuccess) {
+      (void)hipGetLastError();
+      free_targets(*plan);
+      return fail(SE_ERR_WORKSPACE, "hipMalloc of %zu bytes for evaluation points failed", a.bytes);
+    }
+  }
+  std::vector<double> one64;
+  std::vector<float> one32;
+  const void *src;
+  if (rs == 8) {
+    one64.assign(n, 1.0);
+    src = one64.data();
+  } else {
+    one32.assign(n, 1.0f);
+    src = one32.data();
+  }
+  e = hipMemcpy(t.ones, src, n * rs, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemset(t.counts, 0, static_cast<size_t>(plan->ntiles) * sek::kCountStride * 4);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_targets(*plan);
+    return hip_fail(e, "evaluation-point set-up");
+  }
+  t.cap = nt_max;
+  return SE_OK;
+}
+
+se_status se_eval_targets(se_plan *plan, int nt, const void *xt, void *phi_t, void *field_t) {
+  if (!plan) return fail(SE_ERR_ARG, "plan is NULL");
+  if (plan->last_N < 0) return fail(SE_ERR_STATE, "se_eval_targets before se_forward");
+  if (nt < 0 || nt > plan->tgt.cap)
+    return fail(SE_ERR_ARG, "nt=%d outside [0, reserved %d] (se_plan_reserve_targets)", nt,
+                plan->tgt.cap);
+  if (nt == 0 || (!phi_t && !field_t)) return SE_OK;
+  if (!xt) return fail(SE_ERR_ARG, "xt is NULL");
+  sek::BinJob j;
+  j.N = nt;
+  j.x = xt;
+  j.q = plan->tgt.ones;
+  j.fp64 = plan->prm.dtype == SE_FP64;
+  j.h = plan->h;
+  j.M = plan->prm.M;
+  j.T = plan->T;
+  j.ntx = plan->ntx;
+  j.ncells = plan->ntiles;
+  j.counts = plan->tgt.counts;
+  j.key = plan->tgt.key;
+  j.offsets = plan->tgt.offsets;
+  j.sorted = plan->tgt.sorted;
+  j.meta = plan->tgt.meta;
+  j.qsq_part = plan->tgt.part;
+  j.stream = plan->stream;
+  hipError_t e = sek::launch_bin_job(j, nullptr);
+  if (e != hipSuccess) return hip_fail(e, "binning evaluation points");
+  e = sek::launch_gather(*plan, nt, nullptr, sek::kGatherTargets, phi_t, field_t);
+  return e == hipSuccess ? SE_OK : hip_fail(e, "gathering at evaluation points");
 }
 
 se_status se_backward(se_plan *plan, const double *gE_dev, void *grad_x, void *grad_q) {

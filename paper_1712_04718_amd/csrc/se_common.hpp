@@ -107,6 +107,19 @@ inline hipError_t harvest_oldest(StageTimer &t) {
   return e;
 }
 
+// Binning workspace for evaluation points that are not sources
+// (se_eval_targets): cap points, sorted into the plan's tiles.
+struct TargetBuffers {
+  int cap = 0;
+  int *counts = nullptr;   // ntiles counters, kCountStride ints apart
+  int *offsets = nullptr;  // ntiles + 1
+  int2 *key = nullptr;     // cap
+  int2 *meta = nullptr;    // cap
+  void *sorted = nullptr;  // cap SortedParticle<R>
+  double *part = nullptr;  // binning partials (unused)
+  void *ones = nullptr;    // cap unit charges
+};
+
 struct DeviceBuffers {
   void *grid = nullptr;       // M^3 real: the scaled grid Phi (input of gathering)
   void *ghost = nullptr;      // ntiles * (T+S-1)^3 real: spread tile blocks
@@ -153,6 +166,7 @@ struct se_plan {
 
   sek::FftPlan fft;
   sek::DeviceBuffers buf;
+  sek::TargetBuffers tgt;
   sek::FoldTables fold;
   bool fold_by_tiles;  // tiles partition the grid: tile-structured fold
 
@@ -221,6 +235,7 @@ constexpr size_t kMaxLds = 160 * 1024;
 // gather modes
 constexpr int kGatherPotentialForce = 0;  // out_pot = phi, out_vec = F
 constexpr int kGatherAdjoint = 1;         // out_pot = gE phi, out_vec = -gE F
+constexpr int kGatherTargets = 2;         // points of plan.tgt: phi (no self term), -grad phi
 
 constexpr int kThreads = 256;      // work-group size of the binning, fold and FFT kernels
 constexpr int kTileThreads = 512;  // work-group size of the tile spread and gather kernels

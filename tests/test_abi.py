@@ -100,3 +100,9 @@ def test_realspace_plan_rejects_bad_arguments(L, xi, rc, dtype, n_max):
     assert _lib.STATUS_NAMES.get(st) == "SE_ERR_ARG", st
     assert out.value is None
     assert lib.se_last_error().decode()
+
+
+def test_target_entry_points_reject_bad_arguments():
+    lib = _lib.load()
+    assert _lib.STATUS_NAMES[lib.se_plan_reserve_targets(None, 10)] == "SE_ERR_ARG"
+    assert _lib.STATUS_NAMES[lib.se_eval_targets(None, 1, None, None, None)] == "SE_ERR_ARG"

@@ -244,3 +244,48 @@ def test_full_ions_1M_tuned(window, P, M):
     k-space force error of 1e-4 (tests/golden/spme_tuned_grid.json; SPME
     p = 6 at M = 192 is test_full_ions_1M), in the FP32 form that is timed."""
     _sampled_parity("ions_1M", P, torch.float32, window=window, M=M)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("window,M,P", [("gaussian", 30, 8), ("gaussian", 48, 12),
+                                        ("bspline", 30, 5), ("bspline", 32, 6)])
+def test_potential_and_field_at_points(window, M, P, dtype):
+    """se_eval_targets: potential and field of the sources at 700 points that
+    are not sources (some outside [0, L), some on top of sources), against the
+    oracle's gather of unit test charges on its own grid; the sources' own
+    phi and F are unchanged by the call; an empty target set is accepted."""
+    L, xi = 10.0, 1.2
+    x, q = _rand(900, L, 21)
+    rng = np.random.default_rng(22)
+    xt_np = np.concatenate([rng.random((600, 3)) * 14.0 - 2.0, x[:100]])
+    print(f"[targets] {window} M={M} P={P} {dtype}", flush=True)
+    xs, qs = to_dev(x, q, dtype)
+    plan = SEPlan(M, P, L, xi, window=window, dtype=dtype, n_max=len(q))
+    E, phi, F = plan.kspace(xs, qs)
+    xt = torch.tensor(xt_np, dtype=dtype, device=DEV)
+    phi_t, field_t = plan.eval_targets(xt)
+    phi2, F2 = plan.gather()
+    torch.cuda.synchronize()
+    xo, qo = as_oracle_inputs(xs, qs)
+    xto = xt.double().cpu().numpy()
+    ones = np.ones(len(xto))
+    if window == "gaussian":
+        _, _, _, _, Phi = O.se_kspace(xo, qo, L, xi, M, P, return_grids=True)
+        ref_phi, ref_field = O.se_gather(xto, ones, L, M, P, xi, O.se_eta(L, xi, M, P), Phi)
+    else:
+        _, _, _, _, Phi = O.spme_kspace(xo, qo, L, xi, M, P, return_grids=True)
+        ref_phi, ref_field = O.spme_gather(xto, ones, L, M, P, Phi)
+    e = (O.rel_rms(phi_t.double().cpu().numpy(), ref_phi),
+         O.rel_rms(field_t.double().cpu().numpy(), ref_field))
+    assert max(e) < TOL[dtype], e
+    # on top of a source: phi of that source and its force per unit charge
+    pt, ft = phi_t[600:].double(), field_t[600:].double()
+    np.testing.assert_allclose(pt.cpu().numpy(), phi[:100].double().cpu().numpy(),
+                               rtol=0, atol=1e-6 * float(phi.abs().max()))
+    np.testing.assert_allclose((ft * qs[:100, None].double()).cpu().numpy(),
+                               F[:100].double().cpu().numpy(),
+                               rtol=0, atol=1e-5 * float(F.abs().max()))
+    assert torch.equal(phi, phi2) and torch.equal(F, F2)
+    pe, fe = plan.eval_targets(xt[:0])
+    assert pe.numel() == 0 and fe.numel() == 0
+    plan.close()

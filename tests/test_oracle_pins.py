@@ -394,3 +394,32 @@ def test_real_space_targets_match_full_sum(oracle):
     phit, Ft = oracle.ewald_real_targets(x, q, 8.0, 1.1, 2.5, idx)
     np.testing.assert_allclose(phit, phi[idx], rtol=1e-13, atol=1e-14)
     np.testing.assert_allclose(Ft, F[idx], rtol=1e-13, atol=1e-14)
+
+
+def test_potential_and_field_at_points_match_direct_sum(oracle):
+    """Evaluation at points that are not sources (a unit test charge gathering
+    the grid, eq. 4.9 and the force of eq. 4.12 per unit charge): at P = 24
+    the SE values equal the exact k-space potential and field at those points,
+    computed by the direct sum with zero charges placed there (section 1)."""
+    x, q = _rand_neutral(60, 5.0, 11)
+    rng = np.random.default_rng(12)
+    xt = rng.random((25, 3)) * 7.0 - 1.0  # some points outside [0, L)
+    L, xi, M, P = 5.0, 2.0, 40, 24
+    _, _, _, _, Phi = oracle.se_kspace(x, q, L, xi, M, P, return_grids=True)
+    eta = oracle.se_eta(L, xi, M, P)
+    phi_t, field_t = oracle.se_gather(xt, np.ones(len(xt)), L, M, P, xi, eta, Phi)
+    xa = np.concatenate([x, xt])
+    qa = np.concatenate([q, np.zeros(len(xt))])
+    _, phi_d, _ = oracle.ewald_kspace_direct(xa, qa, L, xi)
+    # field = force on a unit charge: differentiate the direct potential
+    h = 1e-5
+    fd = np.empty((len(xt), 3))
+    for d in range(3):
+        xp, xm = xa.copy(), xa.copy()
+        xp[len(x):, d] += h
+        xm[len(x):, d] -= h
+        pp = oracle.ewald_kspace_direct(xp, qa, L, xi)[1][len(x):]
+        pm = oracle.ewald_kspace_direct(xm, qa, L, xi)[1][len(x):]
+        fd[:, d] = -(pp - pm) / (2 * h)
+    assert np.max(np.abs(phi_t - phi_d[len(x):])) < 1e-11 * np.max(np.abs(phi_d))
+    assert np.max(np.abs(field_t - fd)) < 1e-7 * np.max(np.abs(fd))
