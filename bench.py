@@ -31,6 +31,11 @@ METRIC = "SE k-space E+F atom-evals/s at rms force err 1e-5, FP32 vs FP64; %HBM 
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 CALIB_COPY_BYTES = 256 << 20     # bytes read (and written) by the calibration copy
+REAL_SPACE_RC = 10.0             # A: the usual MD cutoff, for the real-space line
+# FP32 operations of the real-space kernel: the distance test of a tested
+# pair (3 differences, 3 scalings, |r|^2) and the terms of a pair in range
+# (rsqrt, xi r, e^{-x^2}, t, eight-term polynomial, phi and force updates)
+RS_FLOPS_TEST, RS_FLOPS_PAIR = 11, 38
 
 # source files each kernel is built from (a change voids stored counters)
 CSRC = os.path.join(ROOT, "paper_1712_04718_amd", "csrc")
@@ -359,6 +364,40 @@ def run(args):
         for t in (plan, tplan):
             t.close()
 
+    # Real-space sum beside the path (FP32, cutoff REAL_SPACE_RC): timed on its
+    # own, reported next to the k-space line
+    real_space = None
+    if not args.no_real_space and 3 * REAL_SPACE_RC <= L:
+        from paper_1712_04718_amd import RealSpacePlan
+        xt = torch.tensor(x, dtype=torch.float32, device=dev)
+        qt = torch.tensor(q, dtype=torch.float32, device=dev)
+        rplan = RealSpacePlan(L, xi, REAL_SPACE_RC, dtype=torch.float32, n_max=N, device=dev)
+        reps = max(10, args.steps // 4)
+        for _ in range(max(3, args.warmup // 4)):
+            rplan.eval(xt, qt)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            rplan.eval(xt, qt)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_rs = e0.elapsed_time(e1) / reps
+        rplan.close()
+        nc = min(int(L // REAL_SPACE_RC), 64)
+        tested = N * 27.0 * (L / nc) ** 3 * N / L ** 3
+        in_range = N * 4.0 / 3.0 * math.pi * REAL_SPACE_RC ** 3 * N / L ** 3
+        flops = tested * RS_FLOPS_TEST + in_range * RS_FLOPS_PAIR
+        real_space = {"rc": REAL_SPACE_RC, "ms_per_eval": ms_rs, "reps": reps,
+                      "value": N / (ms_rs * 1e-3), "unit": "atom-evals/s",
+                      "pairs_in_range_per_s": in_range / (ms_rs * 1e-3),
+                      "tested_pairs_per_s": tested / (ms_rs * 1e-3),
+                      "alu": {"achieved": flops / (ms_rs * 1e-3) / 1e12,
+                              "peak": VALU_PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                              "frac": flops / (ms_rs * 1e-3) / 1e12 / VALU_PEAK_TFLOPS["f32"]},
+                      "step": "se_rs_eval: cell-list binning + pair kernel + energy reduction"}
+        log(f"real space rc={REAL_SPACE_RC}: {ms_rs * 1e3:.1f} us/eval")
+
     # CPU baseline: the oracle as it stands, FP64, repeated full evaluations
     # of the same workload for about ten seconds
     cpu = None
@@ -445,6 +484,7 @@ def run(args):
         "grid_pass_hbm_frac": hbm_frac,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "real_space": real_space,
         "sources": {st: source_hash(st) for st in KERNEL_SOURCES},
     }
     if "f64" in out:
@@ -471,6 +511,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-real-space", action="store_true")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "FETCH_LOG",
                                                        "WRITE_LOG"),
                     help="summarize two rocprofv3 --pmc runs of this script into profiles/ "

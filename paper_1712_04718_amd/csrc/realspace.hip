@@ -44,15 +44,15 @@ namespace sek {
 namespace {
 
 constexpr int kRsThreads = 256;
-constexpr int kQueue = 64;   // pair queue entries per thread (16-bit stage indices)
+constexpr int kQueue = 32;   // pair queue entries per thread
 constexpr int kBatch = 8;    // LDS reads issued together in the test and evaluation loops
 
 template <typename R> struct alignas(4 * sizeof(R)) Staged {
-  R x, y, z, q;  // position relative to the home cell's corner (cell units), charge
+  R x, y, z, q;  // position relative to the home cell's corner (length units), charge
 };
 
-// Staged neighbours per pass: 32 KB of LDS in either precision.
-template <typename R> constexpr int kStageCap = 32768 / sizeof(Staged<R>);
+// Staged neighbours per pass (16 KB of LDS in FP32, 32 KB in FP64).
+template <typename R> constexpr int kStageCap = 1024;
 
 // FP32 erfc(x) for x >= 0 from e2 = e^{-x^2}: e2 t sum a_i t^i, t = 1/(1 + p x)
 // (the form of Abramowitz-Stegun 7.1.26 with eight terms fitted for relative
@@ -111,7 +111,7 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
            R *__restrict__ F, double *__restrict__ epart) {
   constexpr int CAP = kStageCap<R>;
   __shared__ Staged<R> stage[CAP];
-  __shared__ unsigned short queue[kQueue * kRsThreads];
+  __shared__ int queue[kQueue * kRsThreads];  // entry m of thread t at m * 256 + t
   __shared__ int nb_src[27], nb_pre[28];
   __shared__ R red[4][kRsThreads];
   __shared__ double ered[kRsThreads / 64];
@@ -146,6 +146,7 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
     const int hi = tid % nhp, sl = tid / nhp;
     const bool active = sl < G;
     const SortedParticle<R> pi = sorted[hsrc + hb + hi];
+    const R px = pi.dx * cs, py = pi.dy * cs, pz = pi.dz * cs;
     const int self = home0 + hb + hi;
     R ph = R(0), fx = R(0), fy = R(0), fz = R(0);
     for (int c0 = 0; c0 < S; c0 += CAP) {
@@ -172,9 +173,9 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
           if (kk[u] >= 0) {
             const int kc = kk[u];
             stage[tid + u * kRsThreads] =
-                Staged<R>{static_cast<R>(kc % 3 - 1) + buf[u].dx,
-                          static_cast<R>((kc / 3) % 3 - 1) + buf[u].dy,
-                          static_cast<R>(kc / 9 - 1) + buf[u].dz, buf[u].q};
+                Staged<R>{(static_cast<R>(kc % 3 - 1) + buf[u].dx) * cs,
+                          (static_cast<R>((kc / 3) % 3 - 1) + buf[u].dy) * cs,
+                          (static_cast<R>(kc / 9 - 1) + buf[u].dz) * cs, buf[u].q};
           }
         }
       }
@@ -187,16 +188,15 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
         for (int m0 = 0; __any(m0 < qn); m0 += kBatch) {
           int idx[kBatch];
 #pragma unroll
-          for (int u = 0; u < kBatch; ++u)
-            idx[u] = queue[((m0 + u) >> 1) * (2 * kRsThreads) + 2 * tid + ((m0 + u) & 1)];
+          for (int u = 0; u < kBatch; ++u) idx[u] = queue[(m0 + u) * kRsThreads + tid];
           Staged<R> c[kBatch];
 #pragma unroll
-          for (int u = 0; u < kBatch; ++u) c[u] = stage[min(idx[u], cn - 1)];
+          for (int u = 0; u < kBatch; ++u) c[u] = stage[min(static_cast<unsigned>(idx[u]),
+                                                            static_cast<unsigned>(cn - 1))];
 #pragma unroll
           for (int u = 0; u < kBatch; ++u) {
             if (m0 + u < qn) {
-              const R rx = (pi.dx - c[u].x) * cs, ry = (pi.dy - c[u].y) * cs,
-                      rz = (pi.dz - c[u].z) * cs;
+              const R rx = px - c[u].x, ry = py - c[u].y, rz = pz - c[u].z;
               pair_term(rx, ry, rz, rx * rx + ry * ry + rz * rz, c[u].q, xi, c2, ph, fx, fy, fz);
             }
           }
@@ -210,11 +210,11 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
           const int idx = k0 + u;
-          const R rx = (pi.dx - c[u].x) * cs, ry = (pi.dy - c[u].y) * cs, rz = (pi.dz - c[u].z) * cs;
+          const R rx = px - c[u].x, ry = py - c[u].y, rz = pz - c[u].z;
           const R r2 = rx * rx + ry * ry + rz * rz;
           const bool hit = idx < hi_end && r2 < rc2 && idx != self_l;
           // the free slot qn is written either way; only a hit keeps it
-          queue[(qn >> 1) * (2 * kRsThreads) + 2 * tid + (qn & 1)] = static_cast<unsigned short>(idx);
+          queue[qn * kRsThreads + tid] = idx;
           qn += hit ? 1 : 0;
         }
         if (__any(qn > kQueue - kBatch)) flush();
