@@ -89,8 +89,10 @@ enum {
 
 typedef struct {
     int M;          /* grid points per side; even, 2^a 3^b 5^c, 8 <= M <= 512 */
-    int P;          /* SE: Gaussian support points per side, even, 4..16;
-                       SPME: B-spline order p, 3..8.  P <= M.              */
+    int P;          /* SE: Gaussian support points per side, even, 4..16
+                       (FP64 also 18..24, on an untiled path: atomics into
+                       the grid, no binning); SPME: B-spline order p, 3..8.
+                       P <= M.                                              */
     double L;       /* box side, > 0                                         */
     double xi;      /* Ewald splitting parameter, > 0                        */
     double c;       /* SE shape constant of eq. (5.2); <= 0 selects 0.95     */

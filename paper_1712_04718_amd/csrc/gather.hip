@@ -362,6 +362,7 @@ size_t gather_lds_bytes(int real_size, int window, int S, int T) {
 hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode, void *out_pot,
                          void *out_vec) {
   if (N == 0 || (!out_pot && !out_vec)) return hipSuccess;
+  if (plan.direct) return launch_direct_gather(plan, N, gscale, mode, out_pot, out_vec);
   return plan.prm.dtype == SE_FP64 ? gather_dispatch<double>(plan, gscale, mode, out_pot, out_vec)
                                    : gather_dispatch<float>(plan, gscale, mode, out_pot, out_vec);
 }

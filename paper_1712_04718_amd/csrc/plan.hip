@@ -120,8 +120,10 @@ se_status check_params(const se_params *prm, double *eta_out) {
   if (p.P > p.M) return fail(SE_ERR_GRID, "support %d exceeds M=%d", p.P, p.M);
   double eta = 0.0;
   if (p.window == SE_WINDOW_GAUSSIAN) {
-    if ((p.P & 1) || p.P < 4 || p.P > 16)
-      return fail(SE_ERR_UNSUPPORTED, "Gaussian support P=%d: built for even P in 4..16", p.P);
+    const bool wide = p.dtype == SE_FP64 && p.P >= 18 && p.P <= 24;
+    if ((p.P & 1) || p.P < 4 || (p.P > 16 && !wide))
+      return fail(SE_ERR_UNSUPPORTED,
+                  "Gaussian support P=%d: built for even P in 4..16 (FP32) and 4..24 (FP64)", p.P);
     eta = eta_of(p);
     if (!(eta > 0.0 && eta < 1.0))
       return fail(SE_ERR_ETA, "eta = P L^2 xi^2 / (c^2 pi M^2) = %g is outside (0,1)", eta);
@@ -167,11 +169,12 @@ Sizes sizes_of(const se_params &p, int n_max, int ntiles, int bin_blocks, int zb
   const size_t rs = real_size(p), M = p.M, K = M / 2 + 1;
   const size_t n = n_max > 0 ? n_max : 1;
   Sizes s{};
-  auto al = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+  // every buffer gets at least 256 bytes (the untiled path has no tiles)
+  auto al = [](size_t b) { return ((b ? b : 1) + 255) & ~static_cast<size_t>(255); };
   const size_t TS = T + p.P - 1;
   s.grid = al(M * M * M * rs);
-  s.ghost = al(static_cast<size_t>(ntiles) * TS * TS * TS * rs);
-  s.cover = al(M * max_cover(p, T) * 4);
+  s.ghost = al(T > 0 ? static_cast<size_t>(ntiles) * TS * TS * TS * rs : 0);
+  s.cover = al(T > 0 ? M * max_cover(p, T) * 4 : 0);
   s.cover_count = al(M * 4);
   s.spec = al(M * M * K * 2 * rs);
   s.sorted = al(n * 4 * rs);
@@ -200,7 +203,8 @@ void derive(se_plan &pl) {
   } else {
     pl.eta = pl.a = pl.cg = pl.beta = 0.0;
   }
-  pl.T = choose_tile(p);
+  pl.direct = p.window == SE_WINDOW_GAUSSIAN && p.P > 16;
+  pl.T = pl.direct ? 0 : choose_tile(p);
   pl.ntx = pl.T > 0 ? (p.M + pl.T - 1) / pl.T : 0;
   pl.ntiles = pl.ntx * pl.ntx * pl.ntx;
   pl.bin_blocks = (pl.n_max + sek::kThreads - 1) / sek::kThreads;
@@ -295,7 +299,7 @@ se_status se_plan_workspace_size(const se_params *prm, int n_max, size_t *bytes)
   tmp.prm = *prm;
   tmp.n_max = n_max;
   derive(tmp);
-  if (tmp.T == 0)
+  if (tmp.T == 0 && !tmp.direct)
     return fail(SE_ERR_UNSUPPORTED, "support %d in this precision needs more LDS than a CU has",
                 prm->P);
   *bytes = sizes_of(*prm, n_max, tmp.ntiles, tmp.bin_blocks, tmp.zfft_blocks, tmp.T).total;
@@ -317,14 +321,14 @@ se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_p
   pl->stream = static_cast<hipStream_t>(hip_stream);
   pl->last_N = -1;
   derive(*pl);
-  if (pl->T == 0) {
+  if (pl->T == 0 && !pl->direct) {
     delete pl;
     return fail(SE_ERR_UNSUPPORTED, "support %d in this precision needs more LDS than a CU has",
                 prm->P);
   }
   // staged tile blocks index the grid in [-(P-1), M + T + P - 3]; the kernels
   // wrap that range without division (holds for every M >= 8 with P <= M)
-  if (pl->T + pl->prm.P - 3 >= 2 * pl->prm.M) {
+  if (!pl->direct && pl->T + pl->prm.P - 3 >= 2 * pl->prm.M) {
     const int T = pl->T;
     delete pl;
     return fail(SE_ERR_GRID, "tile edge %d with support %d needs a larger grid than M=%d", T,
@@ -385,7 +389,7 @@ se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_p
       if (e == hipSuccess) e = hipEventCreate(&pl->timers[i].end[k]);
     }
   if (e == hipSuccess) e = hipMemset(pl->buf.counts, 0, sz.counts);
-  if (e == hipSuccess) {
+  if (e == hipSuccess && !pl->direct) {
     const auto lists = cover_lists(M, pl->T, pl->prm.P, stencil_offset(pl->prm));
     size_t kc = 0;
     for (const auto &l : lists) kc = std::max(kc, l.size());
@@ -454,9 +458,14 @@ se_status se_forward(se_plan *plan, int N, const void *x, const void *q, double 
   if (N < 0 || N > plan->n_max) return fail(SE_ERR_ARG, "N=%d outside [0, n_max=%d]", N, plan->n_max);
   if (N > 0 && (!x || !q)) return fail(SE_ERR_ARG, "x or q is NULL");
   if (!E_dev) return fail(SE_ERR_ARG, "E_dev is NULL");
-  hipError_t e = sek::launch_bin(*plan, N, x, q);
-  if (e != hipSuccess) return hip_fail(e, "binning");
-  if ((e = sek::launch_spread(*plan)) != hipSuccess) return hip_fail(e, "spreading");
+  hipError_t e;
+  if (plan->direct) {
+    if ((e = sek::launch_direct_forward(*plan, N, x, q)) != hipSuccess)
+      return hip_fail(e, "spreading (untiled)");
+  } else {
+    if ((e = sek::launch_bin(*plan, N, x, q)) != hipSuccess) return hip_fail(e, "binning");
+    if ((e = sek::launch_spread(*plan)) != hipSuccess) return hip_fail(e, "spreading");
+  }
   if ((e = sek::launch_fft_forward_scale_inverse(*plan, E_dev)) != hipSuccess)
     return hip_fail(e, "FFT/scaling");
   plan->last_N = N;
@@ -487,7 +496,7 @@ se_status se_plan_reserve_targets(se_plan *plan, int nt_max) {
   const size_t rs = plan->prm.dtype == SE_FP64 ? 8 : 4;
   const size_t n = static_cast<size_t>(nt_max);
   struct { void **ptr; size_t bytes; } allocs[] = {
-      {reinterpret_cast<void **>(&t.counts), static_cast<size_t>(plan->ntiles) * sek::kCountStride * 4},
+      {reinterpret_cast<void **>(&t.counts), static_cast<size_t>(std::max(plan->ntiles, 1)) * sek::kCountStride * 4},
       {reinterpret_cast<void **>(&t.offsets), static_cast<size_t>(plan->ntiles + 1) * 4},
       {reinterpret_cast<void **>(&t.key), n * 8},
       {reinterpret_cast<void **>(&t.meta), n * 8},
@@ -513,7 +522,7 @@ se_status se_plan_reserve_targets(se_plan *plan, int nt_max) {
   }
   e = hipMemcpy(t.ones, src, n * rs, hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemset(t.counts, 0, static_cast<size_t>(plan->ntiles) * sek::kCountStride * 4);
+    e = hipMemset(t.counts, 0, static_cast<size_t>(std::max(plan->ntiles, 1)) * sek::kCountStride * 4);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_targets(*plan);
@@ -548,7 +557,10 @@ se_status se_eval_targets(se_plan *plan, int nt, const void *xt, void *phi_t, vo
   j.meta = plan->tgt.meta;
   j.qsq_part = plan->tgt.part;
   j.stream = plan->stream;
-  hipError_t e = sek::launch_bin_job(j, nullptr);
+  hipError_t e = plan->direct ? sek::launch_direct_prep(*plan, nt, xt, plan->tgt.ones,
+                                                        plan->tgt.sorted, plan->tgt.meta,
+                                                        plan->tgt.part, nullptr)
+                              : sek::launch_bin_job(j, nullptr);
   if (e != hipSuccess) return hip_fail(e, "binning evaluation points");
   e = sek::launch_gather(*plan, nt, nullptr, sek::kGatherTargets, phi_t, field_t);
   return e == hipSuccess ? SE_OK : hip_fail(e, "gathering at evaluation points");

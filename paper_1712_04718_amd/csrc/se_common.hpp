@@ -169,6 +169,7 @@ struct se_plan {
   sek::TargetBuffers tgt;
   sek::FoldTables fold;
   bool fold_by_tiles;  // tiles partition the grid: tile-structured fold
+  bool direct;         // FP64 Gaussian with P > 16: untiled spread and gather (direct.hip)
 
   int last_N;      // particles of the last se_forward, -1 before the first
 
@@ -209,6 +210,13 @@ se_status report(se_status s, const char *msg);
 // and returns the launch status.
 hipError_t launch_bin(se_plan &plan, int N, const void *x, const void *q);
 hipError_t launch_spread(se_plan &plan);
+// Untiled path (FP64 Gaussian, P = 18..24): anchors and offsets in input
+// order (with q^2 block sums), spread with FP64 atomics, gather per wave.
+hipError_t launch_direct_prep(se_plan &p, int N, const void *x, const void *q, void *pts,
+                              int2 *meta, double *qsq_part, int *parts);
+hipError_t launch_direct_forward(se_plan &p, int N, const void *x, const void *q);
+hipError_t launch_direct_gather(se_plan &p, int N, const double *gscale, int mode, void *pot,
+                                void *vec);
 hipError_t launch_fft_forward_scale_inverse(se_plan &plan, double *E_dev);
 hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode,
                          void *out_pot, void *out_vec);

@@ -240,13 +240,13 @@ se_status se_cost_model_mi355x(int dtype, se_cost_model *m) {
   // Non-negative least-squares fits of the model to se_kspace and se_rs_eval
   // times on an MI355X (calibrate.py of this package; 60 k-space and 15
   // real-space configurations per precision).
-  // Largest relative deviation of the fit: 20% (FP32), 33% (FP64).
+  // Largest relative deviation of the fit: 26% (FP32), 33% (FP64).
   if (dtype == SE_FP32) {
-    *m = se_cost_model{2.3723e-05, 0.0, 1.4702e-12, 1.6354e-08, 1.4340e-12, 4.3958e-05,
-                       8.7079e-11, 3.2677e-13, 3.1170e-12, 1.3210e-11, 0.0};
+    *m = se_cost_model{2.1391e-05, 0.0, 0.0, 1.1224e-08, 1.2684e-12,
+                       4.4925e-05, 8.5423e-11, 3.2684e-13, 3.1091e-12, 1.3104e-11, 0.0};
   } else if (dtype == SE_FP64) {
-    *m = se_cost_model{2.9111e-05, 0.0, 1.3405e-11, 1.7292e-08, 2.6857e-12, 4.3277e-05,
-                       1.7101e-10, 5.6157e-13, 6.2155e-12, 1.0561e-11, 8.6272e-13};
+    *m = se_cost_model{3.3700e-05, 0.0, 1.4808e-11, 1.6829e-08, 2.6432e-12,
+                       4.3906e-05, 1.7071e-10, 5.5856e-13, 6.2187e-12, 4.8356e-12, 1.5822e-12};
   } else {
     return bad("unknown dtype");
   }
