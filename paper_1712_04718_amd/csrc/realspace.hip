@@ -12,10 +12,10 @@
 // cs = L / nc >= rc,
 // so every pair within rc lies in one of the 27 cells around a particle's
 // own.  Particles are put in cell order by the binning kernels (cell edge =
-// one point of an nc^3 grid); their stored offsets from the cell corner (in
-// units of cs) give distances without the rounding of absolute coordinates.
-// One work-group per cell: each thread holds one particle of the cell and
-// the 27 neighbour cells are staged in LDS in turn.
+// one point of an nc^3 grid); their stored offsets from the cell corner
+// give distances without the rounding of absolute coordinates.  One
+// work-group per cell stages the 27 neighbour cells in LDS and evaluates
+// every pair of a home particle with them (k_rs_pairs).
 #include <cmath>
 #include <cstdio>
 #include <new>
@@ -37,7 +37,6 @@ struct se_rs_plan {
   int2 *meta = nullptr;
   void *sorted = nullptr;
   double *part = nullptr;  // q^2 partials of binning (unused), then energy partials
-  int last_N = -1;
 };
 
 namespace sek {
@@ -390,7 +389,6 @@ se_status se_rs_eval(se_rs_plan *plan, int N, const void *x, const void *q, doub
                            ? sek::rs_eval<double>(*plan, N, x, q, E_dev, phi, F)
                            : sek::rs_eval<float>(*plan, N, x, q, E_dev, phi, F);
   if (e != hipSuccess) return sek::report(SE_ERR_HIP, hipGetErrorString(e));
-  plan->last_N = N;
   return SE_OK;
 }
 
