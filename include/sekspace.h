@@ -70,6 +70,15 @@ typedef enum { SE_FP32 = 0, SE_FP64 = 1 } se_dtype;
 #define SE_FLAG_TIMING 2u    /* record a HIP event pair around every kernel launch
                                 (on the plan's stream) for se_plan_stage_times;
                                 such a plan must not be captured in a graph      */
+#define SE_FLAG_IK_FORCE 4u  /* F of se_gather (and the field of se_eval_targets)
+                                by ik differentiation (section 3.1): the field
+                                -grad Phi from -i k times the scaled spectrum,
+                                three more inverse 3D FFTs in se_forward, then
+                                a plain-window gather of each component, instead
+                                of the analytic derivative of the window.  For
+                                comparison: se_backward keeps the analytic
+                                adjoint (the exact gradient of E).  Tiled
+                                supports only (SE P <= 16, SPME).            */
 
 /* Kernel stages of one evaluation, in launch order (se_plan_stage_times). */
 enum {

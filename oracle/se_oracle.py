@@ -231,6 +231,48 @@ def spme_kspace(x, q, L, xi, M, p, return_grids=False):
     return E, phi, F
 
 
+def field_grids(G: np.ndarray, w: np.ndarray, L: float):
+    """Section 3.1, the ik differentiation: the three components of the field
+    -grad Phi on the grid,
+        E_d = (4 pi / L^3) sum_k (-i k_d) w_k G^_k e^{+i k.x_j},
+    with k_d = 0 on the Nyquist row of axis d (the derivative of that mode is
+    not defined on the grid).  Returned as (E_x, E_y, E_z), indexed like G."""
+    M = G.shape[0]
+    V = L ** 3
+    Gh = np.fft.fftn(G)
+    n = np.fft.fftfreq(M, d=1.0 / M)
+    if M % 2 == 0:
+        n[M // 2] = 0.0
+    k = 2.0 * math.pi * n / L
+    shapes = ((1, 1, M), (1, M, 1), (M, 1, 1))  # x, y, z along the [z, y, x] axes
+    return tuple(np.ascontiguousarray(
+        (4.0 * math.pi / V) * np.real(np.fft.ifftn(-1j * k.reshape(sh) * w * Gh)) * M ** 3)
+        for sh in shapes)
+
+
+def se_kspace_ik(x, q, L, xi, M, P, c=0.95):
+    """SE k-space sum with ik-differentiated forces (section 3.1): E and phi
+    as in se_kspace, F_m = q_m (E_x, E_y, E_z) gathered at x_m with the window
+    (eq. 4.9 applied to each field grid)."""
+    eta = se_eta(L, xi, M, P, c)
+    G = se_spread(x, q, L, M, P, xi, eta)
+    w = se_influence(L, xi, M, eta)
+    E, Phi = scale_and_energy(G, w, L)
+    phi, _ = se_gather(x, q, L, M, P, xi, eta, Phi, want_F=False)
+    comps = [se_gather(x, q, L, M, P, xi, eta, Ed, want_F=False)[0] for Ed in field_grids(G, w, L)]
+    return E, phi, np.asarray(q)[:, None] * np.stack(comps, axis=1)
+
+
+def spme_kspace_ik(x, q, L, xi, M, p):
+    """SPME k-space sum with ik-differentiated forces (section 3.1)."""
+    Q = spme_spread(x, q, L, M, p)
+    w = spme_influence(L, xi, M, p)
+    E, Phi = scale_and_energy(Q, w, L)
+    phi, _ = spme_gather(x, q, L, M, p, Phi, want_F=False)
+    comps = [spme_gather(x, q, L, M, p, Ed, want_F=False)[0] for Ed in field_grids(Q, w, L)]
+    return E, phi, np.asarray(q)[:, None] * np.stack(comps, axis=1)
+
+
 # --------------------------------------------------------------------------
 # Exact Ewald sums (section 1) for pinning
 # --------------------------------------------------------------------------

@@ -18,6 +18,7 @@ SE_FP32 = 0
 SE_FP64 = 1
 SE_FLAG_ADD_SELF = 1
 SE_FLAG_TIMING = 2
+SE_FLAG_IK_FORCE = 4
 STAGES = ("bin_count", "bin_scan", "bin_scatter", "spread", "fold", "fft_x", "fft_y",
           "fft_z_scale", "ifft_y", "ifft_x", "gather")
 

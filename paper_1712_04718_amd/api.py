@@ -31,7 +31,7 @@ class SEPlan:
     ``gather`` and ``backward``."""
 
     def __init__(self, M, P, L, xi, window="gaussian", dtype=torch.float32, c=0.95,
-                 n_max=1 << 20, add_self=False, device=None, timing=False):
+                 n_max=1 << 20, add_self=False, device=None, timing=False, ik_force=False):
         if not torch.cuda.is_available():
             raise RuntimeError("SEPlan needs a GPU (no HIP device visible)")
         if dtype not in _DTYPES:
@@ -46,7 +46,8 @@ class SEPlan:
         self.window = window
         self.dtype = dtype
         self.n_max = int(n_max)
-        flags = (_lib.SE_FLAG_ADD_SELF if add_self else 0) | (_lib.SE_FLAG_TIMING if timing else 0)
+        flags = ((_lib.SE_FLAG_ADD_SELF if add_self else 0) | (_lib.SE_FLAG_TIMING if timing else 0)
+                 | (_lib.SE_FLAG_IK_FORCE if ik_force else 0))
         self.params = _lib.make_params(M, P, L, xi, c, _WINDOWS[window], _DTYPES[dtype], flags)
         self._plan = ctypes.c_void_p(None)
         with torch.cuda.device(self.device):

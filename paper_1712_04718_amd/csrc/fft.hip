@@ -410,7 +410,7 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
       spec[static_cast<long long>(c0 + b) * M + y] = v;
     }
   }
-  if (INV && blockIdx.x == 0) {
+  if (INV && blockIdx.x == 0 && eo.E) {
     __shared__ double red[kThreads], redq[kThreads];
     double se = 0.0, sq = 0.0;
     for (int b = threadIdx.x; b < eo.nparts; b += kThreads) se += eo.part[b];
@@ -432,11 +432,17 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
 
 // ------------------------------------------ z pass with scaling and energy
 
+// With ik >= 0 the pass writes, instead of w G^, the spectrum of one
+// component of the field -grad Phi: -i k_ik w G^ (section 3.1, the ik
+// differentiation), into out, with no energy; the Nyquist plane of that axis
+// is zero (its derivative is not defined on the grid).  Otherwise out = in
+// and the energy partials go to epart.
 template <typename R, int MC, int LGBC>
 __global__ void __launch_bounds__(kThreads)
-k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__restrict__ tw_g,
-              const double *__restrict__ axis_f, const double *__restrict__ axis_k2,
-              double wscale, double *__restrict__ epart) {
+k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
+              const cplx_t<R> *__restrict__ tw_g, const double *__restrict__ axis_f,
+              const double *__restrict__ axis_k2, double wscale, double *__restrict__ epart,
+              int ik, double two_pi_over_L) {
   using C = cplx_t<R>;
   constexpr bool CT = MC > 0;
   const int M = CT ? MC : pl.M;
@@ -455,7 +461,7 @@ k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R>
       const int i = threadIdx.x + k * kThreads;
       const int z = i >> lgb, b = i & (B - 1);
       if (i < M * B && c0 + b < npen) {
-        v[k] = spec[z * zs + c0 + b];
+        v[k] = in[z * zs + c0 + b];
       } else {
         v[k].x = v[k].y = R(0);
       }
@@ -469,6 +475,10 @@ k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R>
   __syncthreads();
   C *Z = fft_any<R, MC, LGBC>(b0, b1, lgb, pl, twl);
   C *other = (Z == b0) ? b1 : b0;
+  // signed wave number of an axis index (0 on the Nyquist plane)
+  const auto signed_k = [&](int n) {
+    return 2 * n == M ? 0.0 : two_pi_over_L * static_cast<double>(2 * n < M ? n : n - M);
+  };
 
   double e = 0.0;
   for (int i = threadIdx.x; i < M * B; i += kThreads) {
@@ -487,6 +497,13 @@ k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R>
       const R wr = static_cast<R>(w);
       v.x = v.x * wr;  // conjugated for the inverse transform
       v.y = -(v.y * wr);
+      if (ik >= 0) {
+        // conj(-i k w G^) = i k conj(w G^): (a + i b) -> k (-b + i a)
+        const R kd = static_cast<R>(signed_k(ik == 0 ? kx : (ik == 1 ? ky : kz)));
+        const R a = v.x;
+        v.x = -v.y * kd;
+        v.y = a * kd;
+      }
     } else {
       v.x = v.y = R(0);
     }
@@ -496,8 +513,9 @@ k_fft_z_scale(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R>
   const C *Y = fft_any<R, MC, LGBC>(Z, other, lgb, pl, twl);
   for (int i = threadIdx.x; i < M * B; i += kThreads) {
     const int z = i >> lgb, b = i & (B - 1);
-    if (c0 + b < npen) spec[z * zs + c0 + b] = cconj(Y[i]);
+    if (c0 + b < npen) out[z * zs + c0 + b] = cconj(Y[i]);
   }
+  if (!epart) return;  // uniform across the work-group
 
   // energy: one partial per block, added in a fixed order by the next pass
   __shared__ double red[kThreads];
@@ -540,10 +558,27 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
   k_fft_y<R, MC, LY, false><<<yg, p.fft_threads, lds_of(ly), p.stream>>>(spec, p.fft, ly, tw, none);
   stage_end(p, SE_STAGE_FFT_Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  const double tpl = 2.0 * M_PI / p.prm.L;
+  if (p.prm.flags & SE_FLAG_IK_FORCE) {
+    // the three field components first (they read the forward spectrum,
+    // which the potential's z pass then overwrites); not timed
+    C *spec2 = static_cast<C *>(p.buf.spec2);
+    for (int d = 0; d < 3; ++d) {
+      k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_of(lz), p.stream>>>(
+          spec, spec2, p.fft, lz, tw, static_cast<const double *>(p.buf.axis_f),
+          static_cast<const double *>(p.buf.axis_k2), p.wscale, nullptr, d, tpl);
+      k_fft_y<R, MC, LY, true><<<yg, p.fft_threads, lds_of(ly), p.stream>>>(spec2, p.fft, ly, tw,
+                                                                           none);
+      k_fft_x_c2r<R, MC, LX><<<xblocks, p.fft_threads, lds_of(lx), p.stream>>>(
+          spec2, static_cast<R *>(p.buf.field) + static_cast<long long>(d) * M * M * M, p.fft, lx,
+          tw);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
   stage_begin(p, SE_STAGE_FFT_Z_SCALE);
   k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_of(lz), p.stream>>>(
-      spec, p.fft, lz, tw, static_cast<const double *>(p.buf.axis_f),
-      static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks);
+      spec, spec, p.fft, lz, tw, static_cast<const double *>(p.buf.axis_f),
+      static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks, -1, tpl);
   stage_end(p, SE_STAGE_FFT_Z_SCALE);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double self_coef = (p.prm.flags & SE_FLAG_ADD_SELF) ? -p.prm.xi / sqrt(M_PI) : 0.0;

@@ -273,14 +273,19 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
         if (jx == 0) {
           const R q = f[REC - 1];
           const int orig = org[c];
-          const R pot = t0 + self_coef * q;
-          // potential-force mode: F = -q (t1, t2, t3); adjoint: -gE F = gE q (t1, t2, t3)
-          const R fq = (mode == kGatherPotentialForce) ? -scale * q : scale * q;
-          if (out_pot) out_pot[orig] = scale * pot;
-          if (out_vec) {
-            out_vec[3 * orig + 0] = fq * t1;
-            out_vec[3 * orig + 1] = fq * t2;
-            out_vec[3 * orig + 2] = fq * t3;
+          if (mode >= kGatherIkX) {
+            // the grid is one component of the field: F_d = q E_d
+            out_vec[3 * orig + (mode - kGatherIkX)] = scale * q * t0;
+          } else {
+            const R pot = t0 + self_coef * q;
+            // potential-force mode: F = -q (t1, t2, t3); adjoint: -gE F = gE q (t1, t2, t3)
+            const R fq = (mode == kGatherPotentialForce) ? -scale * q : scale * q;
+            if (out_pot) out_pot[orig] = scale * pot;
+            if (out_vec) {
+              out_vec[3 * orig + 0] = fq * t1;
+              out_vec[3 * orig + 1] = fq * t2;
+              out_vec[3 * orig + 2] = fq * t3;
+            }
           }
         }
       }
@@ -288,14 +293,14 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
   }
 }
 
+// One gather launch over the grid `grid`: the plan's particles, or with
+// `tgt` its evaluation points (unit test charges, no self term).
 template <typename R, int WIN, int S, int T>
-hipError_t gather_one(se_plan &p, const double *gscale, int mode, void *pot, void *vec) {
+hipError_t gather_one(se_plan &p, const void *grid, bool tgt, const double *gscale, int mode,
+                      void *pot, void *vec) {
   const size_t lds = GatherLds<R, WIN, S, T>::TOTAL;
   const double dcoef = (WIN == kGauss) ? 2.0 * p.a * p.h : 1.0 / p.h;
   const WindowConsts wc = window_consts(p.cg, p.beta, dcoef);
-  // evaluation points of se_eval_targets are unit test charges in their own
-  // tile order, without the self term
-  const bool tgt = mode == kGatherTargets;
   const double self =
       (!tgt && (p.prm.flags & SE_FLAG_ADD_SELF)) ? -2.0 * p.prm.xi / sqrt(M_PI) : 0.0;
   const void *sorted = tgt ? p.tgt.sorted : p.buf.sorted;
@@ -309,42 +314,53 @@ hipError_t gather_one(se_plan &p, const double *gscale, int mode, void *pot, voi
   }
   if (!tgt) stage_begin(p, SE_STAGE_GATHER);
   k_gather<R, WIN, S, T><<<p.ntiles, kTileThreads, lds, p.stream>>>(
-      static_cast<const R *>(p.buf.grid), static_cast<const SortedParticle<R> *>(sorted), meta,
-      offsets, p.prm.M, p.ntx, wc, gscale, tgt ? kGatherPotentialForce : mode,
-      static_cast<R>(self), static_cast<R *>(pot), static_cast<R *>(vec));
+      static_cast<const R *>(grid), static_cast<const SortedParticle<R> *>(sorted), meta,
+      offsets, p.prm.M, p.ntx, wc, gscale, mode, static_cast<R>(self), static_cast<R *>(pot),
+      static_cast<R *>(vec));
   if (!tgt) stage_end(p, SE_STAGE_GATHER);
   return hipGetLastError();
 }
 
+struct GatherCall {
+  const void *grid;
+  bool tgt;
+  const double *gscale;
+  int mode;
+  void *pot, *vec;
+};
+
 template <typename R, int WIN, int T>
-hipError_t gather_dispatch_S(se_plan &p, const double *g, int mode, void *a, void *b) {
+hipError_t gather_dispatch_S(se_plan &p, const GatherCall &g) {
   switch (p.prm.P) {
-    case 3: if constexpr (WIN == kBspline) return gather_one<R, WIN, 3, T>(p, g, mode, a, b); break;
-    case 4: return gather_one<R, WIN, 4, T>(p, g, mode, a, b);
-    case 5: if constexpr (WIN == kBspline) return gather_one<R, WIN, 5, T>(p, g, mode, a, b); break;
-    case 6: return gather_one<R, WIN, 6, T>(p, g, mode, a, b);
-    case 7: if constexpr (WIN == kBspline) return gather_one<R, WIN, 7, T>(p, g, mode, a, b); break;
-    case 8: return gather_one<R, WIN, 8, T>(p, g, mode, a, b);
-    case 10: if constexpr (WIN == kGauss) return gather_one<R, WIN, 10, T>(p, g, mode, a, b); break;
-    case 12: if constexpr (WIN == kGauss) return gather_one<R, WIN, 12, T>(p, g, mode, a, b); break;
-    case 14: if constexpr (WIN == kGauss) return gather_one<R, WIN, 14, T>(p, g, mode, a, b); break;
-    case 16: if constexpr (WIN == kGauss) return gather_one<R, WIN, 16, T>(p, g, mode, a, b); break;
+#define SE_GATHER_CASE(S) return gather_one<R, WIN, S, T>(p, g.grid, g.tgt, g.gscale, g.mode, g.pot, g.vec)
+    case 3: if constexpr (WIN == kBspline) SE_GATHER_CASE(3); break;
+    case 4: SE_GATHER_CASE(4);
+    case 5: if constexpr (WIN == kBspline) SE_GATHER_CASE(5); break;
+    case 6: SE_GATHER_CASE(6);
+    case 7: if constexpr (WIN == kBspline) SE_GATHER_CASE(7); break;
+    case 8: SE_GATHER_CASE(8);
+    case 10: if constexpr (WIN == kGauss) SE_GATHER_CASE(10); break;
+    case 12: if constexpr (WIN == kGauss) SE_GATHER_CASE(12); break;
+    case 14: if constexpr (WIN == kGauss) SE_GATHER_CASE(14); break;
+    case 16: if constexpr (WIN == kGauss) SE_GATHER_CASE(16); break;
+#undef SE_GATHER_CASE
     default: break;
   }
   return hipErrorInvalidValue;
 }
 
 template <typename R>
-hipError_t gather_dispatch(se_plan &p, const double *g, int mode, void *a, void *b) {
+hipError_t gather_dispatch(se_plan &p, const GatherCall &g) {
   const bool gauss = p.prm.window == SE_WINDOW_GAUSSIAN;
   if (p.T == 16)
-    return gauss ? gather_dispatch_S<R, kGauss, 16>(p, g, mode, a, b)
-                 : gather_dispatch_S<R, kBspline, 16>(p, g, mode, a, b);
+    return gauss ? gather_dispatch_S<R, kGauss, 16>(p, g) : gather_dispatch_S<R, kBspline, 16>(p, g);
   if (p.T == 12)
-    return gauss ? gather_dispatch_S<R, kGauss, 12>(p, g, mode, a, b)
-                 : gather_dispatch_S<R, kBspline, 12>(p, g, mode, a, b);
-  return gauss ? gather_dispatch_S<R, kGauss, 8>(p, g, mode, a, b)
-               : gather_dispatch_S<R, kBspline, 8>(p, g, mode, a, b);
+    return gauss ? gather_dispatch_S<R, kGauss, 12>(p, g) : gather_dispatch_S<R, kBspline, 12>(p, g);
+  return gauss ? gather_dispatch_S<R, kGauss, 8>(p, g) : gather_dispatch_S<R, kBspline, 8>(p, g);
+}
+
+hipError_t gather_call(se_plan &p, const GatherCall &g) {
+  return p.prm.dtype == SE_FP64 ? gather_dispatch<double>(p, g) : gather_dispatch<float>(p, g);
 }
 
 }  // namespace
@@ -363,8 +379,20 @@ hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode, v
                          void *out_vec) {
   if (N == 0 || (!out_pot && !out_vec)) return hipSuccess;
   if (plan.direct) return launch_direct_gather(plan, N, gscale, mode, out_pot, out_vec);
-  return plan.prm.dtype == SE_FP64 ? gather_dispatch<double>(plan, gscale, mode, out_pot, out_vec)
-                                   : gather_dispatch<float>(plan, gscale, mode, out_pot, out_vec);
+  const bool tgt = mode == kGatherTargets;
+  const int kmode = tgt ? kGatherPotentialForce : mode;
+  // ik forces: the potential from Phi, each force component from its field
+  // grid; the adjoint stays the analytic derivative of the window
+  const bool ik = (plan.prm.flags & SE_FLAG_IK_FORCE) && mode != kGatherAdjoint && out_vec;
+  if (!ik) return gather_call(plan, {plan.buf.grid, tgt, gscale, kmode, out_pot, out_vec});
+  hipError_t e = hipSuccess;
+  if (out_pot) e = gather_call(plan, {plan.buf.grid, tgt, gscale, kmode, out_pot, nullptr});
+  const size_t rs = plan.prm.dtype == SE_FP64 ? 8 : 4;
+  const size_t m3 = static_cast<size_t>(plan.prm.M) * plan.prm.M * plan.prm.M;
+  for (int d = 0; d < 3 && e == hipSuccess; ++d)
+    e = gather_call(plan, {static_cast<const char *>(plan.buf.field) + d * m3 * rs, tgt, gscale,
+                           kGatherIkX + d, nullptr, out_vec});
+  return e;
 }
 
 }  // namespace sek

@@ -114,7 +114,8 @@ se_status check_params(const se_params *prm, double *eta_out) {
   if (p.window != SE_WINDOW_GAUSSIAN && p.window != SE_WINDOW_BSPLINE)
     return fail(SE_ERR_ARG, "unknown window %d", p.window);
   if (p.dtype != SE_FP32 && p.dtype != SE_FP64) return fail(SE_ERR_ARG, "unknown dtype %d", p.dtype);
-  if (p.flags & ~(SE_FLAG_ADD_SELF | SE_FLAG_TIMING)) return fail(SE_ERR_ARG, "unknown flags 0x%x", p.flags);
+  if (p.flags & ~(SE_FLAG_ADD_SELF | SE_FLAG_TIMING | SE_FLAG_IK_FORCE))
+    return fail(SE_ERR_ARG, "unknown flags 0x%x", p.flags);
   if (p.M < 8 || p.M > 512 || (p.M & 1) || !only_235(p.M))
     return fail(SE_ERR_GRID, "M=%d must be even, 8..512 and of the form 2^a 3^b 5^c", p.M);
   if (p.P > p.M) return fail(SE_ERR_GRID, "support %d exceeds M=%d", p.P, p.M);
@@ -131,13 +132,15 @@ se_status check_params(const se_params *prm, double *eta_out) {
     if (p.P < 3 || p.P > 8)
       return fail(SE_ERR_UNSUPPORTED, "B-spline order p=%d: built for 3..8", p.P);
   }
+  if ((p.flags & SE_FLAG_IK_FORCE) && p.window == SE_WINDOW_GAUSSIAN && p.P > 16)
+    return fail(SE_ERR_UNSUPPORTED, "ik forces are built for the tiled supports (P <= 16)");
   if (eta_out) *eta_out = eta;
   return SE_OK;
 }
 
 struct Sizes {
-  size_t grid, ghost, cover, cover_count, spec, sorted, meta, key, counts, offsets, part, tw,
-      f, k2, total;
+  size_t grid, ghost, cover, cover_count, spec, spec2, field, sorted, meta, key, counts, offsets,
+      part, tw, f, k2, total;
 };
 
 // (tile * 64 + index) pairs of the tile blocks covering each grid index along
@@ -177,6 +180,9 @@ Sizes sizes_of(const se_params &p, int n_max, int ntiles, int bin_blocks, int zb
   s.cover = al(T > 0 ? M * max_cover(p, T) * 4 : 0);
   s.cover_count = al(M * 4);
   s.spec = al(M * M * K * 2 * rs);
+  const bool ik = (p.flags & SE_FLAG_IK_FORCE) != 0;
+  s.spec2 = al(ik ? M * M * K * 2 * rs : 0);
+  s.field = al(ik ? 3 * M * M * M * rs : 0);
   s.sorted = al(n * 4 * rs);
   s.meta = al(n * 8);
   s.key = al(n * 8);
@@ -186,7 +192,8 @@ Sizes sizes_of(const se_params &p, int n_max, int ntiles, int bin_blocks, int zb
   s.tw = al(M * 2 * rs);
   s.f = al(M * 8);
   s.k2 = al(M * 8);
-  s.total = s.grid + s.ghost + s.cover + s.cover_count + s.spec + s.sorted + s.meta + s.key +
+  s.total = s.grid + s.ghost + s.cover + s.cover_count + s.spec + s.spec2 + s.field + s.sorted +
+            s.meta + s.key +
             s.counts + s.offsets + s.part + s.tw + s.f + s.k2;
   return s;
 }
@@ -250,6 +257,7 @@ void free_all(se_plan &pl) {
   destroy_events(pl);
   free_targets(pl);
   void *ptrs[] = {pl.buf.grid, pl.buf.ghost, pl.buf.cover, pl.buf.cover_count, pl.buf.spec,
+                  pl.buf.spec2, pl.buf.field,
                   pl.buf.sorted, pl.buf.meta, pl.buf.key, pl.buf.counts, pl.buf.offsets,
                   pl.buf.part, pl.buf.twiddle, pl.buf.axis_f, pl.buf.axis_k2};
   for (void *p : ptrs)
@@ -345,7 +353,8 @@ se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_p
       {&pl->buf.grid, sz.grid},     {&pl->buf.ghost, sz.ghost},
       {reinterpret_cast<void **>(&pl->buf.cover), sz.cover},
       {reinterpret_cast<void **>(&pl->buf.cover_count), sz.cover_count},
-      {&pl->buf.spec, sz.spec},
+      {&pl->buf.spec, sz.spec},     {&pl->buf.spec2, sz.spec2},
+      {&pl->buf.field, sz.field},
       {&pl->buf.sorted, sz.sorted}, {reinterpret_cast<void **>(&pl->buf.meta), sz.meta},
       {reinterpret_cast<void **>(&pl->buf.key), sz.key},
       {reinterpret_cast<void **>(&pl->buf.counts), sz.counts},

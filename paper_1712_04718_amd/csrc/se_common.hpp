@@ -126,6 +126,8 @@ struct DeviceBuffers {
   int *cover = nullptr;       // fold tables (FoldTables)
   int *cover_count = nullptr;
   void *spec = nullptr;       // M*M*(M/2+1) complex half spectrum
+  void *spec2 = nullptr;      // SE_FLAG_IK_FORCE: half spectrum of one field component
+  void *field = nullptr;      // SE_FLAG_IK_FORCE: 3 M^3 real, the field grids -dPhi/dx_d
   void *sorted = nullptr;     // n_max SortedParticle<R>
   int2 *meta = nullptr;       // n_max (packed local anchor, original index)
   int2 *key = nullptr;        // n_max (tile, rank within tile)
@@ -244,6 +246,7 @@ constexpr size_t kMaxLds = 160 * 1024;
 constexpr int kGatherPotentialForce = 0;  // out_pot = phi, out_vec = F
 constexpr int kGatherAdjoint = 1;         // out_pot = gE phi, out_vec = -gE F
 constexpr int kGatherTargets = 2;         // points of plan.tgt: phi (no self term), -grad phi
+constexpr int kGatherIkX = 3;             // +d (d = 0, 1, 2): out_vec[3 n + d] = scale q * (field d at n)
 
 constexpr int kThreads = 256;      // work-group size of the binning, fold and FFT kernels
 constexpr int kTileThreads = 512;  // work-group size of the tile spread and gather kernels

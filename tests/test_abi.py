@@ -54,7 +54,7 @@ def test_eta_matches_paper_formula():
     (dict(window=7), 1), (dict(dtype=3), 1), (dict(flags=8), 1),
     (dict(M=33), 2), (dict(M=14), 2), (dict(M=6), 2), (dict(M=1024), 2), (dict(M=10, P=12), 2),
     (dict(P=7), 4), (dict(P=18), 4), (dict(P=2), 4), (dict(P=26, dtype=1), 4),
-    (dict(P=19, dtype=1), 4),
+    (dict(P=19, dtype=1), 4), (dict(P=18, dtype=1, xi=0.2, flags=4), 4), (dict(flags=16), 1),
     (dict(window=1, P=2), 4), (dict(window=1, P=9), 4),
     (dict(xi=3.0), 3),
 ])
@@ -67,7 +67,8 @@ def test_invalid_parameters_rejected(kw, status):
 def test_valid_parameter_sets():
     for kw in [dict(), dict(dtype=1), dict(window=1, P=4), dict(window=1, P=3),
                dict(window=1, P=7), dict(M=40, L=40.0, P=6), dict(M=30, L=10.0, xi=1.0, P=8),
-               dict(dtype=1, P=18, xi=0.2), dict(dtype=1, P=24, xi=0.2)]:
+               dict(dtype=1, P=18, xi=0.2), dict(dtype=1, P=24, xi=0.2), dict(flags=4),
+               dict(window=1, P=5, flags=4)]:
         st, _ = _check(**kw)
         assert st == _lib.SE_OK, kw
 

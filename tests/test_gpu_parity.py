@@ -328,3 +328,51 @@ def test_wide_support_reaches_the_exact_sum():
     assert O.rel_rms(phi_t.cpu().numpy(), phia[len(x):]) < 1e-12
     assert field_t.shape == (40, 3)
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("window,M,P", [("gaussian", 30, 8), ("gaussian", 48, 12),
+                                        ("bspline", 32, 5), ("bspline", 30, 6)])
+def test_ik_forces(window, M, P, dtype):
+    """SE_FLAG_IK_FORCE: forces by ik differentiation (section 3.1) against the
+    oracle's; E and phi are those of the analytic plan; the field at points
+    and the adjoint (analytic, the exact gradient of E) are unchanged."""
+    L, xi = 10.0, 1.2
+    x, q = _rand(1100, L, 41)
+    print(f"[ik] {window} M={M} P={P} {dtype}", flush=True)
+    xs, qs = to_dev(x, q, dtype)
+    plan = SEPlan(M, P, L, xi, window=window, dtype=dtype, n_max=len(q), ik_force=True)
+    ref = SEPlan(M, P, L, xi, window=window, dtype=dtype, n_max=len(q))
+    E, phi, F = plan.kspace(xs, qs)
+    Ea, phia, Fa = ref.kspace(xs, qs)
+    gx, _ = plan.backward(torch.tensor(1.0, dtype=torch.float64, device=DEV))
+    xt = xs[:50] + 0.3
+    _, field_t = plan.eval_targets(xt)
+    torch.cuda.synchronize()
+    xo, qo = as_oracle_inputs(xs, qs)
+    if window == "gaussian":
+        Eo, phio, Fo = O.se_kspace_ik(xo, qo, L, xi, M, P)
+    else:
+        Eo, phio, Fo = O.spme_kspace_ik(xo, qo, L, xi, M, P)
+    e = errors((E.item(), phi.double().cpu().numpy(), F.double().cpu().numpy()), (Eo, phio, Fo))
+    assert max(e) < TOL[dtype], e
+    # same spread and potential path; FP64 spreads with LDS double atomics, so
+    # it reproduces to rounding only (FP32 bit for bit)
+    rt = 0 if dtype == torch.float32 else 1e-12
+    np.testing.assert_allclose(E.item(), Ea.item(), rtol=rt, atol=0)
+    np.testing.assert_allclose(phi.cpu().numpy(), phia.cpu().numpy(), rtol=0,
+                               atol=rt * float(phia.abs().max()))
+    np.testing.assert_allclose(gx.cpu().numpy(), -Fa.cpu().numpy(), rtol=0,
+                               atol=rt * float(Fa.abs().max()))
+    # the field at a point: each oracle field grid gathered there
+    xto, ones = xt.double().cpu().numpy(), np.ones(50)
+    if window == "gaussian":
+        eta = O.se_eta(L, xi, M, P)
+        grids = O.field_grids(O.se_spread(xo, qo, L, M, P, xi, eta), O.se_influence(L, xi, M, eta), L)
+        Ft = [O.se_gather(xto, ones, L, M, P, xi, eta, g, want_F=False)[0] for g in grids]
+    else:
+        grids = O.field_grids(O.spme_spread(xo, qo, L, M, P), O.spme_influence(L, xi, M, P), L)
+        Ft = [O.spme_gather(xto, ones, L, M, P, g, want_F=False)[0] for g in grids]
+    assert O.rel_rms(field_t.double().cpu().numpy(), np.stack(Ft, axis=1)) < TOL[dtype]
+    for p in (plan, ref):
+        p.close()

@@ -423,3 +423,38 @@ def test_potential_and_field_at_points_match_direct_sum(oracle):
         fd[:, d] = -(pp - pm) / (2 * h)
     assert np.max(np.abs(phi_t - phi_d[len(x):])) < 1e-11 * np.max(np.abs(phi_d))
     assert np.max(np.abs(field_t - fd)) < 1e-7 * np.max(np.abs(fd))
+
+
+def test_ik_forces_reach_the_exact_force(oracle):
+    """Section 3.1: ik differentiation is the most accurate force.  At P = 24
+    on a grid fine enough for the Fourier truncation to vanish, the ik forces
+    equal the exact k-space forces (direct sum) to near machine precision (a
+    k_d applied along the wrong axis fails this) and agree with the
+    analytic-derivative forces of the same method.  At P = 8 both are
+    approximations; the ik forces are the more accurate (1e-5 against 2.5e-4
+    here), and the two differ by about the larger error."""
+    x, q = _rand_neutral(80, 5.0, 17)
+    L, xi = 5.0, 2.0
+    _, _, Fd = oracle.ewald_kspace_direct(x, q, L, xi)
+    E, phi, Fik = oracle.se_kspace_ik(x, q, L, xi, 48, 24)
+    Ea, phia, Fa = oracle.se_kspace(x, q, L, xi, 48, 24)
+    assert oracle.rel_rms(Fik, Fd) < 1e-11
+    assert E == Ea and np.array_equal(phi, phia)
+    assert oracle.rel_rms(Fik, Fa) < 1e-11
+    # at a loose support both are approximations: ik and analytic forces
+    # differ at the level of the method error
+    _, _, Fik8 = oracle.se_kspace_ik(x, q, L, xi, 32, 8)
+    _, _, Fa8 = oracle.se_kspace(x, q, L, xi, 32, 8)
+    e_ik, e_a = oracle.rel_rms(Fik8, Fd), oracle.rel_rms(Fa8, Fd)
+    assert 1e-8 < e_ik < 1e-3 and 1e-8 < e_a < 1e-3
+    assert oracle.rel_rms(Fik8, Fa8) < 3 * max(e_ik, e_a)
+
+
+def test_ik_forces_spme(oracle):
+    """The same ik differentiation behind the SPME window: the force error
+    against the exact force falls with the grid like the analytic one."""
+    x, q = _rand_neutral(80, 5.0, 18)
+    L, xi = 5.0, 2.0
+    _, _, Fd = oracle.ewald_kspace_direct(x, q, L, xi)
+    errs = [oracle.rel_rms(oracle.spme_kspace_ik(x, q, L, xi, M, 6)[2], Fd) for M in (24, 48)]
+    assert errs[1] < errs[0] / 10 and errs[1] < 1e-4
