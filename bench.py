@@ -188,9 +188,9 @@ def summarize_counters(fetch_dir, write_dir, fetch_log, write_log):
           "KiB per dispatch), each scaled by what the counter reads for a calibration copy of "
           f"{CALIB_COPY_BYTES >> 20} MiB (torch.neg): fetch factor {kf:.4f}, write factor {kw:.4f}.\n",
           "```",
-          f"cd /tmp && rocprofv3 --pmc FETCH_SIZE -f csv -d <repo>/gpurun_out/<dir> -o bench -- "
+          f"cd /tmp && rocprofv3 --pmc FETCH_SIZE -f csv -d <out-dir> -o bench -- "
           f"python3 <repo>/bench.py --steps 5 --warmup 2 --no-cpu --no-fp64 --no-real-space",
-          f"cd /tmp && rocprofv3 --pmc WRITE_SIZE -f csv -d <repo>/gpurun_out/<dir> -o bench -- "
+          f"cd /tmp && rocprofv3 --pmc WRITE_SIZE -f csv -d <out-dir> -o bench -- "
           f"python3 <repo>/bench.py --steps 5 --warmup 2 --no-cpu --no-fp64 --no-real-space",
           "```\n",
           "| stage | dispatches | fetch MB | write MB | traffic MB | algorithmic | ratio |",

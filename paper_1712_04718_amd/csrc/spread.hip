@@ -1,6 +1,5 @@
 // Step 2 of Algorithm 1: spread the charges onto the grid (SE eq. 4.5 or
-// SPME eq. 6.1), with neither global atomics nor floating-point atomics in
-// the FP32 path.
+// SPME eq. 6.1), with neither global atomics nor floating-point atomics.
 //
 // One work-group per tile of T^3 anchor points.  The particles anchored in
 // the tile touch a (T+S-1)^3 block of the grid, accumulated in LDS and then
@@ -8,17 +7,16 @@
 // array; a fold kernel then adds the overlapping blocks that cover each grid
 // point, so no grid zeroing and no global atomics are needed.
 //
-// LDS accumulation:
-//   FP32: fixed point in 32-bit integers with a per-tile scale
-//         2^30 / (wmax * sum_tile |q|), where wmax bounds every window value
-//         (beta^3 for the Gaussian, 1 for B-splines): no partial sum can leave
-//         (-2^31, 2^31), each contribution is rounded once, and the result
-//         does not depend on the order of the additions.  (Integer LDS atomics
-//         run far faster than floating-point ones on this chip.)  A
-//         contribution is an FP32 product with 24 significant bits while the
-//         fixed point spans 30, so exact halves are common: they round to
-//         even, which keeps the sum unbiased (rounding halves up would not).
-//   FP64: LDS double atomics.
+// LDS accumulation in fixed point, with a per-tile scale
+// 2^B / (wmax * sum_tile |q|), where wmax bounds every window value (beta^3
+// for the Gaussian, 1 for B-splines): B = 30 in 32-bit integers (FP32) and
+// B = 62 in 64-bit integers (FP64).  No partial sum can leave (-2^(B+1),
+// 2^(B+1)), each contribution is rounded once, and the result does not depend
+// on the order of the additions, so both precisions are bitwise
+// reproducible.  (Integer LDS atomics run far faster than floating-point ones
+// on this chip.)  An FP32 contribution has 24 significant bits while the
+// fixed point spans 30, so exact halves are common: they round to even,
+// which keeps the sum unbiased (rounding halves up would not).
 // Work split: the tile's particles are taken in chunks of one per thread;
 //   phase A: each thread computes its particle's 3S window factors (charge
 //            and scale folded into the x factors) into LDS;
@@ -35,7 +33,7 @@ extern __shared__ __align__(16) unsigned char g_smem[];
 
 template <typename R> struct Acc;
 template <> struct Acc<float> { using T = int; };      // fixed point
-template <> struct Acc<double> { using T = double; };  // floating point
+template <> struct Acc<double> { using T = long long; };  // fixed point
 
 // particles per phase-A round: one per thread, fewer (down to a wave) while
 // the factor table would exceed 32 KB
@@ -74,7 +72,8 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
   constexpr int kChunk = L::CHUNK;
   constexpr int GROUPS = 64 / S;
   constexpr int NWAVES = kTileThreads / 64;
-  constexpr bool FIXED = sizeof(R) == 4;
+  // fixed-point bits of the accumulator
+  constexpr double kFix = sizeof(R) == 4 ? 1073741824.0 : 4611686018427387904.0;  // 2^30, 2^62
   static_assert(NWAVES * 8 <= 128, "per-wave partials must fit the reduction area");
   static_assert(kChunk <= kTileThreads, "phase A holds one particle per thread");
 
@@ -109,7 +108,7 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
   // u = ceil(|q| / qmax * 2^20) >= |q| / qmax * 2^20, and integer sums are
   // exact, so qmax * sum(u) / 2^20 >= sum |q| is the same on every run.
   double scale = 1.0, inv_scale = 1.0;
-  if constexpr (FIXED) {
+  {
     double m = tid < n ? fabs(static_cast<double>(mine.q)) : 0.0;
     for (int p = start + kTileThreads + tid; p < end; p += kTileThreads)
       m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
@@ -133,8 +132,8 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
     for (int w = 0; w < NWAVES; ++w) usum += ured[w];
     const double bound = wmax * qmax * (static_cast<double>(usum) / 1048576.0);
     if (bound > 0.0) {
-      scale = 1073741824.0 / bound;  // 2^30
-      inv_scale = bound / 1073741824.0;
+      scale = kFix / bound;
+      inv_scale = bound / kFix;
     }
   }
 
@@ -188,10 +187,11 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
           const R wz = wq * gz[jz];
 #pragma unroll
           for (int jy = 0; jy < S; ++jy) {
-            if constexpr (FIXED)
+            if constexpr (sizeof(R) == 4)
               atomicAdd(row + (jz * TS + jy) * TS, __float2int_rn(wz * gy[jy]));
-            else
-              unsafeAtomicAdd(row + (jz * TS + jy) * TS, wz * gy[jy]);
+            else  // two's complement: the unsigned add is the signed one
+              atomicAdd(reinterpret_cast<unsigned long long *>(row + (jz * TS + jy) * TS),
+                        static_cast<unsigned long long>(__double2ll_rn(wz * gy[jy])));
           }
         }
       }
@@ -199,11 +199,7 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
   }
   __syncthreads();
   for (int i = tid; i < TS3; i += kTileThreads) {
-    const A v = blk[i];
-    if constexpr (FIXED)
-      out[i] = static_cast<R>(static_cast<double>(v) * inv_scale);
-    else
-      out[i] = v;
+    out[i] = static_cast<R>(static_cast<double>(blk[i]) * inv_scale);
   }
 }
 
