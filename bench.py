@@ -218,6 +218,21 @@ def summarize_counters(fetch_dir, write_dir, fetch_log, write_log):
     print("\n".join(md))
 
 
+def method_error(workload, M, P, window):
+    """Relative rms k-space force error of the method itself at (M, P)
+    against a converged reference, from the stored oracle-only sweep
+    (tests/golden), or None when none covers this configuration."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_method_error.json")
+    if window != "gaussian" or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("M") != M or str(P) not in rec.get("rel_rms_force", {}):
+        return None
+    return {"rel_rms_force": rec["rel_rms_force"][str(P)], "reference": rec["reference"],
+            "source": os.path.relpath(path, ROOT)}
+
+
 def percentile(sorted_vals, p):
     if not sorted_vals:
         return float("nan")
@@ -474,6 +489,7 @@ def run(args):
         "step_ms": {"median": percentile(ps, 0.5), "p10": percentile(ps, 0.1),
                     "p90": percentile(ps, 0.9)},
         "rms_force_err_vs_fp64_oracle": f32["err_F"],
+        "method_error": method_error(args.workload, M, P, window),
         "energy_rel_err_vs_fp64_oracle": f32["err_E"],
         "graph": {"ms_per_step": f32["ms_graph"], "value": N / (f32["ms_graph"] * 1e-3)},
         "autograd": {"ms_per_step": f32["ms_autograd"],

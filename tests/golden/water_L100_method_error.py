@@ -6,8 +6,8 @@ the SE force at P = 24 on the same grid (window error e^{-pi P c^2/2} =
 FP32 headline at P = 8 is quoted at.  Errors are relative rms,
 (sum |F - F*|^2 / sum |F*|^2)^(1/2), as used throughout.
 
-Calls only the oracle.  Writes water_method_error.json beside this file:
-    python tests/golden/water_method_error.py
+Calls only the oracle.  Writes water_L100_method_error.json beside this file:
+    python tests/golden/water_L100_method_error.py
 """
 import json
 import os
@@ -47,7 +47,7 @@ def main():
         e = O.rel_rms(force_at(x, q, L, xi, P, idx), Fref)
         out["rel_rms_force"][str(P)] = e
         print(f"P={P}: {e:.3e}", flush=True)
-    with open(os.path.join(HERE, "water_method_error.json"), "w") as f:
+    with open(os.path.join(HERE, "water_L100_method_error.json"), "w") as f:
         json.dump(out, f, indent=1)
 
 
