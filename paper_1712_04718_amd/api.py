@@ -9,6 +9,7 @@ kernels of libsekspace.so.  PyTorch supplies device memory and the stream.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 import torch
@@ -22,6 +23,14 @@ _WINDOWS = {"gaussian": _lib.SE_WINDOW_GAUSSIAN, "se": _lib.SE_WINDOW_GAUSSIAN,
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _on(device):
+    """Context making ``device`` current; a no-op when it already is (the
+    common case, and the switch costs microseconds per call)."""
+    if torch.cuda.current_device() == device.index:
+        return contextlib.nullcontext()
+    return torch.cuda.device(device)
 
 
 class SEPlan:
@@ -62,6 +71,8 @@ class SEPlan:
 
     # ------------------------------------------------------------ helpers
     def _bind_stream(self):
+        # every call enqueues on torch's current stream of the plan's device
+        # (set each time: the plan may also be driven through the C ABI)
         s = torch.cuda.current_stream(self.device).cuda_stream
         _lib.check(self.lib.se_plan_set_stream(self._plan, ctypes.c_void_p(s)))
 
@@ -81,7 +92,7 @@ class SEPlan:
         """Steps 1-5: returns E (0-d float64 tensor on the device)."""
         x, q = self._check_inputs(x, q)
         E = torch.empty((), dtype=torch.float64, device=self.device)
-        with torch.cuda.device(self.device):
+        with _on(self.device):
             self._bind_stream()
             _lib.check(self.lib.se_forward(self._plan, int(x.shape[0]), _ptr(x), _ptr(q), _ptr(E)))
         self._keep = (x, q)  # inputs stay alive until the enqueued work has used them
@@ -95,7 +106,7 @@ class SEPlan:
             raise RuntimeError("gather before forward")
         phi = torch.empty(self._N, dtype=self.dtype, device=self.device) if want_phi else None
         F = torch.empty(self._N, 3, dtype=self.dtype, device=self.device) if want_F else None
-        with torch.cuda.device(self.device):
+        with _on(self.device):
             self._bind_stream()
             _lib.check(self.lib.se_gather(self._plan, _ptr(phi), _ptr(F)))
         return phi, F
@@ -113,7 +124,7 @@ class SEPlan:
         gE = gE.to(device=self.device, dtype=torch.float64).reshape(()).contiguous()
         gx = torch.empty(self._N, 3, dtype=self.dtype, device=self.device) if want_x else None
         gq = torch.empty(self._N, dtype=self.dtype, device=self.device) if want_q else None
-        with torch.cuda.device(self.device):
+        with _on(self.device):
             self._bind_stream()
             _lib.check(self.lib.se_backward(self._plan, _ptr(gE), _ptr(gx), _ptr(gq)))
         self._keep_g = gE
@@ -133,7 +144,7 @@ class SEPlan:
             self._tcap = max(nt, 1)
         phi = torch.empty(nt, dtype=self.dtype, device=self.device) if want_phi else None
         field = torch.empty(nt, 3, dtype=self.dtype, device=self.device) if want_field else None
-        with torch.cuda.device(self.device):
+        with _on(self.device):
             self._bind_stream()
             _lib.check(self.lib.se_eval_targets(self._plan, nt, _ptr(xt), _ptr(phi), _ptr(field)))
         self._keep_t = xt
@@ -194,7 +205,7 @@ class RealSpacePlan:
         E = torch.empty((), dtype=torch.float64, device=self.device)
         phi = torch.empty(N, dtype=self.dtype, device=self.device) if want_phi else None
         F = torch.empty(N, 3, dtype=self.dtype, device=self.device) if want_F else None
-        with torch.cuda.device(self.device):
+        with _on(self.device):
             s = torch.cuda.current_stream(self.device).cuda_stream
             _lib.check(self.lib.se_rs_plan_set_stream(self._plan, ctypes.c_void_p(s)))
             _lib.check(self.lib.se_rs_eval(self._plan, N, _ptr(x), _ptr(q), _ptr(E), _ptr(phi),
