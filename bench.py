@@ -340,6 +340,30 @@ def run(args):
         torch.cuda.synchronize()
         ms_autograd = e0.elapsed_time(e1) / args.steps
 
+        # the same forward + backward captured once in a HIP graph (the
+        # adjoint reads dL/dE from device memory, so the whole step replays)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                fwd_bwd()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        xg.grad = None
+        qg.grad = None
+        ga = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(ga):
+            SEEnergy.apply(xg, qg, plan).backward()
+        for _ in range(args.warmup):
+            ga.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            ga.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_autograd_graph = e0.elapsed_time(e1) / args.steps
+
         # per-kernel durations: a plan that records a HIP event pair around
         # every launch on its stream, over a timed region of K steps
         tplan = SEPlan(M, P, L, xi, window=window, dtype=dtype, n_max=N, device=dev,
@@ -373,7 +397,7 @@ def run(args):
         err_F = O.rel_rms(Fg, Fo)
         err_E = abs(E.item() - Eo) / abs(Eo)
         out[tag] = dict(ms_eager=ms_eager, ms_graph=ms_graph, per_step=per_step,
-                        ms_autograd=ms_autograd,
+                        ms_autograd=ms_autograd, ms_autograd_graph=ms_autograd_graph,
                         ms_timed_eager=ms_timed_eager, err_F=err_F, err_E=err_E,
                         stages_ms=stages)
         for t in (plan, tplan):
@@ -494,7 +518,10 @@ def run(args):
         "graph": {"ms_per_step": f32["ms_graph"], "value": N / (f32["ms_graph"] * 1e-3)},
         "autograd": {"ms_per_step": f32["ms_autograd"],
                      "value": N / (f32["ms_autograd"] * 1e-3),
-                     "step": "SEEnergy forward + backward (dE/dx, dE/dq)"},
+                     "graph_ms_per_step": f32["ms_autograd_graph"],
+                     "graph_value": N / (f32["ms_autograd_graph"] * 1e-3),
+                     "step": "SEEnergy forward + backward (dE/dx, dE/dq); graph: the same "
+                             "captured once in a HIP graph and replayed"},
         "stages_us": {k: round(v * 1e3, 2) for k, v in stages.items()},
         "stages_region_ms_per_step": f32["ms_timed_eager"],
         "grid_pass_hbm_frac": hbm_frac,
