@@ -47,7 +47,7 @@ KERNEL_SOURCES = {
     "bin_scan": ("bin.hip", "se_common.hpp"),
     "bin_scatter": ("bin.hip", "se_common.hpp"),
 }
-for _st in ("fft_x", "fft_y", "fft_z_scale", "ifft_y", "ifft_x"):
+for _st in ("fft_x", "fft_y", "fft_z_scale", "ifft_y", "ifft_x", "fft_xy", "ifft_yx"):
     KERNEL_SOURCES[_st] = ("fft.hip", "se_common.hpp")
 
 
@@ -59,6 +59,7 @@ STAGE_KERNEL_RE = {
     "fft_x": r"k_fft_x_r2c<float,", "fft_y": r"k_fft_y<float, -?\d+, \d+, false>",
     "fft_z_scale": r"k_fft_z_scale<float,", "ifft_y": r"k_fft_y<float, -?\d+, \d+, true>",
     "ifft_x": r"k_fft_x_c2r<float,", "gather": r"k_gather<float,",
+    "fft_xy": r"k_fft_xy_r2c<float,", "ifft_yx": r"k_fft_yx_c2r<float,",
 }
 CALIB_KERNEL_RE = r"neg_kernel"
 
@@ -104,9 +105,9 @@ def kernel_work(stage, N, M, P, rs, window):
     if stage == "fold":
         ts = T + P - 1
         return "bytes", ((M + T - 1) // T) ** 3 * ts ** 3 * rs + grid
-    if stage == "fft_x":
+    if stage in ("fft_x", "fft_xy"):
         return "bytes", grid + spec
-    if stage == "ifft_x":
+    if stage in ("ifft_x", "ifft_yx"):
         return "bytes", spec + grid
     return "bytes", 2 * spec                                # fft_y, fft_z_scale, ifft_y
 

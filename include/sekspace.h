@@ -80,7 +80,8 @@ typedef enum { SE_FP32 = 0, SE_FP64 = 1 } se_dtype;
                                 adjoint (the exact gradient of E).  Tiled
                                 supports only (SE P <= 16, SPME).            */
 
-/* Kernel stages of one evaluation, in launch order (se_plan_stage_times). */
+/* Kernel stages of one evaluation (se_plan_stage_times), in launch order
+   apart from the fused plane passes at the end. */
 enum {
     SE_STAGE_BIN_COUNT = 0,  /* tile of each particle, its rank in the tile  */
     SE_STAGE_BIN_SCAN,       /* tile offsets (exclusive scan of the counts)  */
@@ -93,6 +94,11 @@ enum {
     SE_STAGE_IFFT_Y,         /* step 5, along y                              */
     SE_STAGE_IFFT_X,         /* step 5, complex-to-real along x              */
     SE_STAGE_GATHER,         /* step 6 (se_gather or se_backward)            */
+    SE_STAGE_FFT_XY,         /* step 3, x and y in one pass per z plane: in
+                                place of FFT_X + FFT_Y where an M x (M/2+1)
+                                plane fits in LDS twice (FP32 M <= 128, FP64
+                                M <= 96, compiled sizes)                     */
+    SE_STAGE_IFFT_YX,        /* step 5, the same in place of IFFT_Y + IFFT_X */
     SE_NUM_STAGES
 };
 

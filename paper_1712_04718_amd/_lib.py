@@ -20,7 +20,7 @@ SE_FLAG_ADD_SELF = 1
 SE_FLAG_TIMING = 2
 SE_FLAG_IK_FORCE = 4
 STAGES = ("bin_count", "bin_scan", "bin_scatter", "spread", "fold", "fft_x", "fft_y",
-          "fft_z_scale", "ifft_y", "ifft_x", "gather")
+          "fft_z_scale", "ifft_y", "ifft_x", "gather", "fft_xy", "ifft_yx")
 
 STATUS_NAMES = {
     0: "SE_OK", 1: "SE_ERR_ARG", 2: "SE_ERR_GRID", 3: "SE_ERR_ETA",

@@ -188,20 +188,22 @@ constexpr RadixList radix_list(int M) {
   return l;
 }
 
-template <typename R, int M, int LGB, int RAD, int NS>
+// B pencils (any count), element e of pencil b at e * PB + b (PB >= B: a
+// padded row), NT threads; lanes run over b fastest.
+template <typename R, int M, int B, int PB, int NT, int RAD, int NS>
 __device__ inline void stockham_stage_ct(const cplx_t<R> *in, cplx_t<R> *out,
                                          const cplx_t<R> *tw) {
   using C = cplx_t<R>;
-  constexpr int B = 1 << LGB, NB = M / RAD, TOTAL = NB * B, TSTEP = M / (NS * RAD);
+  constexpr int NB = M / RAD, TOTAL = NB * B, TSTEP = M / (NS * RAD);
 #pragma unroll
-  for (int t0 = 0; t0 < TOTAL; t0 += kThreads) {
+  for (int t0 = 0; t0 < TOTAL; t0 += NT) {
     const int t = t0 + static_cast<int>(threadIdx.x);
-    if (TOTAL % kThreads == 0 || t < TOTAL) {
-      const int b = t & (B - 1), j = t >> LGB;
+    if (TOTAL % NT == 0 || t < TOTAL) {
+      const int j = t / B, b = t - j * B;
       const int q = j / NS, k = j - q * NS;
       C v[RAD];
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) v[r] = in[((j + r * NB) << LGB) + b];
+      for (int r = 0; r < RAD; ++r) v[r] = in[(j + r * NB) * PB + b];
       if (NS > 1 && k != 0) {
 #pragma unroll
         for (int r = 1; r < RAD; ++r) v[r] = cmul(v[r], tw[r * k * TSTEP]);
@@ -213,21 +215,23 @@ __device__ inline void stockham_stage_ct(const cplx_t<R> *in, cplx_t<R> *out,
       if constexpr (RAD == 8) dft8<R, C>(v);
       const int dst = q * NS * RAD + k;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) out[((dst + r * NS) << LGB) + b] = v[r];
+      for (int r = 0; r < RAD; ++r) out[(dst + r * NS) * PB + b] = v[r];
     }
   }
 }
 
-template <typename R, int M, int LGB, int STAGE, int NS>
+// All stages, ping-ponging between in and out; returns the buffer holding
+// the result.
+template <typename R, int M, int B, int PB, int NT, int STAGE, int NS>
 __device__ inline cplx_t<R> *fft_batch_ct(cplx_t<R> *in, cplx_t<R> *out, const cplx_t<R> *tw) {
   constexpr RadixList L = radix_list(M);
   if constexpr (STAGE == L.n) {
     return in;
   } else {
     constexpr int RAD = L.r[STAGE];
-    stockham_stage_ct<R, M, LGB, RAD, NS>(in, out, tw);
+    stockham_stage_ct<R, M, B, PB, NT, RAD, NS>(in, out, tw);
     __syncthreads();
-    return fft_batch_ct<R, M, LGB, STAGE + 1, NS * RAD>(out, in, tw);
+    return fft_batch_ct<R, M, B, PB, NT, STAGE + 1, NS * RAD>(out, in, tw);
   }
 }
 
@@ -236,7 +240,7 @@ template <typename R, int MC, int LGBC>
 __device__ inline cplx_t<R> *fft_any(cplx_t<R> *buf0, cplx_t<R> *buf1, int lgB, const FftPlan &pl,
                                      const cplx_t<R> *tw) {
   if constexpr (MC > 0)
-    return fft_batch_ct<R, MC, LGBC, 0, 1>(buf0, buf1, tw);
+    return fft_batch_ct<R, MC, 1 << LGBC, 1 << LGBC, kThreads, 0, 1>(buf0, buf1, tw);
   else
     return fft_batch<R>(buf0, buf1, lgB, pl, tw);
 }
@@ -366,6 +370,35 @@ struct EnergyOut {
   double *E;
 };
 
+// E = sum of the z pass's energy partials (+ self_coef sum q^2), each sum
+// taken in a fixed order: per-thread strided sums, then a fixed tree over
+// the lanes of a wave and over the waves.  Called by the whole work-group.
+template <int NT>
+__device__ inline void write_energy(const EnergyOut &eo) {
+  __shared__ double wred[2][NT / 64];
+  double se = 0.0, sq = 0.0;
+  for (int b = threadIdx.x; b < eo.nparts; b += NT) se += eo.part[b];
+  if (eo.self_coef != 0.0)
+    for (int b = threadIdx.x; b < eo.nq; b += NT) sq += eo.qsq_part[b];
+  for (int o = 32; o > 0; o >>= 1) {
+    se += __shfl_xor(se, o);
+    sq += __shfl_xor(sq, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    wred[0][threadIdx.x >> 6] = se;
+    wred[1][threadIdx.x >> 6] = sq;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e = 0.0, q = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+      e += wred[0][w];
+      q += wred[1][w];
+    }
+    *eo.E = e + eo.self_coef * q;
+  }
+}
+
 template <typename R, int MC, int LGBC, bool INV>
 __global__ void __launch_bounds__(kThreads)
 k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__restrict__ tw_g,
@@ -410,24 +443,157 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
       spec[static_cast<long long>(c0 + b) * M + y] = v;
     }
   }
-  if (INV && blockIdx.x == 0 && eo.E) {
-    __shared__ double red[kThreads], redq[kThreads];
-    double se = 0.0, sq = 0.0;
-    for (int b = threadIdx.x; b < eo.nparts; b += kThreads) se += eo.part[b];
-    if (eo.self_coef != 0.0)
-      for (int b = threadIdx.x; b < eo.nq; b += kThreads) sq += eo.qsq_part[b];
-    red[threadIdx.x] = se;
-    redq[threadIdx.x] = sq;
-    __syncthreads();
-    for (int st = kThreads / 2; st > 0; st >>= 1) {
-      if (threadIdx.x < st) {
-        red[threadIdx.x] += red[threadIdx.x + st];
-        redq[threadIdx.x] += redq[threadIdx.x + st];
-      }
-      __syncthreads();
+  if (INV && blockIdx.x == 0 && eo.E) write_energy<kThreads>(eo);
+}
+
+// ------------------------------------------------- fused x-y plane passes
+//
+// When two M x (M/2 + 1) complex buffers fit in LDS, one work-group per z
+// plane does both in-plane transforms, so that the 3D FFT and its inverse
+// take three launches (xy, z with scaling, yx) instead of five:
+//   k_fft_xy_r2c: the plane's real rows in pairs as complex rows (x-major),
+//     FFT along x, split into the two half spectra, FFT along y of the
+//     M/2 + 1 kx pencils, store C[z][kx][y];
+//   k_fft_yx_c2r: the mirror image (conjugated input, inverse along y,
+//     Hermitian rebuild, inverse along x, real rows out).
+// Rows in LDS hold PB = (M/2 + 1) | 1 complex values: with an odd row
+// length the column walks of the load, split and store phases keep 64-bit
+// LDS accesses conflict-free within each half wave.
+template <int M> struct PlaneGeom {
+  static constexpr int H = M / 2, K = M / 2 + 1, PB = K | 1, BUF = M * PB;
+};
+template <typename R, int M> constexpr size_t plane_lds_bytes() {
+  return sizeof(cplx_t<R>) * (2 * PlaneGeom<M>::BUF + M);
+}
+// threads per plane work-group: about four complex values per thread, 64..1024
+constexpr int plane_threads(int M) {
+  int nt = 64;
+  while (nt < 1024 && 4 * nt < (M / 2) * M) nt *= 2;
+  return nt;
+}
+template <typename R, int M> constexpr bool plane_fits() {
+  return plane_lds_bytes<R, M>() <= kMaxLds && M % 4 == 0;
+}
+
+template <typename R, int M, int NT>
+__global__ void __launch_bounds__(NT)
+k_fft_xy_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec,
+             const cplx_t<R> *__restrict__ tw_g) {
+  using C = cplx_t<R>;
+  using G = PlaneGeom<M>;
+  constexpr int H = G::H, K = G::K, PB = G::PB;
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + G::BUF, *twl = b1 + G::BUF;
+  for (int i = threadIdx.x; i < M; i += NT) twl[i] = tw_g[i];
+  const long long z = blockIdx.x;
+  const R *plane = grid + z * M * M;
+  // pencil b = rows 2b (real part) and 2b + 1 (imaginary part); all loads
+  // are issued before the first LDS store
+  constexpr int NP = H * M, PER = (NP + NT - 1) / NT;
+  R re[PER], im[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = threadIdx.x + k * NT;  // i = b M + x
+    if (NP % NT == 0 || i < NP) {
+      const int b = i / M, x = i - b * M;
+      re[k] = plane[(2 * b) * M + x];
+      im[k] = plane[(2 * b + 1) * M + x];
     }
-    if (threadIdx.x == 0) *eo.E = red[0] + eo.self_coef * redq[0];
   }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = threadIdx.x + k * NT;
+    if (NP % NT == 0 || i < NP) {
+      const int b = i / M, x = i - b * M;
+      C v;
+      v.x = re[k];
+      v.y = im[k];
+      b0[x * PB + b] = v;
+    }
+  }
+  __syncthreads();
+  C *X = fft_batch_ct<R, M, H, PB, NT, 0, 1>(b0, b1, twl);
+  C *Y = (X == b0) ? b1 : b0;
+  // Z = FFT(r1 + i r2): R1[k] = (Z[k] + conj Z[M-k]) / 2 (row 2b),
+  // R2[k] = (Z[k] - conj Z[M-k]) / 2i (row 2b + 1); element y of kx pencil k
+  for (int i = threadIdx.x; i < H * K; i += NT) {
+    const int b = i / K, k = i - b * K;
+    const C zk = X[k * PB + b];
+    const C zm = X[(k == 0 ? 0 : M - k) * PB + b];
+    C r1, r2;
+    r1.x = R(0.5) * (zk.x + zm.x);
+    r1.y = R(0.5) * (zk.y - zm.y);
+    r2.x = R(0.5) * (zk.y + zm.y);
+    r2.y = R(-0.5) * (zk.x - zm.x);
+    Y[(2 * b) * PB + k] = r1;
+    Y[(2 * b + 1) * PB + k] = r2;
+  }
+  __syncthreads();
+  const C *S = fft_batch_ct<R, M, K, PB, NT, 0, 1>(Y, X, twl);
+  C *out = spec + z * K * M;
+  for (int i = threadIdx.x; i < K * M; i += NT) {
+    const int kx = i / M, y = i - kx * M;
+    out[i] = S[y * PB + kx];
+  }
+}
+
+template <typename R, int M, int NT>
+__global__ void __launch_bounds__(NT)
+k_fft_yx_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid,
+             const cplx_t<R> *__restrict__ tw_g, EnergyOut eo) {
+  using C = cplx_t<R>;
+  using G = PlaneGeom<M>;
+  constexpr int H = G::H, K = G::K, PB = G::PB;
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + G::BUF, *twl = b1 + G::BUF;
+  for (int i = threadIdx.x; i < M; i += NT) twl[i] = tw_g[i];
+  const long long z = blockIdx.x;
+  const C *in = spec + z * K * M;
+  // conjugated on the way in: the inverse is conj(FFT(conj(.)))
+  constexpr int NS = K * M, PER = (NS + NT - 1) / NT;
+  C v[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = threadIdx.x + k * NT;  // i = kx M + y
+    if (NS % NT == 0 || i < NS) v[k] = in[i];
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = threadIdx.x + k * NT;
+    if (NS % NT == 0 || i < NS) {
+      const int kx = i / M, y = i - kx * M;
+      b0[y * PB + kx] = cconj(v[k]);
+    }
+  }
+  __syncthreads();
+  C *Y = fft_batch_ct<R, M, K, PB, NT, 0, 1>(b0, b1, twl);  // conj of the inverse along y
+  C *X = (Y == b0) ? b1 : b0;
+  // rows 2b, 2b + 1 with half spectra R1, R2 (the conjugates of Y's):
+  // Z[k] = R1[k] + i R2[k] on 0..M/2, conj(R1[M-k]) + i conj(R2[M-k]) above,
+  // stored conjugated for the inverse along x
+  for (int i = threadIdx.x; i < H * K; i += NT) {
+    const int b = i / K, k = i - b * K;
+    const C r1 = cconj(Y[(2 * b) * PB + k]);
+    const C r2 = cconj(Y[(2 * b + 1) * PB + k]);
+    C zz;
+    zz.x = r1.x - r2.y;
+    zz.y = -(r1.y + r2.x);
+    X[k * PB + b] = zz;
+    if (k > 0 && k < M - k) {
+      C zc;
+      zc.x = r1.x + r2.y;
+      zc.y = -(r2.x - r1.y);
+      X[(M - k) * PB + b] = zc;
+    }
+  }
+  __syncthreads();
+  const C *Zr = fft_batch_ct<R, M, H, PB, NT, 0, 1>(X, Y, twl);
+  R *out = grid + z * M * M;
+  for (int i = threadIdx.x; i < H * M; i += NT) {
+    const int b = i / M, x = i - b * M;
+    const C zz = Zr[x * PB + b];
+    out[(2 * b) * M + x] = zz.x;       // real part of the conjugate
+    out[(2 * b + 1) * M + x] = -zz.y;  // imaginary part of the conjugate
+  }
+  if (blockIdx.x == 0 && eo.E) write_energy<NT>(eo);
 }
 
 // ------------------------------------------ z pass with scaling and energy
@@ -528,8 +694,68 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
   if (threadIdx.x == 0) epart[blockIdx.x] = red[0];
 }
 
+// The three-launch sequence with the fused plane passes (compile-time M
+// whose plane buffers fit in LDS).
+template <typename R, int MC>
+hipError_t fft_run_planes(se_plan &p, double *E_dev) {
+  using C = cplx_t<R>;
+  constexpr int LZ = fft_lgb(MC, sizeof(R), kPassZ);
+  constexpr int NT = plane_threads(MC);
+  constexpr size_t lds = plane_lds_bytes<R, MC>();
+  if (MC != p.prm.M || LZ != p.fft_lgb[kPassZ] || p.fft_threads != kThreads)
+    return hipErrorInvalidValue;
+  hipError_t e;
+  if (lds > 65536) {
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_xy_r2c<R, MC, NT>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 static_cast<int>(lds))) != hipSuccess)
+      return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_yx_c2r<R, MC, NT>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 static_cast<int>(lds))) != hipSuccess)
+      return e;
+  }
+  const size_t lds_z = sizeof(C) * (2 * MC * (1 << LZ) + MC);
+  C *spec = static_cast<C *>(p.buf.spec);
+  const C *tw = static_cast<const C *>(p.buf.twiddle);
+  stage_begin(p, SE_STAGE_FFT_XY);
+  k_fft_xy_r2c<R, MC, NT><<<MC, NT, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec, tw);
+  stage_end(p, SE_STAGE_FFT_XY);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const double tpl = 2.0 * M_PI / p.prm.L;
+  const EnergyOut none{nullptr, 0, nullptr, 0, 0.0, nullptr};
+  if (p.prm.flags & SE_FLAG_IK_FORCE) {
+    // the three field components first (they read the forward spectrum,
+    // which the potential's z pass then overwrites); not timed
+    C *spec2 = static_cast<C *>(p.buf.spec2);
+    for (int d = 0; d < 3; ++d) {
+      k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_z, p.stream>>>(
+          spec, spec2, p.fft, LZ, tw, static_cast<const double *>(p.buf.axis_f),
+          static_cast<const double *>(p.buf.axis_k2), p.wscale, nullptr, d, tpl);
+      k_fft_yx_c2r<R, MC, NT><<<MC, NT, lds, p.stream>>>(
+          spec2, static_cast<R *>(p.buf.field) + static_cast<long long>(d) * MC * MC * MC, tw,
+          none);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  stage_begin(p, SE_STAGE_FFT_Z_SCALE);
+  k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_z, p.stream>>>(
+      spec, spec, p.fft, LZ, tw, static_cast<const double *>(p.buf.axis_f),
+      static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks, -1, tpl);
+  stage_end(p, SE_STAGE_FFT_Z_SCALE);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const double self_coef = (p.prm.flags & SE_FLAG_ADD_SELF) ? -p.prm.xi / sqrt(M_PI) : 0.0;
+  const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.part, p.bin_parts, self_coef,
+                     E_dev};
+  stage_begin(p, SE_STAGE_IFFT_YX);
+  k_fft_yx_c2r<R, MC, NT><<<MC, NT, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), tw, eo);
+  stage_end(p, SE_STAGE_IFFT_YX);
+  return hipGetLastError();
+}
+
 template <typename R, int MC>
 hipError_t fft_run(se_plan &p, double *E_dev) {
+  if constexpr (MC > 0 && plane_fits<R, MC>()) return fft_run_planes<R, MC>(p, E_dev);
   // compiled pencils per work-group of each pass (ignored for MC = 0)
   constexpr int LX = MC > 0 ? fft_lgb(MC, sizeof(R), kPassX) : 0;
   constexpr int LY = MC > 0 ? fft_lgb(MC, sizeof(R), kPassY) : 0;

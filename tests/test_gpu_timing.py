@@ -11,20 +11,27 @@ from paper_1712_04718_amd import SEPlan, _lib
 pytestmark = pytest.mark.gpu
 
 
-def test_stage_means_cover_every_launch_and_reset():
-    print("[timing] N=3000 L=20 M=40 P=8 fp32, 40 steps", flush=True)
+FIVE_PASSES = {"fft_x", "fft_y", "ifft_y", "ifft_x"}
+PLANE_PASSES = {"fft_xy", "ifft_yx"}
+
+
+# M = 40: the plane fits in LDS, so x and y run as one pass each way;
+# M = 144 in FP32 does not fit and runs the five separate passes
+@pytest.mark.parametrize("M,fft_stages", [(40, PLANE_PASSES), (144, FIVE_PASSES)])
+def test_stage_means_cover_every_launch_and_reset(M, fft_stages):
+    print(f"[timing] N=3000 L=20 M={M} P=8 fp32, 40 steps", flush=True)
     rng = np.random.default_rng(11)
     x = rng.random((3000, 3)) * 20.0
     q = rng.standard_normal(3000)
     q -= q.mean()
     xt, qt = to_dev(x, q, torch.float32)
-    ref = SEPlan(40, 8, 20.0, 0.6, dtype=torch.float32, n_max=3000)
-    tim = SEPlan(40, 8, 20.0, 0.6, dtype=torch.float32, n_max=3000, timing=True)
+    ref = SEPlan(M, 8, 20.0, 0.6, dtype=torch.float32, n_max=3000)
+    tim = SEPlan(M, 8, 20.0, 0.6, dtype=torch.float32, n_max=3000, timing=True)
     E0, phi0, F0 = ref.kspace(xt, qt)
     for _ in range(40):  # more launches than the ring of event pairs holds
         E1, phi1, F1 = tim.kspace(xt, qt)
     times = tim.stage_times()
-    assert set(times) == set(_lib.STAGES)
+    assert set(times) == (set(_lib.STAGES) - FIVE_PASSES - PLANE_PASSES) | fft_stages
     assert all(v > 0 for v in times.values()), times
     # nothing launched since the read: every stage reports "not launched"
     assert tim.stage_times() == {}
