@@ -163,8 +163,10 @@ k_bin_count_run(int N, const R *__restrict__ x, const R *__restrict__ q, double 
 }
 
 // One work-group: exclusive scan of the tile counts into offsets, and the
-// counts reset for the next call.  Each thread requests its whole chunk of
-// counts before using any.
+// counts reset for the next call.  Each thread takes a contiguous chunk of
+// tiles and requests all its counts before using any; the chunk sums are
+// scanned within each wave by shuffles and across the waves through LDS
+// (one barrier).
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 32;  // counts per thread held in registers
 __global__ void __launch_bounds__(kScanThreads)
@@ -179,16 +181,19 @@ k_bin_scan(int *__restrict__ counts, int *__restrict__ offsets, int ntiles) {
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) local += v[k];
   for (int t = lo + kScanPer; t < hi; ++t) local += counts[t * kCountStride];  // > 32K tiles
-  __shared__ int scan[kScanThreads];
-  scan[tid] = local;
-  __syncthreads();
-  for (int s = 1; s < kScanThreads; s <<= 1) {  // inclusive Hillis-Steele scan
-    const int u = tid >= s ? scan[tid - s] : 0;
-    __syncthreads();
-    scan[tid] += u;
-    __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
+  int incl = local;  // inclusive scan over the lanes of the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
   }
-  int run = scan[tid] - local;
+  __shared__ int wsum[kScanThreads / 64];
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wave; ++w) base += wsum[w];
+  int run = base + incl - local;
   const auto emit = [&](int t, int c) {
     offsets[t] = run;
     run += c;
@@ -198,7 +203,7 @@ k_bin_scan(int *__restrict__ counts, int *__restrict__ offsets, int ntiles) {
   for (int k = 0; k < kScanPer; ++k)
     if (lo + k < hi) emit(lo + k, v[k]);
   for (int t = lo + kScanPer; t < hi; ++t) emit(t, counts[t * kCountStride]);
-  if (tid == kScanThreads - 1) offsets[ntiles] = scan[kScanThreads - 1];
+  if (tid == kScanThreads - 1) offsets[ntiles] = base + incl;
 }
 
 template <typename R>

@@ -448,22 +448,29 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
 
 // ------------------------------------------------- fused x-y plane passes
 //
-// When two M x (M/2 + 1) complex buffers fit in LDS, one work-group per z
-// plane does both in-plane transforms, so that the 3D FFT and its inverse
-// take three launches (xy, z with scaling, yx) instead of five:
+// When two M x (M/2 + 1) complex buffers fit in LDS, work-groups that each
+// hold a whole z plane do both in-plane transforms, so that the 3D FFT and
+// its inverse take three launches (xy, z with scaling, yx) instead of five:
 //   k_fft_xy_r2c: the plane's real rows in pairs as complex rows (x-major),
-//     FFT along x, split into the two half spectra, FFT along y of the
-//     M/2 + 1 kx pencils, store C[z][kx][y];
+//     FFT along x, split into the two half spectra, FFT along y of the kx
+//     pencils, store C[z][kx][y];
 //   k_fft_yx_c2r: the mirror image (conjugated input, inverse along y,
 //     Hermitian rebuild, inverse along x, real rows out).
+// NS work-groups share a plane so that more CUs take part: each repeats the
+// first transform of the plane (along x forward, along y inverse) and does
+// the second for its 1/NS of the pencils (kx pencils forward, row pairs
+// inverse).
 // Rows in LDS hold PB = (M/2 + 1) | 1 complex values: with an odd row
 // length the column walks of the load, split and store phases keep 64-bit
 // LDS accesses conflict-free within each half wave.
-template <int M> struct PlaneGeom {
+template <int M, int NS> struct PlaneGeom {
   static constexpr int H = M / 2, K = M / 2 + 1, PB = K | 1, BUF = M * PB;
+  static constexpr int KP = (K + NS - 1) / NS;  // kx pencils per work-group (forward)
+  static constexpr int HP = H / NS;             // row pairs per work-group (inverse)
 };
+constexpr int kPlaneSplit = 2;
 template <typename R, int M> constexpr size_t plane_lds_bytes() {
-  return sizeof(cplx_t<R>) * (2 * PlaneGeom<M>::BUF + M);
+  return sizeof(cplx_t<R>) * (2 * PlaneGeom<M, 1>::BUF + M);
 }
 // threads per plane work-group: about four complex values per thread, 64..1024
 constexpr int plane_threads(int M) {
@@ -472,19 +479,20 @@ constexpr int plane_threads(int M) {
   return nt;
 }
 template <typename R, int M> constexpr bool plane_fits() {
-  return plane_lds_bytes<R, M>() <= kMaxLds && M % 4 == 0;
+  return plane_lds_bytes<R, M>() <= kMaxLds && M % 4 == 0 && (M / 2) % kPlaneSplit == 0;
 }
 
-template <typename R, int M, int NT>
+template <typename R, int M, int NT, int NS>
 __global__ void __launch_bounds__(NT)
 k_fft_xy_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec,
              const cplx_t<R> *__restrict__ tw_g) {
   using C = cplx_t<R>;
-  using G = PlaneGeom<M>;
-  constexpr int H = G::H, K = G::K, PB = G::PB;
+  using G = PlaneGeom<M, NS>;
+  constexpr int H = G::H, K = G::K, PB = G::PB, KP = G::KP;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + G::BUF, *twl = b1 + G::BUF;
   for (int i = threadIdx.x; i < M; i += NT) twl[i] = tw_g[i];
-  const long long z = blockIdx.x;
+  const long long z = blockIdx.x / NS;
+  const int k0 = static_cast<int>(blockIdx.x % NS) * KP;  // first kx pencil of this work-group
   const R *plane = grid + z * M * M;
   // pencil b = rows 2b (real part) and 2b + 1 (imaginary part); all loads
   // are issued before the first LDS store
@@ -514,51 +522,58 @@ k_fft_xy_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec,
   C *X = fft_batch_ct<R, M, H, PB, NT, 0, 1>(b0, b1, twl);
   C *Y = (X == b0) ? b1 : b0;
   // Z = FFT(r1 + i r2): R1[k] = (Z[k] + conj Z[M-k]) / 2 (row 2b),
-  // R2[k] = (Z[k] - conj Z[M-k]) / 2i (row 2b + 1); element y of kx pencil k
-  for (int i = threadIdx.x; i < H * K; i += NT) {
-    const int b = i / K, k = i - b * K;
-    const C zk = X[k * PB + b];
-    const C zm = X[(k == 0 ? 0 : M - k) * PB + b];
+  // R2[k] = (Z[k] - conj Z[M-k]) / 2i (row 2b + 1); element y of this
+  // work-group's pencil kx = k0 + kk (zero past the last one)
+  for (int i = threadIdx.x; i < H * KP; i += NT) {
+    const int b = i / KP, kk = i - b * KP, k = k0 + kk;
     C r1, r2;
-    r1.x = R(0.5) * (zk.x + zm.x);
-    r1.y = R(0.5) * (zk.y - zm.y);
-    r2.x = R(0.5) * (zk.y + zm.y);
-    r2.y = R(-0.5) * (zk.x - zm.x);
-    Y[(2 * b) * PB + k] = r1;
-    Y[(2 * b + 1) * PB + k] = r2;
+    if (k < K) {
+      const C zk = X[k * PB + b];
+      const C zm = X[(k == 0 ? 0 : M - k) * PB + b];
+      r1.x = R(0.5) * (zk.x + zm.x);
+      r1.y = R(0.5) * (zk.y - zm.y);
+      r2.x = R(0.5) * (zk.y + zm.y);
+      r2.y = R(-0.5) * (zk.x - zm.x);
+    } else {
+      r1.x = r1.y = r2.x = r2.y = R(0);
+    }
+    Y[(2 * b) * PB + kk] = r1;
+    Y[(2 * b + 1) * PB + kk] = r2;
   }
   __syncthreads();
-  const C *S = fft_batch_ct<R, M, K, PB, NT, 0, 1>(Y, X, twl);
-  C *out = spec + z * K * M;
-  for (int i = threadIdx.x; i < K * M; i += NT) {
-    const int kx = i / M, y = i - kx * M;
-    out[i] = S[y * PB + kx];
+  const C *S = fft_batch_ct<R, M, KP, PB, NT, 0, 1>(Y, X, twl);
+  C *out = spec + (z * K + k0) * M;
+  const int nk = min(KP, K - k0);
+  for (int i = threadIdx.x; i < nk * M; i += NT) {
+    const int kk = i / M, y = i - kk * M;
+    out[i] = S[y * PB + kk];
   }
 }
 
-template <typename R, int M, int NT>
+template <typename R, int M, int NT, int NS>
 __global__ void __launch_bounds__(NT)
 k_fft_yx_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid,
              const cplx_t<R> *__restrict__ tw_g, EnergyOut eo) {
   using C = cplx_t<R>;
-  using G = PlaneGeom<M>;
-  constexpr int H = G::H, K = G::K, PB = G::PB;
+  using G = PlaneGeom<M, NS>;
+  constexpr int K = G::K, PB = G::PB, HP = G::HP;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + G::BUF, *twl = b1 + G::BUF;
   for (int i = threadIdx.x; i < M; i += NT) twl[i] = tw_g[i];
-  const long long z = blockIdx.x;
+  const long long z = blockIdx.x / NS;
+  const int p0 = static_cast<int>(blockIdx.x % NS) * HP;  // first row pair of this work-group
   const C *in = spec + z * K * M;
   // conjugated on the way in: the inverse is conj(FFT(conj(.)))
-  constexpr int NS = K * M, PER = (NS + NT - 1) / NT;
+  constexpr int NSP = K * M, PER = (NSP + NT - 1) / NT;
   C v[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int i = threadIdx.x + k * NT;  // i = kx M + y
-    if (NS % NT == 0 || i < NS) v[k] = in[i];
+    if (NSP % NT == 0 || i < NSP) v[k] = in[i];
   }
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int i = threadIdx.x + k * NT;
-    if (NS % NT == 0 || i < NS) {
+    if (NSP % NT == 0 || i < NSP) {
       const int kx = i / M, y = i - kx * M;
       b0[y * PB + kx] = cconj(v[k]);
     }
@@ -566,30 +581,31 @@ k_fft_yx_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid,
   __syncthreads();
   C *Y = fft_batch_ct<R, M, K, PB, NT, 0, 1>(b0, b1, twl);  // conj of the inverse along y
   C *X = (Y == b0) ? b1 : b0;
-  // rows 2b, 2b + 1 with half spectra R1, R2 (the conjugates of Y's):
-  // Z[k] = R1[k] + i R2[k] on 0..M/2, conj(R1[M-k]) + i conj(R2[M-k]) above,
-  // stored conjugated for the inverse along x
-  for (int i = threadIdx.x; i < H * K; i += NT) {
-    const int b = i / K, k = i - b * K;
+  // row pair b = p0 + bb (rows 2b, 2b + 1) with half spectra R1, R2 (the
+  // conjugates of Y's): Z[k] = R1[k] + i R2[k] on 0..M/2 and
+  // conj(R1[M-k]) + i conj(R2[M-k]) above, stored conjugated for the
+  // inverse along x
+  for (int i = threadIdx.x; i < HP * K; i += NT) {
+    const int bb = i / K, k = i - bb * K, b = p0 + bb;
     const C r1 = cconj(Y[(2 * b) * PB + k]);
     const C r2 = cconj(Y[(2 * b + 1) * PB + k]);
     C zz;
     zz.x = r1.x - r2.y;
     zz.y = -(r1.y + r2.x);
-    X[k * PB + b] = zz;
+    X[k * PB + bb] = zz;
     if (k > 0 && k < M - k) {
       C zc;
       zc.x = r1.x + r2.y;
       zc.y = -(r2.x - r1.y);
-      X[(M - k) * PB + b] = zc;
+      X[(M - k) * PB + bb] = zc;
     }
   }
   __syncthreads();
-  const C *Zr = fft_batch_ct<R, M, H, PB, NT, 0, 1>(X, Y, twl);
+  const C *Zr = fft_batch_ct<R, M, HP, PB, NT, 0, 1>(X, Y, twl);
   R *out = grid + z * M * M;
-  for (int i = threadIdx.x; i < H * M; i += NT) {
-    const int b = i / M, x = i - b * M;
-    const C zz = Zr[x * PB + b];
+  for (int i = threadIdx.x; i < HP * M; i += NT) {
+    const int bb = i / M, x = i - bb * M, b = p0 + bb;
+    const C zz = Zr[x * PB + bb];
     out[(2 * b) * M + x] = zz.x;       // real part of the conjugate
     out[(2 * b + 1) * M + x] = -zz.y;  // imaginary part of the conjugate
   }
@@ -702,15 +718,18 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
   constexpr int LZ = fft_lgb(MC, sizeof(R), kPassZ);
   constexpr int NT = plane_threads(MC);
   constexpr size_t lds = plane_lds_bytes<R, MC>();
+  constexpr unsigned nblk = MC * kPlaneSplit;
   if (MC != p.prm.M || LZ != p.fft_lgb[kPassZ] || p.fft_threads != kThreads)
     return hipErrorInvalidValue;
   hipError_t e;
   if (lds > 65536) {
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_xy_r2c<R, MC, NT>),
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(
+                                     &k_fft_xy_r2c<R, MC, NT, kPlaneSplit>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  static_cast<int>(lds))) != hipSuccess)
       return e;
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_yx_c2r<R, MC, NT>),
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(
+                                     &k_fft_yx_c2r<R, MC, NT, kPlaneSplit>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  static_cast<int>(lds))) != hipSuccess)
       return e;
@@ -719,7 +738,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
   C *spec = static_cast<C *>(p.buf.spec);
   const C *tw = static_cast<const C *>(p.buf.twiddle);
   stage_begin(p, SE_STAGE_FFT_XY);
-  k_fft_xy_r2c<R, MC, NT><<<MC, NT, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec, tw);
+  k_fft_xy_r2c<R, MC, NT, kPlaneSplit><<<nblk, NT, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec, tw);
   stage_end(p, SE_STAGE_FFT_XY);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double tpl = 2.0 * M_PI / p.prm.L;
@@ -732,7 +751,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
       k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_z, p.stream>>>(
           spec, spec2, p.fft, LZ, tw, static_cast<const double *>(p.buf.axis_f),
           static_cast<const double *>(p.buf.axis_k2), p.wscale, nullptr, d, tpl);
-      k_fft_yx_c2r<R, MC, NT><<<MC, NT, lds, p.stream>>>(
+      k_fft_yx_c2r<R, MC, NT, kPlaneSplit><<<nblk, NT, lds, p.stream>>>(
           spec2, static_cast<R *>(p.buf.field) + static_cast<long long>(d) * MC * MC * MC, tw,
           none);
       if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -748,7 +767,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
   const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.part, p.bin_parts, self_coef,
                      E_dev};
   stage_begin(p, SE_STAGE_IFFT_YX);
-  k_fft_yx_c2r<R, MC, NT><<<MC, NT, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), tw, eo);
+  k_fft_yx_c2r<R, MC, NT, kPlaneSplit><<<nblk, NT, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), tw, eo);
   stage_end(p, SE_STAGE_IFFT_YX);
   return hipGetLastError();
 }

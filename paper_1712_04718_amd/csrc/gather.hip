@@ -56,7 +56,9 @@ template <typename R, int WIN, int S, int T> struct GatherLds {
   static constexpr size_t RED = (S & (S - 1)) ? sizeof(R) * kTileThreads * 4 : 0;
   static constexpr size_t FAC = sizeof(R) * CHUNK * REC;
   static constexpr size_t IDX = 2 * sizeof(int) * CHUNK;
-  static constexpr size_t TOTAL = BLK + RED + FAC + IDX;
+  // grid offsets of the block's rows (z, y) and wrapped x coordinates
+  static constexpr size_t TAB = sizeof(int) * (TS * TS + TS);
+  static constexpr size_t TOTAL = BLK + RED + FAC + IDX + TAB;
 };
 
 template <typename R, int WIN, int S, int T>
@@ -80,27 +82,35 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
   R *fac = reinterpret_cast<R *>(h_smem + L::BLK + L::RED);
   int *anc = reinterpret_cast<int *>(h_smem + L::BLK + L::RED + L::FAC);
   int *org = anc + CHUNK;
+  int *rowtab = org + CHUNK, *xtab = rowtab + TS * TS;
 
   // Stage the block: loads are issued in unrolled batches into registers and
   // only then written to LDS, so a thread has a batch of loads in flight
-  // instead of waiting for each one in turn.  The block depends only on the
-  // tile index, so the first batch goes out before the tile's particle range
-  // is known, and the first round of particles is read while it is in
-  // flight: the three reads overlap instead of following one another.
+  // instead of waiting for each one in turn.  An element's grid offset is
+  // the offset of its (z, y) row plus its wrapped x, both from small tables
+  // built first: one division by TS and two table reads per element instead
+  // of three divisions and three wraps.  The tile's particle range is read
+  // while the tables are built, and its first round of particles while the
+  // block loads are in flight.
   const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
   const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
   constexpr int TS3 = TS * TS * TS;
   constexpr int NST = (TS3 + kTileThreads - 1) / kTileThreads;  // elements per thread
   constexpr int BATCH = sizeof(R) == 4 ? 16 : 8;
+  const int start = offsets[tile], end = offsets[tile + 1];
+  for (int r = tid; r < TS * TS; r += kTileThreads) {
+    const int lz = r / TS, ly = r - lz * TS;
+    rowtab[r] = (wrap_near(bz + lz, M) * M + wrap_near(by + ly, M)) * M;
+  }
+  if (tid < TS) xtab[tid] = wrap_near(bx + tid, M);
+  __syncthreads();
   const auto load_batch = [&](int k0, R (&v)[BATCH]) {
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
       const int i = tid + (k0 + k) * kTileThreads;
       if (k0 + k < NST && i < TS3) {
-        const int lz = i / (TS * TS), rem = i - lz * (TS * TS);
-        const int ly = rem / TS, lx = rem - ly * TS;
-        const int gz = wrap_near(bz + lz, M), gy = wrap_near(by + ly, M), gx = wrap_near(bx + lx, M);
-        v[k] = phi_grid[(gz * M + gy) * M + gx];
+        const int r = i / TS, lx = i - r * TS;
+        v[k] = phi_grid[rowtab[r] + xtab[lx]];
       }
     }
   };
@@ -113,7 +123,6 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
   };
   R v0[BATCH];
   load_batch(0, v0);
-  const int start = offsets[tile], end = offsets[tile + 1];
   SortedParticle<R> sp0{};
   int2 mt0 = make_int2(0, 0);
   if (tid < min(CHUNK, end - start)) {
@@ -372,7 +381,7 @@ size_t gather_lds_bytes(int real_size, int window, int S, int T) {
   const size_t chunk = gather_chunk(real_size, static_cast<int>(rec));
   const size_t red = (S & (S - 1)) ? static_cast<size_t>(real_size) * kTileThreads * 4 : 0;
   return real_size * ((ts * ts * ts + 3) & ~static_cast<size_t>(3)) + red +
-         real_size * chunk * rec + 2 * 4 * chunk;
+         real_size * chunk * rec + 2 * 4 * chunk + 4 * (ts * ts + ts);
 }
 
 hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode, void *out_pot,
