@@ -54,7 +54,7 @@ for _st in ("fft_x", "fft_y", "fft_z_scale", "ifft_y", "ifft_x", "fft_xy", "ifft
 # kernel names of each stage in a rocprofv3 trace (FP32 instantiations)
 STAGE_KERNEL_RE = {
     "bin_count": r"k_bin_count_(lds|run)<float", "bin_scan": r"k_bin_scan",
-    "bin_scatter": r"k_bin_scatter<float>",
+    "bin_scatter": r"k_bin_scatter(_scan)?<float>",
     "spread": r"k_spread<float,", "fold": r"k_fold(_tiles)?<float",
     "fft_x": r"k_fft_x_r2c<float,", "fft_y": r"k_fft_y<float, -?\d+, \d+, false>",
     "fft_z_scale": r"k_fft_z_scale<float,", "ifft_y": r"k_fft_y<float, -?\d+, \d+, true>",
@@ -96,8 +96,8 @@ def kernel_work(stage, N, M, P, rs, window):
         return "bytes", N * 4 * rs + N * 8                  # x, q in; keys out
     if stage == "bin_scan":
         return "bytes", ntiles * 12                        # counts in and reset; offsets out
-    if stage == "bin_scatter":
-        return "bytes", N * 4 * rs + N * 8 + N * (4 * rs + 8)  # x, q, keys in; sorted, meta out
+    if stage == "bin_scatter":  # x, q, keys, counts in; sorted, meta, offsets out
+        return "bytes", N * 4 * rs + N * 8 + N * (4 * rs + 8) + ntiles * 8
     if stage == "spread":
         return "flops", N * 2 * P ** 3                      # a multiply and an add per point
     if stage == "gather":

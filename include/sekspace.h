@@ -84,8 +84,10 @@ typedef enum { SE_FP32 = 0, SE_FP64 = 1 } se_dtype;
    apart from the fused plane passes at the end. */
 enum {
     SE_STAGE_BIN_COUNT = 0,  /* tile of each particle, its rank in the tile  */
-    SE_STAGE_BIN_SCAN,       /* tile offsets (exclusive scan of the counts)  */
-    SE_STAGE_BIN_SCATTER,    /* write particles in tile order                */
+    SE_STAGE_BIN_SCAN,       /* tile offsets (exclusive scan of the counts);
+                                a launch of its own only above 8192 tiles   */
+    SE_STAGE_BIN_SCATTER,    /* write particles in tile order (and, up to
+                                8192 tiles, the scan)                        */
     SE_STAGE_SPREAD,         /* step 2 (tile blocks)                          */
     SE_STAGE_FOLD,           /* step 2, tile blocks summed into the grid      */
     SE_STAGE_FFT_X,          /* step 3, real-to-complex along x              */

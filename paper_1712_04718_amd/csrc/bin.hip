@@ -22,7 +22,10 @@
 // k_bin_scan: one work-group turns the tile counts into offsets (exclusive
 //   scan) and resets the counts for the next call;
 // k_bin_scatter: write the particles in tile order as (offsets from the
-//   anchor in grid units, q) plus (packed local anchor, original index).
+//   anchor in grid units, q) plus (packed local anchor, original index);
+// k_bin_scatter_scan: the two in one launch for up to 8192 tiles (each
+//   work-group scans the counts itself); the counts are then reset by the
+//   kernel that consumes the tiles (the k-space spread).
 #include "se_common.hpp"
 
 namespace sek {
@@ -229,6 +232,78 @@ k_bin_scatter(int N, const R *__restrict__ x, const R *__restrict__ q, double h,
   meta[dst] = make_int2((ax % T) | ((ay % T) << 8) | ((az % T) << 16), n);
 }
 
+// k_bin_scatter with the scan folded in: every work-group scans the tile
+// counts into LDS itself (a chunk of counts per thread, shuffles within the
+// waves, one barrier across them), work-group 0 also publishes the offsets,
+// and the counts are left for the consumer of the tiles to reset.  Saves the
+// one-work-group scan launch between counting and scattering.
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+k_bin_scatter_scan(int N, const R *__restrict__ x, const R *__restrict__ q, double h, int M,
+                   int T, const int2 *__restrict__ key, const int *__restrict__ counts,
+                   int ntiles, int *__restrict__ offsets, SortedParticle<R> *__restrict__ sorted,
+                   int2 *__restrict__ meta) {
+  extern __shared__ int soff[];  // ntiles + 1 offsets
+  const int tid = threadIdx.x;
+  const int n = blockIdx.x * blockDim.x + tid;
+  // the particle's inputs are requested before the scan
+  int2 kk = make_int2(0, 0);
+  R px = R(0), py = R(0), pz = R(0), pq = R(0);
+  if (n < N) {
+    kk = key[n];
+    px = x[3 * n + 0];
+    py = x[3 * n + 1];
+    pz = x[3 * n + 2];
+    pq = q[n];
+  }
+  const int chunk = (ntiles + kThreads - 1) / kThreads;
+  const int lo = min(tid * chunk, ntiles), hi = min(lo + chunk, ntiles);
+  constexpr int kPer = 32;  // counts per thread held in registers (ntiles <= 8192)
+  int v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) v[k] = (lo + k < hi) ? counts[(lo + k) * kCountStride] : 0;
+  int local = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) local += v[k];
+  const int lane = tid & 63, wave = tid >> 6;
+  int incl = local;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
+  }
+  __shared__ int wsum[kThreads / 64];
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int run = incl - local;
+  for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (lo + k < hi) {
+      soff[lo + k] = run;
+      if (blockIdx.x == 0) offsets[lo + k] = run;
+      run += v[k];
+    }
+  if (tid == kThreads - 1) {
+    soff[ntiles] = run;
+    if (blockIdx.x == 0) offsets[ntiles] = run;
+  }
+  __syncthreads();
+  if (n >= N) return;
+  const int dst = soff[kk.x] + kk.y;
+  double fx, fy, fz;
+  const int ax = static_cast<int>(floor_div_mod(static_cast<double>(px) / h, M, &fx));
+  const int ay = static_cast<int>(floor_div_mod(static_cast<double>(py) / h, M, &fy));
+  const int az = static_cast<int>(floor_div_mod(static_cast<double>(pz) / h, M, &fz));
+  SortedParticle<R> sp;
+  sp.dx = static_cast<R>(fx);
+  sp.dy = static_cast<R>(fy);
+  sp.dz = static_cast<R>(fz);
+  sp.q = pq;
+  sorted[dst] = sp;
+  meta[dst] = make_int2((ax % T) | ((ay % T) << 8) | ((az % T) << 16), n);
+}
+
 template <typename R>
 hipError_t bin_impl(const BinJob &j, se_plan *timing) {
   const R *xr = static_cast<const R *>(j.x), *qr = static_cast<const R *>(j.q);
@@ -260,6 +335,15 @@ hipError_t bin_impl(const BinJob &j, se_plan *timing) {
   if (j.qsq_parts) *j.qsq_parts = parts;
   if (timing) stage_end(*timing, SE_STAGE_BIN_COUNT);
   if (e != hipSuccess) return e;
+  if (j.fused_scan && j.ncells <= kLdsTilesMax) {
+    // the consumer of the tiles resets the counts
+    if (timing) stage_begin(*timing, SE_STAGE_BIN_SCATTER);
+    k_bin_scatter_scan<R><<<max(blocks1, 1), kThreads, sizeof(int) * (j.ncells + 1), j.stream>>>(
+        N, xr, qr, j.h, j.M, j.T, j.key, j.counts, j.ncells, j.offsets,
+        static_cast<SortedParticle<R> *>(j.sorted), j.meta);
+    if (timing) stage_end(*timing, SE_STAGE_BIN_SCATTER);
+    return hipGetLastError();
+  }
   if (timing) stage_begin(*timing, SE_STAGE_BIN_SCAN);
   k_bin_scan<<<1, kScanThreads, 0, j.stream>>>(j.counts, j.offsets, j.ncells);
   if (timing) stage_end(*timing, SE_STAGE_BIN_SCAN);
@@ -297,6 +381,7 @@ hipError_t launch_bin(se_plan &plan, int N, const void *x, const void *q) {
   j.qsq_part = plan.buf.part;
   j.qsq_parts = &plan.bin_parts;
   j.stream = plan.stream;
+  j.fused_scan = true;  // the spread resets the tile counts
   return launch_bin_job(j, &plan);
 }
 

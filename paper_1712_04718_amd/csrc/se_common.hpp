@@ -202,6 +202,9 @@ struct BinJob {
   double *qsq_part = nullptr;  // per-block q^2 sums (at least ceil(N/256) entries)
   int *qsq_parts = nullptr;    // out: number of partials written
   hipStream_t stream = nullptr;
+  // scan inside the scatter kernel (up to 8192 tiles); the counts are then
+  // left for the consumer of the tiles to reset before the next binning
+  bool fused_scan = false;
 };
 hipError_t launch_bin_job(const BinJob &job, se_plan *timing);
 

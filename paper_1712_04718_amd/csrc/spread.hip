@@ -65,7 +65,8 @@ template <typename R, int S, int T> struct SpreadLds {
 template <typename R, int WIN, int S, int T>
 __global__ void __launch_bounds__(kTileThreads)
 k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ meta,
-         const int *__restrict__ offsets, WindowConsts wc, double wmax, R *__restrict__ ghost) {
+         const int *__restrict__ offsets, int *__restrict__ counts, WindowConsts wc, double wmax,
+         R *__restrict__ ghost) {
   using L = SpreadLds<R, S, T>;
   using A = typename Acc<R>::T;
   constexpr int TS = L::TS, REC = L::REC, TS3 = TS * TS * TS;
@@ -80,6 +81,8 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
   const int tile = xcd_local(blockIdx.x, gridDim.x);
   const int start = offsets[tile], end = offsets[tile + 1];
   const int tid = threadIdx.x;
+  // the binning left this tile's count for its consumer to reset
+  if (tid == 0) counts[tile * kCountStride] = 0;
   R *out = ghost + static_cast<long long>(tile) * TS3;
   if (start == end) {  // uniform across the work-group
     for (int i = tid; i < TS3; i += kTileThreads) out[i] = R(0);
@@ -297,8 +300,8 @@ hipError_t spread_one(se_plan &p) {
   }
   stage_begin(p, SE_STAGE_SPREAD);
   k_spread<R, WIN, S, T><<<p.ntiles, kTileThreads, lds, p.stream>>>(
-      static_cast<const SortedParticle<R> *>(p.buf.sorted), p.buf.meta, p.buf.offsets, wc, wmax,
-      static_cast<R *>(p.buf.ghost));
+      static_cast<const SortedParticle<R> *>(p.buf.sorted), p.buf.meta, p.buf.offsets,
+      p.buf.counts, wc, wmax, static_cast<R *>(p.buf.ghost));
   stage_end(p, SE_STAGE_SPREAD);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -31,7 +31,8 @@ def test_stage_means_cover_every_launch_and_reset(M, fft_stages):
     for _ in range(40):  # more launches than the ring of event pairs holds
         E1, phi1, F1 = tim.kspace(xt, qt)
     times = tim.stage_times()
-    assert set(times) == (set(_lib.STAGES) - FIVE_PASSES - PLANE_PASSES) | fft_stages
+    # up to 8192 tiles the scan runs inside the scatter kernel
+    assert set(times) == (set(_lib.STAGES) - FIVE_PASSES - PLANE_PASSES - {"bin_scan"}) | fft_stages
     assert all(v > 0 for v in times.values()), times
     # nothing launched since the read: every stage reports "not launched"
     assert tim.stage_times() == {}
