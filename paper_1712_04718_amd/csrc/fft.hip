@@ -633,7 +633,14 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
   const int npen = M * K;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
   C *twl = b1 + M * B;  // twiddles staged in LDS
-  for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
+  // the per-axis tables of the influence function too, so that the scaling
+  // step between the two transforms needs no global memory round trip
+  double *af = reinterpret_cast<double *>(twl + M), *ak2 = af + M;
+  for (int i = threadIdx.x; i < M; i += kThreads) {
+    twl[i] = tw_g[i];
+    af[i] = axis_f[i];
+    ak2[i] = axis_k2[i];
+  }
   const int c0 = xcd_local(blockIdx.x, gridDim.x) * B;  // pencils c = kx M + ky, contiguous in a z plane
   const long long zs = static_cast<long long>(M) * K;
   {
@@ -669,10 +676,10 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
     C v = Z[i];
     if (c < npen) {
       const int kx = div_M<MC>(c, pl), ky = c - kx * M;
-      const double k2 = axis_k2[kx] + axis_k2[ky] + axis_k2[kz];
+      const double k2 = ak2[kx] + ak2[ky] + ak2[kz];
       const double w = (kx == 0 && ky == 0 && kz == 0)
                            ? 0.0
-                           : wscale * axis_f[kx] * axis_f[ky] * axis_f[kz] / k2;
+                           : wscale * af[kx] * af[ky] * af[kz] / k2;
       const double mu = (kx == 0 || 2 * kx == M) ? 1.0 : 2.0;
       const double re = static_cast<double>(v.x), im = static_cast<double>(v.y);
       e += 0.5 * mu * w * (re * re + im * im);
@@ -734,7 +741,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
                                  static_cast<int>(lds))) != hipSuccess)
       return e;
   }
-  const size_t lds_z = sizeof(C) * (2 * MC * (1 << LZ) + MC);
+  const size_t lds_z = sizeof(C) * (2 * MC * (1 << LZ) + MC) + 2 * sizeof(double) * MC;
   C *spec = static_cast<C *>(p.buf.spec);
   const C *tw = static_cast<const C *>(p.buf.twiddle);
   stage_begin(p, SE_STAGE_FFT_XY);
@@ -788,6 +795,7 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
     return hipErrorInvalidValue;
   const int Bx = 1 << lx, By = 1 << ly;
   const auto lds_of = [M](int lg) { return sizeof(C) * (2 * M * (1 << lg) + M); };
+  const auto lds_zof = [M, lds_of](int lg) { return lds_of(lg) + 2 * sizeof(double) * M; };
   C *spec = static_cast<C *>(p.buf.spec);
   const C *tw = static_cast<const C *>(p.buf.twiddle);
   const int xblocks = (M * M + 2 * Bx - 1) / (2 * Bx);
@@ -809,7 +817,7 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
     // which the potential's z pass then overwrites); not timed
     C *spec2 = static_cast<C *>(p.buf.spec2);
     for (int d = 0; d < 3; ++d) {
-      k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_of(lz), p.stream>>>(
+      k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_zof(lz), p.stream>>>(
           spec, spec2, p.fft, lz, tw, static_cast<const double *>(p.buf.axis_f),
           static_cast<const double *>(p.buf.axis_k2), p.wscale, nullptr, d, tpl);
       k_fft_y<R, MC, LY, true><<<yg, p.fft_threads, lds_of(ly), p.stream>>>(spec2, p.fft, ly, tw,
@@ -821,7 +829,7 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
     }
   }
   stage_begin(p, SE_STAGE_FFT_Z_SCALE);
-  k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_of(lz), p.stream>>>(
+  k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_zof(lz), p.stream>>>(
       spec, spec, p.fft, lz, tw, static_cast<const double *>(p.buf.axis_f),
       static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks, -1, tpl);
   stage_end(p, SE_STAGE_FFT_Z_SCALE);

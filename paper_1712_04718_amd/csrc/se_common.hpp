@@ -263,11 +263,15 @@ constexpr int kFftBatchCap[3] = {8, 4, 8};
 
 // Pencils per FFT work-group of one pass, as log2: B a power of two, at most
 // kFftBatchCap[pass], with M * B <= 16 * kThreads (elements per thread when
-// loading) and two LDS buffers of M x B complex plus the M twiddles within
-// 64 KB.
+// loading) and two LDS buffers of M x B complex plus the M twiddles (and,
+// in the z pass, the two FP64 axis tables of the influence function)
+// within 64 KB.
 constexpr int fft_lgb(int M, int real_size, int pass) {
+  const int tables = pass == kPassZ ? 2 * 8 * M : 0;
   int B = kFftBatchCap[pass];
-  while (B > 1 && (M * B > 16 * kThreads || (2 * M * B + M) * 2 * real_size > 65536)) B >>= 1;
+  while (B > 1 &&
+         (M * B > 16 * kThreads || (2 * M * B + M) * 2 * real_size + tables > 65536))
+    B >>= 1;
   int lg = 0;
   while ((1 << lg) < B) ++lg;
   return lg;
