@@ -23,9 +23,9 @@
 //   scan) and resets the counts for the next call;
 // k_bin_scatter: write the particles in tile order as (offsets from the
 //   anchor in grid units, q) plus (packed local anchor, original index);
-// k_bin_scatter_scan: the two in one launch for up to 8192 tiles (each
-//   work-group scans the counts itself); the counts are then reset by the
-//   kernel that consumes the tiles (the k-space spread).
+// k_bin_scatter_scan: the two in one launch when tiles x work-groups is at
+//   most 2^20 (each work-group scans the counts itself); the counts are
+//   then reset by the kernel that consumes the tiles (the k-space spread).
 #include "se_common.hpp"
 
 namespace sek {
@@ -335,7 +335,10 @@ hipError_t bin_impl(const BinJob &j, se_plan *timing) {
   if (j.qsq_parts) *j.qsq_parts = parts;
   if (timing) stage_end(*timing, SE_STAGE_BIN_COUNT);
   if (e != hipSuccess) return e;
-  if (j.fused_scan && j.ncells <= kLdsTilesMax) {
+  // every scatter work-group reads all the (line-spaced) counts: worth it
+  // while that stays small against the separate scan's launch
+  const long long scan_reads = static_cast<long long>(j.ncells) * max(blocks1, 1);
+  if (j.fused_scan && j.ncells <= kLdsTilesMax && scan_reads <= (1LL << 20)) {
     // the consumer of the tiles resets the counts
     if (timing) stage_begin(*timing, SE_STAGE_BIN_SCATTER);
     k_bin_scatter_scan<R><<<max(blocks1, 1), kThreads, sizeof(int) * (j.ncells + 1), j.stream>>>(

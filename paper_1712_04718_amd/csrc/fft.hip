@@ -456,10 +456,10 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
 //     pencils, store C[z][kx][y];
 //   k_fft_yx_c2r: the mirror image (conjugated input, inverse along y,
 //     Hermitian rebuild, inverse along x, real rows out).
-// NS work-groups share a plane so that more CUs take part: each repeats the
-// first transform of the plane (along x forward, along y inverse) and does
-// the second for its 1/NS of the pencils (kx pencils forward, row pairs
-// inverse).
+// NS work-groups may share a plane so that more CUs take part: each repeats
+// the first transform of the plane (along x forward, along y inverse) and
+// does the second for its 1/NS of the pencils (kx pencils forward, row
+// pairs inverse).
 // Rows in LDS hold PB = (M/2 + 1) | 1 complex values: with an odd row
 // length the column walks of the load, split and store phases keep 64-bit
 // LDS accesses conflict-free within each half wave.
@@ -468,7 +468,9 @@ template <int M, int NS> struct PlaneGeom {
   static constexpr int KP = (K + NS - 1) / NS;  // kx pencils per work-group (forward)
   static constexpr int HP = H / NS;             // row pairs per work-group (inverse)
 };
-constexpr int kPlaneSplit = 2;
+// work-groups per plane (two beat one in both directions at M = 96, FP32
+// and FP64, despite reading each plane twice)
+constexpr int kPlaneSplitFwd = 2, kPlaneSplitInv = 2;
 template <typename R, int M> constexpr size_t plane_lds_bytes() {
   return sizeof(cplx_t<R>) * (2 * PlaneGeom<M, 1>::BUF + M);
 }
@@ -479,7 +481,7 @@ constexpr int plane_threads(int M) {
   return nt;
 }
 template <typename R, int M> constexpr bool plane_fits() {
-  return plane_lds_bytes<R, M>() <= kMaxLds && M % 4 == 0 && (M / 2) % kPlaneSplit == 0;
+  return plane_lds_bytes<R, M>() <= kMaxLds && M % 4 == 0 && (M / 2) % kPlaneSplitInv == 0;
 }
 
 template <typename R, int M, int NT, int NS>
@@ -725,18 +727,18 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
   constexpr int LZ = fft_lgb(MC, sizeof(R), kPassZ);
   constexpr int NT = plane_threads(MC);
   constexpr size_t lds = plane_lds_bytes<R, MC>();
-  constexpr unsigned nblk = MC * kPlaneSplit;
+  constexpr unsigned nfwd = MC * kPlaneSplitFwd, ninv = MC * kPlaneSplitInv;
   if (MC != p.prm.M || LZ != p.fft_lgb[kPassZ] || p.fft_threads != kThreads)
     return hipErrorInvalidValue;
   hipError_t e;
   if (lds > 65536) {
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(
-                                     &k_fft_xy_r2c<R, MC, NT, kPlaneSplit>),
+                                     &k_fft_xy_r2c<R, MC, NT, kPlaneSplitFwd>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  static_cast<int>(lds))) != hipSuccess)
       return e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(
-                                     &k_fft_yx_c2r<R, MC, NT, kPlaneSplit>),
+                                     &k_fft_yx_c2r<R, MC, NT, kPlaneSplitInv>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  static_cast<int>(lds))) != hipSuccess)
       return e;
@@ -745,7 +747,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
   C *spec = static_cast<C *>(p.buf.spec);
   const C *tw = static_cast<const C *>(p.buf.twiddle);
   stage_begin(p, SE_STAGE_FFT_XY);
-  k_fft_xy_r2c<R, MC, NT, kPlaneSplit><<<nblk, NT, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec, tw);
+  k_fft_xy_r2c<R, MC, NT, kPlaneSplitFwd><<<nfwd, NT, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec, tw);
   stage_end(p, SE_STAGE_FFT_XY);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double tpl = 2.0 * M_PI / p.prm.L;
@@ -758,7 +760,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
       k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_z, p.stream>>>(
           spec, spec2, p.fft, LZ, tw, static_cast<const double *>(p.buf.axis_f),
           static_cast<const double *>(p.buf.axis_k2), p.wscale, nullptr, d, tpl);
-      k_fft_yx_c2r<R, MC, NT, kPlaneSplit><<<nblk, NT, lds, p.stream>>>(
+      k_fft_yx_c2r<R, MC, NT, kPlaneSplitInv><<<ninv, NT, lds, p.stream>>>(
           spec2, static_cast<R *>(p.buf.field) + static_cast<long long>(d) * MC * MC * MC, tw,
           none);
       if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -774,7 +776,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
   const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.part, p.bin_parts, self_coef,
                      E_dev};
   stage_begin(p, SE_STAGE_IFFT_YX);
-  k_fft_yx_c2r<R, MC, NT, kPlaneSplit><<<nblk, NT, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), tw, eo);
+  k_fft_yx_c2r<R, MC, NT, kPlaneSplitInv><<<ninv, NT, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), tw, eo);
   stage_end(p, SE_STAGE_IFFT_YX);
   return hipGetLastError();
 }
