@@ -423,7 +423,26 @@ def run(args):
         e1.record()
         torch.cuda.synchronize()
         ms_rs = e0.elapsed_time(e1) / reps
+        # the total Ewald sum (k space with self terms + real space), the two
+        # parts in sequence on one stream and overlapped on two streams
+        from paper_1712_04718_amd import SEPlan, ewald_total
+        kplan = SEPlan(M, P, L, xi, window=window, dtype=torch.float32, n_max=N, device=dev,
+                       add_self=True)
+        total_ms = {}
+        for mode in (False, True):
+            for _ in range(3):
+                ewald_total(xt, qt, kplan, rplan, overlap=mode)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                ewald_total(xt, qt, kplan, rplan, overlap=mode)
+            e1.record()
+            torch.cuda.synchronize()
+            total_ms["overlapped" if mode else "sequential"] = e0.elapsed_time(e1) / reps
+        kplan.close()
         rplan.close()
+        log(f"total Ewald sum: sequential {total_ms['sequential'] * 1e3:.1f} us, "
+            f"overlapped {total_ms['overlapped'] * 1e3:.1f} us")
         nc = min(int(L // REAL_SPACE_RC), 64)
         tested = N * 27.0 * (L / nc) ** 3 * N / L ** 3
         in_range = N * 4.0 / 3.0 * math.pi * REAL_SPACE_RC ** 3 * N / L ** 3
@@ -435,7 +454,10 @@ def run(args):
                       "alu": {"achieved": flops / (ms_rs * 1e-3) / 1e12,
                               "peak": VALU_PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
                               "frac": flops / (ms_rs * 1e-3) / 1e12 / VALU_PEAK_TFLOPS["f32"]},
-                      "step": "se_rs_eval: cell-list binning + pair kernel + energy reduction"}
+                      "step": "se_rs_eval: cell-list binning + pair kernel + energy reduction",
+                      "total_ms": {k: round(v, 4) for k, v in total_ms.items()},
+                      "total_step": "ewald_total: k space (same M, P, self terms) + real space, "
+                                    "in sequence on one stream or overlapped on two"}
         log(f"real space rc={REAL_SPACE_RC}: {ms_rs * 1e3:.1f} us/eval")
 
     # CPU baseline: the oracle as it stands, FP64, repeated full evaluations
@@ -462,6 +484,29 @@ def run(args):
                          f"({(reps + 1) * dt:.1f} s; spread and FFT on one thread, gather "
                          f"on {cores} OpenMP threads)"}
         log(f"oracle: {dt:.3f} s per evaluation")
+        # the same oracle on one thread (the OpenMP runtime it links), for
+        # comparison with per-core CPU figures; a bounded sample of ~3 s
+        try:
+            gomp = ctypes.CDLL("libgomp.so.1")
+            gomp.omp_get_max_threads.restype = ctypes.c_int
+            nthr = gomp.omp_get_max_threads()
+            gomp.omp_set_num_threads(1)
+            try:
+                t0 = time.perf_counter()
+                evaluate(x, q)
+                n1 = 1
+                while time.perf_counter() - t0 < 3.0 and n1 < 50:
+                    evaluate(x, q)
+                    n1 += 1
+                dt1 = (time.perf_counter() - t0) / n1
+            finally:
+                gomp.omp_set_num_threads(nthr)
+            cpu["single_thread"] = {"value": N / dt1, "unit": "atom-evals/s", "cores": 1,
+                                    "sample": f"{n1} full FP64 evaluations on one thread "
+                                              f"({n1 * dt1:.1f} s)"}
+            log(f"oracle, one thread: {dt1:.3f} s per evaluation")
+        except OSError:
+            pass
 
     f32 = out["f32"]
     ms = f32["ms_eager"]

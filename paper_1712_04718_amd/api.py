@@ -225,11 +225,44 @@ class RealSpacePlan:
             pass
 
 
-def ewald_total(x, q, kplan: SEPlan, rplan: RealSpacePlan):
+_SIDE_STREAMS = {}
+
+
+def _side_stream(device):
+    """A second stream (default priority) on ``device`` for work that may
+    overlap the caller's current stream."""
+    s = _SIDE_STREAMS.get(device)
+    if s is None:
+        s = _SIDE_STREAMS[device] = torch.cuda.Stream(device=device)
+    return s
+
+
+def ewald_total(x, q, kplan: SEPlan, rplan: RealSpacePlan, overlap=True):
     """(E, phi, F) of the total Ewald sum: real space + k space + self terms
-    (the k-space plan must have been created with ``add_self=True``)."""
+    (the k-space plan must have been created with ``add_self=True``).
+
+    With ``overlap`` the real-space sum runs on a second stream of the device
+    while the k-space evaluation runs on the caller's stream (the two only
+    read x and q and have separate workspaces): the k-space kernels leave
+    CUs idle that the pair kernel can use.  The caller's stream waits for
+    both before the sums, so the result is ordered on it as usual."""
+    if not overlap or kplan.device != rplan.device:
+        Ek, phik, Fk = kplan.kspace(x, q)
+        Er, phir, Fr = rplan.eval(x, q)
+        return Ek + Er, phik + phir, Fk + Fr
+    dev = kplan.device
+    main = torch.cuda.current_stream(dev)
+    side = _side_stream(dev)
+    side.wait_stream(main)  # x and q are ready on the side stream
+    with torch.cuda.stream(side):
+        Er, phir, Fr = rplan.eval(x, q)
     Ek, phik, Fk = kplan.kspace(x, q)
-    Er, phir, Fr = rplan.eval(x, q)
+    main.wait_stream(side)
+    # memory used across the two streams is not reused before both are done
+    x.record_stream(side)
+    q.record_stream(side)
+    for t in (Er, phir, Fr):
+        t.record_stream(main)
     return Ek + Er, phik + phir, Fk + Fr
 
 
