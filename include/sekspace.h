@@ -57,7 +57,10 @@ typedef enum {
     SE_ERR_ETA = 3,          /* Gaussian shape eta outside (0,1) (section 4) */
     SE_ERR_UNSUPPORTED = 4,  /* window/precision/P combination not built */
     SE_ERR_WORKSPACE = 5,    /* device allocation failed */
-    SE_ERR_HIP = 6,          /* HIP runtime error while enqueueing */
+    SE_ERR_HIP = 6,          /* HIP runtime error while enqueueing; the
+                                plan's workspace is then in an undefined
+                                state (a launch may be missing from the
+                                sequence): destroy the plan               */
     SE_ERR_STATE = 7         /* se_gather/se_backward before any se_forward */
 } se_status;
 
