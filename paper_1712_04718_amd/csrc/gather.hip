@@ -90,8 +90,8 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
   // the offset of its (z, y) row plus its wrapped x, both from small tables
   // built first: one division by TS and two table reads per element instead
   // of three divisions and three wraps.  The tile's particle range is read
-  // while the tables are built, and its first round of particles while the
-  // block loads are in flight.
+  // while the tables are built; its first round of particles is read, and
+  // their window factors computed, while the block loads are in flight.
   const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
   const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
   constexpr int TS3 = TS * TS * TS;
@@ -121,15 +121,39 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
       if (k0 + k < NST && i < TS3) blk[i] = v[k];
     }
   };
+  // phase A: the window factors of one particle (its own thread) into LDS
+  const auto phase_a = [&](const SortedParticle<R> &sp, const int2 &mt) {
+    R *f = fac + tid * REC;
+    R g[S], dg[S];
+    const R dd[3] = {sp.dx, sp.dy, sp.dz};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      window_axis<R, WIN, S, WIN == kBspline>(dd[ax], wc, g, dg);
+#pragma unroll
+      for (int j = 0; j < S; ++j) f[ax * S + j] = g[j];
+      if constexpr (WIN == kBspline) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) f[3 * S + ax * S + j] = dg[j];
+      } else {
+        f[3 * S + ax] = dd[ax];
+      }
+    }
+    f[REC - 1] = sp.q;
+    anc[tid] = mt.x;
+    org[tid] = mt.y;
+  };
   R v0[BATCH];
   load_batch(0, v0);
   SortedParticle<R> sp0{};
   int2 mt0 = make_int2(0, 0);
-  if (tid < min(CHUNK, end - start)) {
+  const int nval0 = min(CHUNK, end - start);
+  if (tid < nval0) {
     sp0 = sorted[start + tid];
     mt0 = meta[start + tid];
   }
   if (start == end) return;  // uniform across the work-group
+  // the first round's factors are computed while the block loads are in flight
+  if (tid < nval0) phase_a(sp0, mt0);
   store_batch(0, v0);
 #pragma unroll
   for (int k0 = BATCH; k0 < NST; k0 += BATCH) {
@@ -143,29 +167,9 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
   R *wred = red + wave * 64 * 4;
   for (int base = start; base < end; base += CHUNK) {
     const int nval = min(CHUNK, end - base);
-    __syncthreads();  // grid block staged; previous round done with the factors
-    // phase A: factors of particle base + tid
-    if (tid < nval) {
-      const SortedParticle<R> sp = base == start ? sp0 : sorted[base + tid];
-      const int2 mt = base == start ? mt0 : meta[base + tid];
-      R *f = fac + tid * REC;
-      R g[S], dg[S];
-      const R dd[3] = {sp.dx, sp.dy, sp.dz};
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        window_axis<R, WIN, S, WIN == kBspline>(dd[ax], wc, g, dg);
-#pragma unroll
-        for (int j = 0; j < S; ++j) f[ax * S + j] = g[j];
-        if constexpr (WIN == kBspline) {
-#pragma unroll
-          for (int j = 0; j < S; ++j) f[3 * S + ax * S + j] = dg[j];
-        } else {
-          f[3 * S + ax] = dd[ax];
-        }
-      }
-      f[REC - 1] = sp.q;
-      anc[tid] = mt.x;
-      org[tid] = mt.y;
+    if (base != start) {
+      __syncthreads();  // previous round done with the factors
+      if (tid < nval) phase_a(sorted[base + tid], meta[base + tid]);
     }
     __syncthreads();
     // phase B: particle groups of S lanes across the work-group

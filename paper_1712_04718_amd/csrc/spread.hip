@@ -10,16 +10,17 @@
 // LDS accumulation in fixed point, with a per-tile scale
 // 2^B / (wmax * sum_tile |q|), where wmax bounds every window value (beta^3
 // for the Gaussian, 1 for B-splines): B = 30 in 32-bit integers (FP32) and
-// B = 62 in 64-bit integers (FP64).  No partial sum can leave (-2^(B+1),
-// 2^(B+1)), each contribution is rounded once, and the result does not depend
-// on the order of the additions, so both precisions are bitwise
-// reproducible.  (Integer LDS atomics run far faster than floating-point ones
+// B = 62 in 64-bit integers (FP64).
+// No partial sum can leave (-2^(B+1), 2^(B+1)), each contribution is rounded
+// once, and the result does not depend on the order of the additions, so
+// both precisions are bitwise reproducible.  (Integer LDS atomics run far faster than floating-point ones
 // on this chip.)  An FP32 contribution has 24 significant bits while the
 // fixed point spans 30, so exact halves are common: they round to even,
 // which keeps the sum unbiased (rounding halves up would not).
 // Work split: the tile's particles are taken in chunks of one per thread;
-//   phase A: each thread computes its particle's 3S window factors (charge
-//            and scale folded into the x factors) into LDS;
+//   phase A: each thread computes its particle's 3S window factors and
+//            stores them with its charge in LDS (the first chunk while the
+//            tile's max |q| is being reduced);
 //   phase B: each wave holds 64/S particle groups of S lanes; lane
 //            (group, jx) owns the x-offset jx of one particle and adds its
 //            S^2 (jy, jz) products.
@@ -47,7 +48,7 @@ constexpr size_t spread_lds_total(int real_size, int S, int T) {
   const size_t TS = T + S - 1, acc = real_size == 4 ? 4 : 8;
   const size_t chunk = spread_chunk(real_size, S);
   return acc * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) + real_size * chunk * 3 * S +
-         4 * chunk + 128;
+         4 * chunk + real_size * chunk + 128;
 }
 
 template <typename R, int S, int T> struct SpreadLds {
@@ -58,7 +59,8 @@ template <typename R, int S, int T> struct SpreadLds {
   static constexpr size_t BLK = sizeof(A) * ((TS * TS * TS + 3) & ~3);
   static constexpr size_t FAC = sizeof(R) * CHUNK * REC;
   static constexpr size_t ANC = sizeof(int) * CHUNK;
-  static constexpr size_t TOTAL = BLK + FAC + ANC + 128;
+  static constexpr size_t QV = sizeof(R) * CHUNK;
+  static constexpr size_t TOTAL = BLK + FAC + ANC + QV + 128;
   static_assert(TOTAL == spread_lds_total(sizeof(R), S, T), "LDS size mismatch");
 };
 
@@ -75,7 +77,7 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
   constexpr int NWAVES = kTileThreads / 64;
   // fixed-point bits of the accumulator
   constexpr double kFix = sizeof(R) == 4 ? 1073741824.0 : 4611686018427387904.0;  // 2^30, 2^62
-  static_assert(NWAVES * 8 <= 128, "per-wave partials must fit the reduction area");
+  static_assert(NWAVES * 16 <= 128, "per-wave partials must fit the reduction area");
   static_assert(kChunk <= kTileThreads, "phase A holds one particle per thread");
 
   const int tile = xcd_local(blockIdx.x, gridDim.x);
@@ -92,85 +94,85 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
   A *blk = reinterpret_cast<A *>(g_smem);
   R *fac = reinterpret_cast<R *>(g_smem + L::BLK);
   int *anc = reinterpret_cast<int *>(g_smem + L::BLK + L::FAC);
-  double *red = reinterpret_cast<double *>(g_smem + L::BLK + L::FAC + L::ANC);
+  R *qv = reinterpret_cast<R *>(g_smem + L::BLK + L::FAC + L::ANC);
+  double *red = reinterpret_cast<double *>(g_smem + L::BLK + L::FAC + L::ANC + L::QV);
 
-  // The tile's first kTileThreads particles are read once, into registers;
-  // they serve the charge bound and the first round of phase A.
+  // The tile's first kChunk particles are read once, into registers; they
+  // serve the charge bound and the first round of phase A.
   const int n = end - start;
   SortedParticle<R> mine{};
   int mine_anchor = 0;
-  if (tid < n) {
+  if (tid < min(n, kChunk)) {
     mine = sorted[start + tid];
     mine_anchor = meta[start + tid].x;
   }
   for (int i = tid; i < TS3; i += kTileThreads) blk[i] = A(0);
 
-  // Fixed-point scale of this tile, from a bound on sum |q| that does not
+  // phase A: a particle's 3S window factors and its charge into LDS (the
+  // fixed-point scale is applied in phase B, so this needs no bound)
+  const auto phase_a = [&](const SortedParticle<R> &sp, int a) {
+    R g[S], unused[S];
+    R *f = fac + tid * REC;
+    window_axis<R, WIN, S, false>(sp.dx, wc, g, unused);
+#pragma unroll
+    for (int j = 0; j < S; ++j) f[j] = g[j];
+    window_axis<R, WIN, S, false>(sp.dy, wc, g, unused);
+#pragma unroll
+    for (int j = 0; j < S; ++j) f[S + j] = g[j];
+    window_axis<R, WIN, S, false>(sp.dz, wc, g, unused);
+#pragma unroll
+    for (int j = 0; j < S; ++j) f[2 * S + j] = g[j];
+    qv[tid] = sp.q;
+    anc[tid] = a;
+  };
+
+  // Fixed-point scale of this tile from a bound on sum |q| that does not
   // depend on the order of the particles (the order inside a tile comes from
   // atomics): qmax = max |q| is exact, each particle contributes the integer
   // u = ceil(|q| / qmax * 2^20) >= |q| / qmax * 2^20, and integer sums are
-  // exact, so qmax * sum(u) / 2^20 >= sum |q| is the same on every run.
-  double scale = 1.0, inv_scale = 1.0;
-  {
-    double m = tid < n ? fabs(static_cast<double>(mine.q)) : 0.0;
+  // exact, so qmax * sum(u) / 2^20 >= sum |q| is the same on every run.  The
+  // first round's factors are computed while the maximum is reduced; the
+  // two reductions use separate LDS slots, one barrier each.
+  R qa = R(0);  // |q| of particle start + tid
+  if (tid < n) qa = fabs(tid < kChunk ? mine.q : sorted[start + tid].q);
+  double m = static_cast<double>(qa);
+  for (int p = start + kTileThreads + tid; p < end; p += kTileThreads)
+    m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  double *red_max = red;
+  long long *red_u = reinterpret_cast<long long *>(red + NWAVES);
+  if ((tid & 63) == 0) red_max[tid >> 6] = m;
+  if (tid < min(n, kChunk)) phase_a(mine, mine_anchor);
+  __syncthreads();  // maximum, first factors and zeroed block visible
+  double qmax = 0.0;
+  for (int w = 0; w < NWAVES; ++w) qmax = fmax(qmax, red_max[w]);
+  long long u = 0;
+  if (qmax > 0.0) {
+    if (tid < n) u = static_cast<long long>(ceil(static_cast<double>(qa) / qmax * 1048576.0));
     for (int p = start + kTileThreads + tid; p < end; p += kTileThreads)
-      m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    if ((tid & 63) == 0) red[tid >> 6] = m;
-    __syncthreads();
-    double qmax = 0.0;
-    for (int w = 0; w < NWAVES; ++w) qmax = fmax(qmax, red[w]);
-    long long u = 0;
-    if (qmax > 0.0) {
-      if (tid < n) u = static_cast<long long>(ceil(fabs(static_cast<double>(mine.q)) / qmax * 1048576.0));
-      for (int p = start + kTileThreads + tid; p < end; p += kTileThreads)
-        u += static_cast<long long>(ceil(fabs(static_cast<double>(sorted[p].q)) / qmax * 1048576.0));
-    }
-    for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
-    __syncthreads();  // every wave has read red[]
-    long long *ured = reinterpret_cast<long long *>(red);
-    if ((tid & 63) == 0) ured[tid >> 6] = u;
-    __syncthreads();
-    long long usum = 0;
-    for (int w = 0; w < NWAVES; ++w) usum += ured[w];
-    const double bound = wmax * qmax * (static_cast<double>(usum) / 1048576.0);
-    if (bound > 0.0) {
-      scale = kFix / bound;
-      inv_scale = bound / kFix;
-    }
+      u += static_cast<long long>(ceil(fabs(static_cast<double>(sorted[p].q)) / qmax * 1048576.0));
+  }
+  for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
+  if ((tid & 63) == 0) red_u[tid >> 6] = u;
+  __syncthreads();
+  long long usum = 0;
+  for (int w = 0; w < NWAVES; ++w) usum += red_u[w];
+  const double bound = wmax * qmax * (static_cast<double>(usum) / 1048576.0);
+  double scale = 1.0, inv_scale = 1.0;
+  if (bound > 0.0) {
+    scale = kFix / bound;
+    inv_scale = bound / kFix;
   }
 
   const int wave = tid >> 6, lane = tid & 63;
   const int grp = lane / S, jx = lane - grp * S;
   for (int base = start; base < end; base += kChunk) {
     const int nval = min(kChunk, end - base);
-    __syncthreads();  // previous round done with fac / anc; blk zeroed
-    // phase A: factors of particle base + tid (charge and scale in the x factors)
-    if (tid < nval) {
-      SortedParticle<R> sp;
-      int a;
-      if (base == start) {
-        sp = mine;
-        a = mine_anchor;
-      } else {
-        sp = sorted[base + tid];
-        a = meta[base + tid].x;
-      }
-      R g[S], unused[S];
-      R *f = fac + tid * REC;
-      const R qs = static_cast<R>(static_cast<double>(sp.q) * scale);
-      window_axis<R, WIN, S, false>(sp.dx, wc, g, unused);
-#pragma unroll
-      for (int j = 0; j < S; ++j) f[j] = qs * g[j];
-      window_axis<R, WIN, S, false>(sp.dy, wc, g, unused);
-#pragma unroll
-      for (int j = 0; j < S; ++j) f[S + j] = g[j];
-      window_axis<R, WIN, S, false>(sp.dz, wc, g, unused);
-#pragma unroll
-      for (int j = 0; j < S; ++j) f[2 * S + j] = g[j];
-      anc[tid] = a;
+    if (base != start) {
+      __syncthreads();  // previous round done with fac / qv / anc
+      if (tid < nval) phase_a(sorted[base + tid], meta[base + tid].x);
+      __syncthreads();
     }
-    __syncthreads();
     // phase B: lane (group, jx) of 64/S particle groups adds its S^2 products
     if (grp < GROUPS) {
       for (int c = wave * GROUPS + grp; c < nval; c += NWAVES * GROUPS) {
@@ -178,7 +180,8 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
         const int packed = anc[c];
         const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
         A *row = blk + (az * TS + ay) * TS + ax + jx;
-        const R wq = f[jx];
+        // the charge in fixed-point units times this lane's x factor
+        const R wq = static_cast<R>(static_cast<double>(qv[c]) * scale) * f[jx];
         R gy[S], gz[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) {
