@@ -28,6 +28,7 @@ struct se_rs_plan {
   int n_max;
   hipStream_t stream;
   int nc;        // cells per side
+  int cus;       // compute units of the plan's device
   int ncells;
   double cs;     // cell edge
   int bin_blocks;
@@ -43,15 +44,21 @@ namespace sek {
 namespace {
 
 constexpr int kRsThreads = 256;
-constexpr int kQueue = 32;   // pair queue entries per thread
+// Pair queue entries per thread.  FP32 keeps the work-group's LDS at about
+// 37 KB (16 KB of queue), so four work-groups share a CU; a 32-entry queue
+// (53 KB, three per CU) made water_L100 459 us instead of 352.  FP64 keeps 32
+// (a shorter queue flushed more often and was slower there).
+template <typename R> constexpr int kQueue = sizeof(R) == 4 ? 16 : 32;
 constexpr int kBatch = 8;    // LDS reads issued together in the test and evaluation loops
 
 template <typename R> struct alignas(4 * sizeof(R)) Staged {
   R x, y, z, q;  // position relative to the home cell's corner (length units), charge
 };
 
-// Staged neighbours per pass (16 KB of LDS in FP32, 32 KB in FP64).
-template <typename R> constexpr int kStageCap = 1024;
+// Staged neighbours per pass (CAP): 1024 (16 KB of LDS in FP32, 32 KB in
+// FP64); FP32 takes 512 when the cells outnumber four work-groups per CU, so
+// that five share a CU (10^6 ions: 2.61 instead of 2.83 ms), and keeps 1024,
+// fewer staging passes, when every cell already runs at once.
 
 // FP32 erfc(x) for x >= 0 from e2 = e^{-x^2}: e2 t sum a_i t^i, t = 1/(1 + p x)
 // (the form of Abramowitz-Stegun 7.1.26 with eight terms fitted for relative
@@ -96,21 +103,21 @@ __device__ inline void pair_term(double rx, double ry, double rz, double r2, dou
 }
 
 // One work-group per cell.  The particles of the 27 neighbour cells (home
-// cell included) are staged in LDS, in passes of kStageCap.  Home particles
+// cell included) are staged in LDS, in passes of CAP.  Home particles
 // take nhp = min(nh, 256) lanes, and the other lanes take the same home
 // particles again: G = 256 / nhp slices of the staged range per home particle,
 // summed at the end.  Each thread first tests its candidates (distance only)
 // and queues the indices of the pairs in range in LDS; the wave evaluates the
 // queued pairs together once some lane's queue could overflow, so the erfc and
 // exp run on full waves instead of on every tested pair under a mask.
-template <typename R>
+template <typename R, int CAP>
 __global__ void __launch_bounds__(kRsThreads)
 k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ meta,
            const int *__restrict__ offsets, int nc, R cs, R xi, R rc2, R *__restrict__ phi,
            R *__restrict__ F, double *__restrict__ epart) {
-  constexpr int CAP = kStageCap<R>;
+  constexpr int QN = kQueue<R>;
   __shared__ Staged<R> stage[CAP];
-  __shared__ int queue[kQueue * kRsThreads];  // entry m of thread t at m * 256 + t
+  __shared__ int queue[QN * kRsThreads];  // entry m of thread t at m * 256 + t
   __shared__ int nb_src[27], nb_pre[28];
   __shared__ R red[4][kRsThreads];
   __shared__ double ered[kRsThreads / 64];
@@ -216,7 +223,7 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
           queue[qn * kRsThreads + tid] = idx;
           qn += hit ? 1 : 0;
         }
-        if (__any(qn > kQueue - kBatch)) flush();
+        if (__any(qn > QN - kBatch)) flush();
       }
       flush();
     }
@@ -293,10 +300,20 @@ hipError_t rs_eval(se_rs_plan &p, int N, const void *x, const void *q, double *E
   hipError_t e = launch_bin_job(j, nullptr);
   if (e != hipSuccess) return e;
   double *epart = p.part + p.bin_blocks;
-  k_rs_pairs<R><<<p.ncells, kRsThreads, 0, p.stream>>>(
-      static_cast<const SortedParticle<R> *>(p.sorted), p.meta, p.offsets, p.nc,
-      static_cast<R>(p.cs), static_cast<R>(p.xi), static_cast<R>(p.rc * p.rc),
-      static_cast<R *>(phi), static_cast<R *>(F), epart);
+  const auto sorted = static_cast<const SortedParticle<R> *>(p.sorted);
+  const R cs = static_cast<R>(p.cs), xi = static_cast<R>(p.xi), rc2 = static_cast<R>(p.rc * p.rc);
+  bool small_stage = false;
+  if constexpr (sizeof(R) == 4) small_stage = p.ncells > 4 * p.cus;
+  if constexpr (sizeof(R) == 4) {
+    if (small_stage)
+      k_rs_pairs<R, 512><<<p.ncells, kRsThreads, 0, p.stream>>>(
+          sorted, p.meta, p.offsets, p.nc, cs, xi, rc2, static_cast<R *>(phi),
+          static_cast<R *>(F), epart);
+  }
+  if (!small_stage)
+    k_rs_pairs<R, 1024><<<p.ncells, kRsThreads, 0, p.stream>>>(
+        sorted, p.meta, p.offsets, p.nc, cs, xi, rc2, static_cast<R *>(phi), static_cast<R *>(F),
+        epart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_rs_energy<<<1, kRsThreads, 0, p.stream>>>(epart, p.ncells, E);
   return hipGetLastError();
@@ -344,6 +361,14 @@ se_status se_rs_plan_create(double L, double xi, double rc, int dtype, int n_max
   p->nc = nc;
   p->ncells = nc * nc * nc;
   p->cs = L / nc;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    p->cus = cus;
+  }
   p->bin_blocks = (n_max + sek::kThreads - 1) / sek::kThreads;
   const size_t rs = dtype == SE_FP64 ? 8 : 4;
   struct { void **ptr; size_t n; } allocs[] = {
