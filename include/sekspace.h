@@ -286,8 +286,9 @@ se_status se_est_se_support(int kind, double eps, double Q, double L, double xi,
  *              + k_grid M^3 + k_fft (M^3/2) ln(M^3/2),
  * with nbar = (4/3) pi rc^3 N / L^3 (section 7.1); for se_rs_eval's cell list
  * nc = min(floor(L/rc), 64), ncells = nc^3, ntest = 27 (L/nc)^3 N / L^3 the
- * pairs it tests per particle and q = ceil(ncells/512) 512 / ncells the
- * work-group rounds on a 256-CU device at two cells per CU; T the tile edge
+ * pairs it tests per particle and q = ceil(ncells/R) R / ncells the
+ * work-group rounds on a 256-CU device with R cells resident at once
+ * (FP32: 1024, or 1280 above 1024 cells; FP64: 512); T the tile edge
  * se_plan_create picks for (M, P, dtype) and nt = ceil(M/T) (the tile blocks
  * that spread, fold and gather move).  The paper's CPU model is
  * real_pair = c_real, k_window = c_sp-ga, k_grid = c_solve,

@@ -136,7 +136,12 @@ bool only_235(int m) {
   return m == 1;
 }
 
-constexpr double kRsResident = 512.0;  // real-space work-groups resident at once (2 per CU)
+// Real-space work-groups resident at once on a 256-CU device: FP32 four per
+// CU (five with the smaller stage it takes above 1024 cells), FP64 two.
+inline double rs_resident(int dtype, double ncells) {
+  if (dtype == SE_FP64) return 512.0;
+  return ncells > 1024.0 ? 1280.0 : 1024.0;
+}
 
 // The runtime model (terms as documented with se_cost_model); false when no
 // tile edge fits (M, P) in this precision.
@@ -147,7 +152,8 @@ bool predict(const se_cost_model &cm, int dtype, int N, double L, double rc, int
   const double cs = L / nc;
   const double L3 = L * L * L;
   const double ntest = 27.0 * cs * cs * cs * N / L3;
-  const double q = std::ceil(ncells / kRsResident) * kRsResident / ncells;
+  const double res = rs_resident(dtype, ncells);
+  const double q = std::ceil(ncells / res) * res / ncells;
   const double nbar = 4.0 / 3.0 * kPi * rc * rc * rc * N / L3;
   se_params prm{};
   prm.M = M;
@@ -240,13 +246,13 @@ se_status se_cost_model_mi355x(int dtype, se_cost_model *m) {
   // Non-negative least-squares fits of the model to se_kspace and se_rs_eval
   // times on an MI355X (calibrate.py of this package; 60 k-space and 15
   // real-space configurations per precision).
-  // Largest relative deviation of the fit: 26% (FP32), 33% (FP64).
+  // Largest relative deviation of the fit: 26% (FP32), 28% (FP64).
   if (dtype == SE_FP32) {
-    *m = se_cost_model{2.1391e-05, 0.0, 0.0, 1.1224e-08, 1.2684e-12,
-                       4.4925e-05, 8.5423e-11, 3.2684e-13, 3.1091e-12, 1.3104e-11, 0.0};
+    *m = se_cost_model{2.3131e-05, 0.0, 2.2287e-12, 8.2460e-09, 7.3007e-13,
+                       3.6741e-05, 8.8837e-11, 3.2826e-13, 2.2196e-12, 1.4448e-11, 0.0};
   } else if (dtype == SE_FP64) {
-    *m = se_cost_model{3.3700e-05, 0.0, 1.4808e-11, 1.6829e-08, 2.6432e-12,
-                       4.3906e-05, 1.7071e-10, 5.5856e-13, 6.2187e-12, 4.8356e-12, 1.5822e-12};
+    *m = se_cost_model{3.0820e-05, 0.0, 1.4854e-11, 1.6782e-08, 2.6519e-12,
+                       3.4925e-05, 1.4091e-10, 6.0824e-13, 6.7329e-12, 4.1532e-12, 1.7340e-12};
   } else {
     return bad("unknown dtype");
   }

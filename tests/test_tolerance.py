@@ -212,7 +212,8 @@ def test_library_choice_with_gpu_terms(T):
             continue
         nc = min(math.floor(L / rc), 64)
         ntest = 27 * (L / nc) ** 3 * N / L ** 3
-        q = math.ceil(nc ** 3 / 512) * 512 / nc ** 3
+        res = 1280 if nc ** 3 > 1024 else 1024  # FP32 pair work-groups resident at once
+        q = math.ceil(nc ** 3 / res) * res / nc ** 3
         t = (model["real_fixed"] + model["real_atom"] * N + model["real_cell"] * nc ** 3
              + model["real_test"] * N * ntest * q
              + model["k_fixed"] + model["k_atom"] * N + model["k_window"] * N * P ** 3
