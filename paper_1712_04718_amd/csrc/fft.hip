@@ -1,9 +1,12 @@
 // Steps 3-5 of Algorithm 1: forward 3D FFT of the real grid, multiplication
 // by the influence function with the k-space energy, inverse 3D FFT.
 //
-// Five passes over a half spectrum stored as C[z][kx][y], kx = 0..M/2
+// Passes over a half spectrum stored as C[z][kx][y], kx = 0..M/2
 // (K = M/2 + 1 values), y contiguous, all built on one batched Stockham FFT
-// held in LDS:
+// held in LDS.  Where a z plane fits in LDS twice (compiled M, FP32 M <= 128,
+// FP64 M <= 96) the x and y passes of each direction run as one plane pass
+// (k_fft_xy_r2c, k_fft_yx_c2r, below), so the sequence is xy, z, yx; other
+// sizes run the five passes:
 //   x_r2c : pairs of real rows packed as one complex row, transformed, and
 //           split into two half spectra, written as runs along y;
 //   y_fwd : FFT of B contiguous y pencils (consecutive (z, kx));
@@ -21,8 +24,9 @@
 // unnormalised; the inverse is conj(FFT(conj(.))).
 //
 // In LDS a batch of B pencils of length M is stored element-major
-// (element k of pencil b at k*B + b) so that the B threads working on the
-// same butterfly index of different pencils touch consecutive addresses.
+// (element k of pencil b at k*PB + b, PB >= B) so that the B threads working
+// on the same butterfly index of different pencils touch consecutive
+// addresses.
 #include "se_common.hpp"
 
 namespace sek {
