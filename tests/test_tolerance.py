@@ -243,6 +243,21 @@ def test_library_cost_terms(T):
         assert (tr, tk) == (pytest.approx(want[n][0], rel=1e-12), pytest.approx(want[n][1], rel=1e-12)), n
 
 
+@pytest.mark.parametrize("dtype,resident", [("f32", 1280), ("f64", 512)])
+def test_library_real_space_rounds(T, dtype, resident):
+    """The work-group rounds factor of the tested-pairs term above 1024
+    cells (L = 220, rc = 10: 22^3 cells): FP32 holds 1280 pair work-groups at
+    once (five per CU with the smaller stage), FP64 512."""
+    N, L, rc = 1_000_000, 220.0, 10.0
+    names = [n for n, _ in __import__("paper_1712_04718_amd._lib", fromlist=["x"]).SeCostModel._fields_]
+    unit = {k: 0.0 for k in names}
+    unit["real_test"] = 1.0
+    tr, _ = T.predict(unit, dtype, N, L, rc, 192, 8)
+    cells = 22 ** 3
+    q = math.ceil(cells / resident) * resident / cells
+    assert tr == pytest.approx(N * 27 * (L / 22) ** 3 * N / L ** 3 * q, rel=1e-12)
+
+
 def test_library_argument_errors(T):
     from paper_1712_04718_amd._lib import SeError
     bad = [lambda: T.real_error("force", -1.0, 10.0, 1.0, 1.0),
