@@ -1,8 +1,9 @@
 """Evaluations captured in a HIP graph: every replay, with new positions and
 charges copied into the captured inputs and eager work between the replays,
 equals an eager evaluation of the same inputs: the k-space path bit for bit
-in FP32 (its spread is order-free) and to rounding in FP64 (LDS double
-atomics), the real-space sum to rounding."""
+in both precisions (its spread accumulates in fixed point, order-free), the
+real-space sum to rounding (the order of particles in a cell comes from
+atomics)."""
 import ctypes
 
 import numpy as np
@@ -58,7 +59,7 @@ def test_kspace_graph_replays(window, M, P, dtype):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         step()
-    rt = 0.0 if dtype == torch.float32 else 1e-12
+    rt = 0.0
     for rep in range(4):
         x, q = _inputs(rng, N, L)
         xs.copy_(torch.tensor(x, dtype=dtype))

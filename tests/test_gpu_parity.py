@@ -356,9 +356,9 @@ def test_ik_forces(window, M, P, dtype):
         Eo, phio, Fo = O.spme_kspace_ik(xo, qo, L, xi, M, P)
     e = errors((E.item(), phi.double().cpu().numpy(), F.double().cpu().numpy()), (Eo, phio, Fo))
     assert max(e) < TOL[dtype], e
-    # same spread and potential path; FP64 spreads with LDS double atomics, so
-    # it reproduces to rounding only (FP32 bit for bit)
-    rt = 0 if dtype == torch.float32 else 1e-12
+    # same spread and potential path, and both precisions accumulate in fixed
+    # point (order-free), so E, phi and the adjoint agree bit for bit
+    rt = 0
     np.testing.assert_allclose(E.item(), Ea.item(), rtol=rt, atol=0)
     np.testing.assert_allclose(phi.cpu().numpy(), phia.cpu().numpy(), rtol=0,
                                atol=rt * float(phia.abs().max()))
