@@ -712,15 +712,17 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
   }
   if (!epart) return;  // uniform across the work-group
 
-  // energy: one partial per block, added in a fixed order by the next pass
-  __shared__ double red[kThreads];
-  red[threadIdx.x] = e;
+  // energy: one partial per block (a fixed tree over the lanes of each wave,
+  // then the waves in order), added in a fixed order by the next pass
+  for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
+  __shared__ double wred[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = e;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) s += wred[w];
+    epart[blockIdx.x] = s;
   }
-  if (threadIdx.x == 0) epart[blockIdx.x] = red[0];
 }
 
 // The three-launch sequence with the fused plane passes (compile-time M

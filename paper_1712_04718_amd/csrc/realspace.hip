@@ -265,16 +265,17 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
 // E = sum of the cell partials in a fixed order (one work-group).
 __global__ void __launch_bounds__(kRsThreads)
 k_rs_energy(const double *__restrict__ epart, int n, double *__restrict__ E) {
-  __shared__ double red[kRsThreads];
+  __shared__ double red[kRsThreads / 64];
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += kRsThreads) s += epart[i];
-  red[threadIdx.x] = s;
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int st = kRsThreads / 2; st > 0; st >>= 1) {
-    if (static_cast<int>(threadIdx.x) < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kRsThreads / 64; ++w) t += red[w];
+    *E = t;
   }
-  if (threadIdx.x == 0) *E = red[0];
 }
 
 template <typename R>
