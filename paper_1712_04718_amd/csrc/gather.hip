@@ -36,21 +36,28 @@ template <typename R> struct Kahan {
   __device__ inline R value() const { return s - c; }
 };
 
-// particles per phase-A round: one per thread, fewer (down to a wave) while
-// the factor table would exceed 32 KB
-constexpr int gather_chunk(int real_size, int rec) {
-  int c = kTileThreads;
-  while (c > 64 && real_size * rec * c > 32768) c /= 2;
-  return c;
-}
 constexpr int gather_rec(int window, int S) { return window == kGauss ? 3 * S + 4 : 6 * S + 1; }
+// LDS of a gathering work-group besides its factor table and indices: the
+// tile block, the lane partials (supports that are not a power of two) and
+// the offset tables
+constexpr long long gather_fixed_bytes(int real_size, int S, int T) {
+  const long long ts = T + S - 1;
+  return real_size * ((ts * ts * ts + 3) & ~3LL) +
+         ((S & (S - 1)) ? static_cast<long long>(real_size) * kTileThreads * 4 : 0) +
+         4 * (ts * ts + ts);
+}
+// particles per phase-A round (tile_chunk): factors plus two indices each
+constexpr int gather_chunk(int real_size, int window, int S, int T) {
+  return tile_chunk(static_cast<long long>(real_size) * gather_rec(window, S) + 8,
+                    gather_fixed_bytes(real_size, S, T));
+}
 
 // LDS layout: [tile block][lane partials][factors][anchors][original indices]
 template <typename R, int WIN, int S, int T> struct GatherLds {
   static constexpr int TS = T + S - 1;
   // SE: g (3S), offsets d (3), q; B-spline: g (3S), dg (3S), q
   static constexpr int REC = gather_rec(WIN, S);
-  static constexpr int CHUNK = gather_chunk(sizeof(R), REC);
+  static constexpr int CHUNK = gather_chunk(sizeof(R), WIN, S, T);
   static constexpr size_t BLK = sizeof(R) * ((TS * TS * TS + 3) & ~3);
   // lane partials, only for supports that are not a power of two
   static constexpr size_t RED = (S & (S - 1)) ? sizeof(R) * kTileThreads * 4 : 0;
@@ -59,6 +66,8 @@ template <typename R, int WIN, int S, int T> struct GatherLds {
   // grid offsets of the block's rows (z, y) and wrapped x coordinates
   static constexpr size_t TAB = sizeof(int) * (TS * TS + TS);
   static constexpr size_t TOTAL = BLK + RED + FAC + IDX + TAB;
+  static_assert(BLK + RED + TAB == static_cast<size_t>(gather_fixed_bytes(sizeof(R), S, T)),
+                "LDS layout and chunk rule disagree");
 };
 
 template <typename R, int WIN, int S, int T>
@@ -379,13 +388,11 @@ hipError_t gather_call(se_plan &p, const GatherCall &g) {
 }  // namespace
 
 size_t gather_lds_bytes(int real_size, int window, int S, int T) {
-  const size_t ts = T + S - 1;
   const int win = window == SE_WINDOW_GAUSSIAN ? kGauss : kBspline;
   const size_t rec = gather_rec(win, S);
-  const size_t chunk = gather_chunk(real_size, static_cast<int>(rec));
-  const size_t red = (S & (S - 1)) ? static_cast<size_t>(real_size) * kTileThreads * 4 : 0;
-  return real_size * ((ts * ts * ts + 3) & ~static_cast<size_t>(3)) + red +
-         real_size * chunk * rec + 2 * 4 * chunk + 4 * (ts * ts + ts);
+  const size_t chunk = gather_chunk(real_size, win, S, T);
+  return static_cast<size_t>(gather_fixed_bytes(real_size, S, T)) + real_size * chunk * rec +
+         2 * 4 * chunk;
 }
 
 hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode, void *out_pot,

@@ -36,17 +36,17 @@ template <typename R> struct Acc;
 template <> struct Acc<float> { using T = int; };      // fixed point
 template <> struct Acc<double> { using T = long long; };  // fixed point
 
-// particles per phase-A round: one per thread, fewer (down to a wave) while
-// the factor table would exceed 32 KB
-constexpr int spread_chunk(int real_size, int S) {
-  int c = kTileThreads;
-  while (c > 64 && real_size * 3 * S * c > 32768) c /= 2;
-  return c;
+// particles per phase-A round (tile_chunk): 3S factors, an anchor and a
+// charge each, beside the fixed-point block and the reduction slots
+constexpr int spread_chunk(int real_size, int S, int T) {
+  const long long ts = T + S - 1, acc = real_size == 4 ? 4 : 8;
+  return tile_chunk(static_cast<long long>(real_size) * 3 * S + 4 + real_size,
+                    acc * ((ts * ts * ts + 3) & ~3LL) + 128);
 }
 
 constexpr size_t spread_lds_total(int real_size, int S, int T) {
   const size_t TS = T + S - 1, acc = real_size == 4 ? 4 : 8;
-  const size_t chunk = spread_chunk(real_size, S);
+  const size_t chunk = spread_chunk(real_size, S, T);
   return acc * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) + real_size * chunk * 3 * S +
          4 * chunk + real_size * chunk + 128;
 }
@@ -55,7 +55,7 @@ template <typename R, int S, int T> struct SpreadLds {
   using A = typename Acc<R>::T;
   static constexpr int TS = T + S - 1;
   static constexpr int REC = 3 * S;
-  static constexpr int CHUNK = spread_chunk(sizeof(R), S);
+  static constexpr int CHUNK = spread_chunk(sizeof(R), S, T);
   static constexpr size_t BLK = sizeof(A) * ((TS * TS * TS + 3) & ~3);
   static constexpr size_t FAC = sizeof(R) * CHUNK * REC;
   static constexpr size_t ANC = sizeof(int) * CHUNK;
