@@ -44,11 +44,12 @@ namespace sek {
 namespace {
 
 constexpr int kRsThreads = 256;
-// Pair queue entries per thread.  FP32 keeps the work-group's LDS at about
-// 37 KB (16 KB of queue), so four work-groups share a CU; a 32-entry queue
-// (53 KB, three per CU) made water_L100 459 us instead of 352.  FP64 keeps 32
-// (a shorter queue flushed more often and was slower there).
-template <typename R> constexpr int kQueue = sizeof(R) == 4 ? 16 : 32;
+// Pair queue entries per thread (a template argument of the pair kernel):
+// FP32 takes 16 with the 1024-particle stage, keeping the work-group's LDS at
+// about 37 KB so that four share a CU (a 32-entry queue, 53 KB and three per
+// CU, made water_L100 459 us instead of 352), and 12 with the 512-particle
+// stage (10^6 ions: 2.44 instead of 2.61 ms).  FP64 keeps 32 (a shorter
+// queue flushed more often and was slower there).
 constexpr int kBatch = 8;    // LDS reads issued together in the test and evaluation loops
 
 template <typename R> struct alignas(4 * sizeof(R)) Staged {
@@ -57,8 +58,9 @@ template <typename R> struct alignas(4 * sizeof(R)) Staged {
 
 // Staged neighbours per pass (CAP): 1024 (16 KB of LDS in FP32, 32 KB in
 // FP64); FP32 takes 512 when the cells outnumber four work-groups per CU, so
-// that five share a CU (10^6 ions: 2.61 instead of 2.83 ms), and keeps 1024,
-// fewer staging passes, when every cell already runs at once.
+// that more share a CU (10^6 ions: 2.61 instead of 2.83 ms with a 16-entry
+// queue), and keeps 1024, fewer staging passes, when every cell already runs
+// at once.
 
 // FP32 erfc(x) for x >= 0 from e2 = e^{-x^2}: e2 t sum a_i t^i, t = 1/(1 + p x)
 // (the form of Abramowitz-Stegun 7.1.26 with eight terms fitted for relative
@@ -110,12 +112,12 @@ __device__ inline void pair_term(double rx, double ry, double rz, double r2, dou
 // and queues the indices of the pairs in range in LDS; the wave evaluates the
 // queued pairs together once some lane's queue could overflow, so the erfc and
 // exp run on full waves instead of on every tested pair under a mask.
-template <typename R, int CAP>
+template <typename R, int CAP, int QN>
 __global__ void __launch_bounds__(kRsThreads)
 k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ meta,
            const int *__restrict__ offsets, int nc, R cs, R xi, R rc2, R *__restrict__ phi,
            R *__restrict__ F, double *__restrict__ epart) {
-  constexpr int QN = kQueue<R>;
+  static_assert(QN >= kBatch, "a batch of tests must fit the queue");
   __shared__ Staged<R> stage[CAP];
   __shared__ int queue[QN * kRsThreads];  // entry m of thread t at m * 256 + t
   __shared__ int nb_src[27], nb_pre[28];
@@ -307,12 +309,12 @@ hipError_t rs_eval(se_rs_plan &p, int N, const void *x, const void *q, double *E
   if constexpr (sizeof(R) == 4) small_stage = p.ncells > 4 * p.cus;
   if constexpr (sizeof(R) == 4) {
     if (small_stage)
-      k_rs_pairs<R, 512><<<p.ncells, kRsThreads, 0, p.stream>>>(
+      k_rs_pairs<R, 512, 12><<<p.ncells, kRsThreads, 0, p.stream>>>(
           sorted, p.meta, p.offsets, p.nc, cs, xi, rc2, static_cast<R *>(phi),
           static_cast<R *>(F), epart);
   }
   if (!small_stage)
-    k_rs_pairs<R, 1024><<<p.ncells, kRsThreads, 0, p.stream>>>(
+    k_rs_pairs<R, 1024, sizeof(R) == 4 ? 16 : 32><<<p.ncells, kRsThreads, 0, p.stream>>>(
         sorted, p.meta, p.offsets, p.nc, cs, xi, rc2, static_cast<R *>(phi), static_cast<R *>(F),
         epart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
