@@ -39,7 +39,9 @@
  *   - The k = 0 mode is always dropped (section 1); a non-neutral charge set
  *     is accepted and no neutralising-background term is added, so that
  *     dE/dq = phi holds for any q.
- *   - NaN or Inf inputs are not detected; they propagate into the outputs.
+ *   - NaN or Inf inputs are not detected: the results of that call are then
+ *     unspecified, but no index derived from them leaves the grid or the
+ *     plan's workspace, and the plan stays usable for the next call.
  */
 #ifndef SEKSPACE_H
 #define SEKSPACE_H

@@ -34,10 +34,7 @@ namespace {
 constexpr int kLdsTilesMax = 8192;  // tiles the LDS tables of k_bin_count_lds hold
 
 __device__ inline long long floor_div_mod(double u, int M, double *frac) {
-  double fl = floor(u);
-  *frac = u - fl;
-  long long i = static_cast<long long>(fl) % M;
-  return i < 0 ? i + M : i;
+  return anchor_mod(u, M, frac);
 }
 
 // Tile of a particle at (x0, x1, x2).

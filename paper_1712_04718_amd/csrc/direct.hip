@@ -33,11 +33,9 @@ k_direct_prep(int N, const R *__restrict__ x, const R *__restrict__ q, double h,
     R d[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const double u = static_cast<double>(x[3 * n + ax]) / h;
-      const double fl = floor(u);
-      long long i = static_cast<long long>(fl) % M;
-      a[ax] = static_cast<int>(i < 0 ? i + M : i);
-      d[ax] = static_cast<R>(u - fl);
+      double frac;
+      a[ax] = anchor_mod(static_cast<double>(x[3 * n + ax]) / h, M, &frac);
+      d[ax] = static_cast<R>(frac);
     }
     const R qn = q[n];
     out[n] = SortedParticle<R>{d[0], d[1], d[2], qn};

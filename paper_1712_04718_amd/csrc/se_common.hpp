@@ -53,6 +53,21 @@ __device__ inline int xcd_local(int b, int G) {
 // v mod M for v in [-M, 3M), branch-free.  Every grid index of a staged tile
 // block lies in [-(S-1), M + T + S - 3], inside that range whenever S <= M and
 // T + S - 3 < 2M (the plan checks both).
+// Anchor of a coordinate u in grid units: floor(u) reduced mod M into
+// [0, M), and the offset u - floor(u).  A non-finite u (or one beyond the
+// integer range) takes anchor 0 while its offset stays NaN, so the outputs
+// show the bad input and no index derived from it leaves the grid.
+__device__ inline int anchor_mod(double u, int M, double *frac) {
+  double fl = floor(u);
+  *frac = u - fl;
+  if (!(fabs(fl) < 4.0e18)) {
+    fl = 0.0;
+    *frac = __builtin_nan("");
+  }
+  const long long i = static_cast<long long>(fl) % M;
+  return static_cast<int>(i < 0 ? i + M : i);
+}
+
 __device__ inline int wrap_near(int v, int M) {
   v = v < 0 ? v + M : v;
   v = v >= M ? v - M : v;

@@ -146,11 +146,16 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
   __syncthreads();  // maximum, first factors and zeroed block visible
   double qmax = 0.0;
   for (int w = 0; w < NWAVES; ++w) qmax = fmax(qmax, red_max[w]);
+  // (a non-finite charge weighs 0 here: the integer conversion stays defined)
+  const auto weight = [&](double aq) {
+    const double w = ceil(aq / qmax * 1048576.0);
+    return w <= 1048576.0 ? static_cast<long long>(w) : 0LL;
+  };
   long long u = 0;
   if (qmax > 0.0) {
-    if (tid < n) u = static_cast<long long>(ceil(static_cast<double>(qa) / qmax * 1048576.0));
+    if (tid < n) u = weight(static_cast<double>(qa));
     for (int p = start + kTileThreads + tid; p < end; p += kTileThreads)
-      u += static_cast<long long>(ceil(fabs(static_cast<double>(sorted[p].q)) / qmax * 1048576.0));
+      u += weight(fabs(static_cast<double>(sorted[p].q)));
   }
   for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
   if ((tid & 63) == 0) red_u[tid >> 6] = u;

@@ -395,3 +395,31 @@ def test_bitwise_reproducible_both_precisions(window, P):
         (E1, p1, F1), (E2, p2, F2) = outs
         assert E1.item() == E2.item(), dtype
         assert torch.equal(p1, p2) and torch.equal(F1, F2), dtype
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_nonfinite_inputs_leave_the_plan_usable(dtype):
+    """A call with NaN and Inf positions and charges returns (its results are
+    unspecified), and the next call with finite inputs on the same plan
+    equals a fresh plan's bit for bit."""
+    print(f"[nonfinite] {dtype}", flush=True)
+    L, xi, M, P = 10.0, 1.2, 32, 8
+    x, q = _rand(500, L, 71)
+    xs, qs = to_dev(x, q, dtype)
+    bad_x, bad_q = xs.clone(), qs.clone()
+    bad_x[3, 0] = float("nan")
+    bad_x[7, 1] = float("inf")
+    bad_x[9, 2] = -float("inf")
+    bad_q[11] = float("nan")
+    bad_q[13] = float("inf")
+    plan = SEPlan(M, P, L, xi, dtype=dtype, n_max=len(q))
+    fresh = SEPlan(M, P, L, xi, dtype=dtype, n_max=len(q))
+    plan.kspace(bad_x, bad_q)
+    torch.cuda.synchronize()
+    E1, phi1, F1 = plan.kspace(xs, qs)
+    E2, phi2, F2 = fresh.kspace(xs, qs)
+    torch.cuda.synchronize()
+    assert E1.item() == E2.item()
+    assert torch.equal(phi1, phi2) and torch.equal(F1, F2)
+    for p in (plan, fresh):
+        p.close()
