@@ -246,13 +246,13 @@ se_status se_cost_model_mi355x(int dtype, se_cost_model *m) {
   // Non-negative least-squares fits of the model to se_kspace and se_rs_eval
   // times on an MI355X (calibrate.py of this package; 60 k-space and 15
   // real-space configurations per precision).
-  // Largest relative deviation of the fit: 26% (FP32), 28% (FP64).
+  // Largest relative deviation of the fit: 26% (FP32), 25% (FP64).
   if (dtype == SE_FP32) {
     *m = se_cost_model{2.3131e-05, 0.0, 2.2287e-12, 8.2460e-09, 7.3007e-13,
                        3.6741e-05, 8.8837e-11, 3.2826e-13, 2.2196e-12, 1.4448e-11, 0.0};
   } else if (dtype == SE_FP64) {
-    *m = se_cost_model{3.0820e-05, 0.0, 1.4854e-11, 1.6782e-08, 2.6519e-12,
-                       3.4925e-05, 1.4091e-10, 6.0824e-13, 6.7329e-12, 4.1532e-12, 1.7340e-12};
+    *m = se_cost_model{2.9351e-05, 0.0, 8.7526e-12, 1.6545e-08, 1.9063e-12,
+                       3.6234e-05, 1.4825e-10, 5.9724e-13, 6.8787e-12, 0.0, 1.9454e-12};
   } else {
     return bad("unknown dtype");
   }
