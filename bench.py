@@ -444,8 +444,15 @@ def run(args):
         if total_ms:
             log(f"total Ewald sum: sequential {total_ms['sequential'] * 1e3:.1f} us, "
                 f"overlapped {total_ms['overlapped'] * 1e3:.1f} us")
-        nc = min(int(L // REAL_SPACE_RC), 64)
-        tested = N * 27.0 * (L / nc) ** 3 * N / L ** 3
+        # the cell list the library takes for this N: its cell count from the
+        # runtime model's per-cell term; the fine list (more cells than the
+        # coarse one) searches 5 cells wide, the coarse one 3
+        from paper_1712_04718_amd import _lib as rs_lib, tolerance as rs_tol
+        unit = {n: 0.0 for n, _ in rs_lib.SeCostModel._fields_}
+        unit["real_cell"] = 1.0
+        nc = round(rs_tol.predict(unit, "f32", N, L, REAL_SPACE_RC, 48, 4)[0] ** (1.0 / 3.0))
+        w = 5 if nc > int(L // REAL_SPACE_RC) else 3
+        tested = N * float(w) ** 3 * (L / nc) ** 3 * N / L ** 3
         in_range = N * 4.0 / 3.0 * math.pi * REAL_SPACE_RC ** 3 * N / L ** 3
         flops = tested * RS_FLOPS_TEST + in_range * RS_FLOPS_PAIR
         real_space = {"rc": REAL_SPACE_RC, "ms_per_eval": ms_rs, "reps": reps,

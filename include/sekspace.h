@@ -219,7 +219,12 @@ se_status se_eval_targets(se_plan *plan, int nt, const void *xt, void *phi_t, vo
 typedef struct se_rs_plan se_rs_plan;
 
 /* A real-space plan on the current device for up to n_max particles in a
- * cube of side L: cell list with cells of edge >= rc.  Requires
+ * cube of side L.  Each se_rs_eval builds a cell list for its N: cells of
+ * edge >= rc searched one cell to each side, or, where those of edge
+ * >= rc/2 hold on average >= 10 particles (>= 5 when the coarse list has
+ * fewer than 1024 cells), cells of edge >= rc/2 searched two to each side;
+ * at most 64 cells per side (the coarse list alone where L >= 64 rc).
+ * Requires
  * 0 < rc <= L/3 (SE_ERR_ARG otherwise), so at most one image of a pair lies
  * within rc.  The plan owns its workspace. */
 se_status se_rs_plan_create(double L, double xi, double rc, int dtype, int n_max,
@@ -287,7 +292,8 @@ se_status se_est_se_support(int kind, double eps, double Q, double L, double xi,
  *   t_kspace = k_fixed + k_atom N + k_window N P^3 + k_block nt^3 (T+P-1)^3
  *              + k_grid M^3 + k_fft (M^3/2) ln(M^3/2),
  * with nbar = (4/3) pi rc^3 N / L^3 (section 7.1); for se_rs_eval's cell list
- * nc = min(floor(L/rc), 64), ncells = nc^3, ntest = 27 (L/nc)^3 N / L^3 the
+ * (nc cells per side searched w = 3 or 5 wide, as se_rs_plan_create
+ * states) ncells = nc^3, ntest = w^3 (L/nc)^3 N / L^3 the
  * pairs it tests per particle and q = ceil(ncells/R) R / ncells the
  * work-group rounds on a 256-CU device with R cells resident at once
  * (FP32: 1024, or 1280 above 1024 cells; FP64: 512); T the tile edge

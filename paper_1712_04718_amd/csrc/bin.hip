@@ -180,7 +180,14 @@ k_bin_scan(int *__restrict__ counts, int *__restrict__ offsets, int ntiles) {
   int local = 0;
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) local += v[k];
-  for (int t = lo + kScanPer; t < hi; ++t) local += counts[t * kCountStride];  // > 32K tiles
+  // more than 32K tiles: the rest in blocks of kScanPer loads issued together
+  for (int t0 = lo + kScanPer; t0 < hi; t0 += kScanPer) {
+    int w[kScanPer];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) w[k] = (t0 + k < hi) ? counts[(t0 + k) * kCountStride] : 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) local += w[k];
+  }
   const int lane = tid & 63, wave = tid >> 6;
   int incl = local;  // inclusive scan over the lanes of the wave
 #pragma unroll
@@ -202,7 +209,14 @@ k_bin_scan(int *__restrict__ counts, int *__restrict__ offsets, int ntiles) {
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k)
     if (lo + k < hi) emit(lo + k, v[k]);
-  for (int t = lo + kScanPer; t < hi; ++t) emit(t, counts[t * kCountStride]);
+  for (int t0 = lo + kScanPer; t0 < hi; t0 += kScanPer) {
+    int w[kScanPer];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) w[k] = (t0 + k < hi) ? counts[(t0 + k) * kCountStride] : 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+      if (t0 + k < hi) emit(t0 + k, w[k]);
+  }
   if (tid == kScanThreads - 1) offsets[ntiles] = base + incl;
 }
 

@@ -27,7 +27,10 @@ struct se_rs_plan {
   int dtype;
   int n_max;
   hipStream_t stream;
+  int nc_max;    // cells per side the buffers hold
+  // the current call's cell list
   int nc;        // cells per side
+  int reach;     // neighbour cells searched on each side (1 or 2)
   int cus;       // compute units of the plan's device
   int ncells;
   double cs;     // cell edge
@@ -41,6 +44,10 @@ struct se_rs_plan {
 };
 
 namespace sek {
+
+int rs_reach(double L, double rc, long long N);
+int rs_cells_per_side(double L, double rc, int reach);
+
 namespace {
 
 constexpr int kRsThreads = 256;
@@ -149,22 +156,24 @@ __device__ inline void pair_term(double rx, double ry, double rz, double r2, dou
 // and queues the indices of the pairs in range in LDS; the wave evaluates the
 // queued pairs together once some lane's queue could overflow, so the erfc and
 // exp run on full waves instead of on every tested pair under a mask.
-template <typename R, int CAP, int QN>
+template <typename R, int CAP, int QN, int RCH>
 __global__ void __launch_bounds__(kRsThreads)
 k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ meta,
            const int *__restrict__ offsets, int nc, R cs, R xi, R rc2, R *__restrict__ phi,
            R *__restrict__ F, double *__restrict__ epart) {
   static_assert(QN >= kBatch, "a batch of tests must fit the queue");
+  constexpr int W = 2 * RCH + 1, NB = W * W * W;  // neighbour cells, home at NB / 2
+  static_assert(NB <= 128, "the prefix sum takes two neighbour cells per lane of one wave");
   __shared__ Staged<R> stage[CAP];
   __shared__ int queue[QN * kRsThreads];  // entry m of thread t at m * 256 + t
-  __shared__ int nb_src[27], nb_pre[28];
+  __shared__ int nb_src[NB], nb_pre[NB + 1];
   __shared__ R red[4][kRsThreads];
   __shared__ double ered[kRsThreads / 64];
   const int tid = threadIdx.x;
   const int cell = xcd_local(blockIdx.x, gridDim.x);
   const int cz = cell / (nc * nc), cy = (cell / nc) % nc, cx = cell % nc;
-  if (tid < 27) {
-    const int oz = tid / 9 - 1, oy = (tid / 3) % 3 - 1, ox = tid % 3 - 1;
+  if (tid < NB) {
+    const int oz = tid / (W * W) - RCH, oy = (tid / W) % W - RCH, ox = tid % W - RCH;
     const int nz = cz + oz < 0 ? cz + oz + nc : (cz + oz >= nc ? cz + oz - nc : cz + oz);
     const int ny = cy + oy < 0 ? cy + oy + nc : (cy + oy >= nc ? cy + oy - nc : cy + oy);
     const int nx = cx + ox < 0 ? cx + ox + nc : (cx + ox >= nc ? cx + ox - nc : cx + ox);
@@ -173,15 +182,25 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
     nb_pre[tid + 1] = offsets[nb + 1] - offsets[nb];
   }
   __syncthreads();
-  if (tid == 0) {
-    nb_pre[0] = 0;
-    for (int k = 0; k < 27; ++k) nb_pre[k + 1] += nb_pre[k];
+  if (tid < 64) {
+    // inclusive prefix sum of the counts nb_pre[1..NB], two per lane
+    const int i1 = 2 * tid + 1, i2 = 2 * tid + 2;
+    const int a = i1 <= NB ? nb_pre[i1] : 0, b = i2 <= NB ? nb_pre[i2] : 0;
+    int v = a + b;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o);
+      if (tid >= o) v += u;
+    }
+    const int before = v - a - b;
+    if (i1 <= NB) nb_pre[i1] = before + a;
+    if (i2 <= NB) nb_pre[i2] = v;
+    if (tid == 0) nb_pre[0] = 0;
   }
   __syncthreads();
-  const int S = nb_pre[27];
-  const int home0 = nb_pre[13];          // home cell (offset 0,0,0) in the staged order
-  const int nh = nb_pre[14] - home0;
-  const int hsrc = nb_src[13];
+  const int S = nb_pre[NB];
+  const int home0 = nb_pre[NB / 2];  // home cell (offset 0,0,0) in the staged order
+  const int nh = nb_pre[NB / 2 + 1] - home0;
+  const int hsrc = nb_src[NB / 2];
   const R c2 = static_cast<R>(1.1283791670955126) * xi;  // 2 xi / sqrt(pi)
   double e = 0.0;
 
@@ -208,6 +227,15 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
           const int j = c0 + tid + u * kRsThreads;
           kk[u] = -1;
           if (j < c0 + cn) {
+            if constexpr (RCH > 1) {
+              // neighbour cell of staged particle j: the last k with nb_pre[k] <= j
+              int lo_k = k, hi_k = NB - 1;
+              while (lo_k < hi_k) {
+                const int mid = (lo_k + hi_k + 1) >> 1;
+                if (nb_pre[mid] <= j) lo_k = mid; else hi_k = mid - 1;
+              }
+              k = lo_k;
+            }
             while (nb_pre[k + 1] <= j) ++k;
             kk[u] = k;
             buf[u] = sorted[nb_src[k] + (j - nb_pre[k])];
@@ -218,9 +246,9 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
           if (kk[u] >= 0) {
             const int kc = kk[u];
             stage[tid + u * kRsThreads] =
-                Staged<R>{(static_cast<R>(kc % 3 - 1) + buf[u].dx) * cs,
-                          (static_cast<R>((kc / 3) % 3 - 1) + buf[u].dy) * cs,
-                          (static_cast<R>(kc / 9 - 1) + buf[u].dz) * cs, buf[u].q};
+                Staged<R>{(static_cast<R>(kc % W - RCH) + buf[u].dx) * cs,
+                          (static_cast<R>((kc / W) % W - RCH) + buf[u].dy) * cs,
+                          (static_cast<R>(kc / (W * W) - RCH) + buf[u].dz) * cs, buf[u].q};
           }
         }
       }
@@ -305,8 +333,20 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
 __global__ void __launch_bounds__(kRsThreads)
 k_rs_energy(const double *__restrict__ epart, int n, double *__restrict__ E) {
   __shared__ double red[kRsThreads / 64];
+  // each thread sums its strided share in index order, loads issued eight
+  // at a time (the cell count reaches 64^3)
+  constexpr int U = 8;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kRsThreads) s += epart[i];
+  for (int i0 = threadIdx.x; i0 < n; i0 += U * kRsThreads) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kRsThreads;
+      v[u] = i < n ? epart[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
+  }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -320,6 +360,11 @@ k_rs_energy(const double *__restrict__ epart, int n, double *__restrict__ E) {
 template <typename R>
 hipError_t rs_eval(se_rs_plan &p, int N, const void *x, const void *q, double *E, void *phi,
                    void *F) {
+  p.reach = rs_reach(p.L, p.rc, N);
+  p.nc = rs_cells_per_side(p.L, p.rc, p.reach);
+  p.ncells = p.nc * p.nc * p.nc;
+  p.cs = p.L / p.nc;
+  if (p.nc > p.nc_max) return hipErrorInvalidValue;
   BinJob j;
   j.N = N;
   j.x = x;
@@ -342,18 +387,27 @@ hipError_t rs_eval(se_rs_plan &p, int N, const void *x, const void *q, double *E
   double *epart = p.part + p.bin_blocks;
   const auto sorted = static_cast<const SortedParticle<R> *>(p.sorted);
   const R cs = static_cast<R>(p.cs), xi = static_cast<R>(p.xi), rc2 = static_cast<R>(p.rc * p.rc);
+  const auto run = [&](auto kernel) {
+    kernel<<<p.ncells, kRsThreads, 0, p.stream>>>(sorted, p.meta, p.offsets, p.nc, cs, xi, rc2,
+                                                  static_cast<R *>(phi), static_cast<R *>(F),
+                                                  epart);
+  };
   bool small_stage = false;
-  if constexpr (sizeof(R) == 4) small_stage = p.ncells > 4 * p.cus;
   if constexpr (sizeof(R) == 4) {
-    if (small_stage)
-      k_rs_pairs<R, 512, 12><<<p.ncells, kRsThreads, 0, p.stream>>>(
-          sorted, p.meta, p.offsets, p.nc, cs, xi, rc2, static_cast<R *>(phi),
-          static_cast<R *>(F), epart);
+    small_stage = p.ncells > 4 * p.cus;
+    if (small_stage) {
+      if (p.reach == 2)
+        run(k_rs_pairs<R, 512, 12, 2>);
+      else
+        run(k_rs_pairs<R, 512, 12, 1>);
+    }
   }
-  if (!small_stage)
-    k_rs_pairs<R, 1024, sizeof(R) == 4 ? 16 : 32><<<p.ncells, kRsThreads, 0, p.stream>>>(
-        sorted, p.meta, p.offsets, p.nc, cs, xi, rc2, static_cast<R *>(phi), static_cast<R *>(F),
-        epart);
+  if (!small_stage) {
+    if (p.reach == 2)
+      run(k_rs_pairs<R, 1024, sizeof(R) == 4 ? 16 : 32, 2>);
+    else
+      run(k_rs_pairs<R, 1024, sizeof(R) == 4 ? 16 : 32, 1>);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_rs_energy<<<1, kRsThreads, 0, p.stream>>>(epart, p.ncells, E);
   return hipGetLastError();
@@ -372,6 +426,29 @@ void rs_free(se_rs_plan &p) {
 }
 
 }  // namespace
+
+// Cell list of the real-space sum of N particles, box edge L, cutoff
+// rc <= L/3: cells of edge >= rc searched one cell to each side (3^3
+// neighbour cells, which test 27 cs^3 / ((4/3) pi rc^3) >= 6.4 times the
+// pairs in range), or cells of edge >= rc / 2 searched two to each side
+// (5^3 cells, 3.7 times).  The finer list pays a fixed cost per cell (125
+// neighbour ranges to find and stage) and wins only where its cells are
+// populated: MI355X times (FP32 and FP64, 20k-400k particles, rc 4-12 at
+// 0.1 per unit volume) favour it from 10 particles per cell, and from 5
+// when the coarse list has fewer than 1024 cells (four work-groups per CU);
+// below 3 per cell it took 1.7 to 8 times as long.  At most 64 cells per
+// side (the counters take a cache line each); larger cells stay correct.
+int rs_reach(double L, double rc, long long N) {
+  const double nc1 = std::floor(L / rc);
+  if (nc1 >= 64.0) return 1;
+  const double nc2 = std::fmin(std::floor(2.0 * L / rc), 64.0);
+  const double occ = static_cast<double>(N) / (nc2 * nc2 * nc2);
+  return (occ >= 10.0 || (occ >= 5.0 && nc1 * nc1 * nc1 < 1024.0)) ? 2 : 1;
+}
+int rs_cells_per_side(double L, double rc, int reach) {
+  return static_cast<int>(std::fmin(std::floor(reach * L / rc), 64.0));
+}
+
 }  // namespace sek
 
 extern "C" {
@@ -387,9 +464,9 @@ se_status se_rs_plan_create(double L, double xi, double rc, int dtype, int n_max
     return rs_fail(SE_ERR_ARG, "cutoff rc = %g must lie in (0, L/3], L = %g", rc, L);
   if (dtype != SE_FP32 && dtype != SE_FP64) return sek::report(SE_ERR_ARG, "unknown dtype");
   if (n_max < 1) return sek::report(SE_ERR_ARG, "n_max must be >= 1");
-  // cells of edge L / nc >= rc; at most 64 per side (the counters take a
-  // cache line each), larger cells are still correct
-  const int nc = static_cast<int>(std::fmin(std::floor(L / rc), 64.0));
+  // the cell list of each call follows its N (sek::rs_reach); the buffers
+  // hold the finer of the two
+  const int nc = sek::rs_cells_per_side(L, rc, std::floor(L / rc) >= 64.0 ? 1 : 2);
   se_rs_plan *p = new (std::nothrow) se_rs_plan{};
   if (!p) return sek::report(SE_ERR_WORKSPACE, "host allocation failed");
   p->L = L;
@@ -398,9 +475,7 @@ se_status se_rs_plan_create(double L, double xi, double rc, int dtype, int n_max
   p->dtype = dtype;
   p->n_max = n_max;
   p->stream = static_cast<hipStream_t>(hip_stream);
-  p->nc = nc;
-  p->ncells = nc * nc * nc;
-  p->cs = L / nc;
+  p->nc_max = nc;
   {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -410,14 +485,15 @@ se_status se_rs_plan_create(double L, double xi, double rc, int dtype, int n_max
     p->cus = cus;
   }
   p->bin_blocks = (n_max + sek::kThreads - 1) / sek::kThreads;
+  const size_t cells_max = static_cast<size_t>(nc) * nc * nc;
   const size_t rs = dtype == SE_FP64 ? 8 : 4;
   struct { void **ptr; size_t n; } allocs[] = {
-      {reinterpret_cast<void **>(&p->counts), static_cast<size_t>(p->ncells) * sek::kCountStride * 4},
-      {reinterpret_cast<void **>(&p->offsets), static_cast<size_t>(p->ncells + 1) * 4},
+      {reinterpret_cast<void **>(&p->counts), cells_max * sek::kCountStride * 4},
+      {reinterpret_cast<void **>(&p->offsets), (cells_max + 1) * 4},
       {reinterpret_cast<void **>(&p->key), static_cast<size_t>(n_max) * 8},
       {reinterpret_cast<void **>(&p->meta), static_cast<size_t>(n_max) * 8},
       {&p->sorted, static_cast<size_t>(n_max) * 4 * rs},
-      {reinterpret_cast<void **>(&p->part), static_cast<size_t>(p->bin_blocks + p->ncells) * 8}};
+      {reinterpret_cast<void **>(&p->part), (p->bin_blocks + cells_max) * 8}};
   for (auto &a : allocs) {
     hipError_t e = hipMalloc(a.ptr, a.n);
     if (e != hipSuccess) {
@@ -427,7 +503,7 @@ se_status se_rs_plan_create(double L, double xi, double rc, int dtype, int n_max
       return sek::report(SE_ERR_WORKSPACE, "hipMalloc failed for the real-space workspace");
     }
   }
-  hipError_t e = hipMemset(p->counts, 0, static_cast<size_t>(p->ncells) * sek::kCountStride * 4);
+  hipError_t e = hipMemset(p->counts, 0, cells_max * sek::kCountStride * 4);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     sek::rs_free(*p);

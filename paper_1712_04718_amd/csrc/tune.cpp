@@ -12,6 +12,8 @@
 namespace sek {
 se_status report(se_status s, const char *msg);
 int tile_edge_of(const se_params &p);
+int rs_reach(double L, double rc, long long N);
+int rs_cells_per_side(double L, double rc, int reach);
 }
 
 namespace {
@@ -147,11 +149,13 @@ inline double rs_resident(int dtype, double ncells) {
 // tile edge fits (M, P) in this precision.
 bool predict(const se_cost_model &cm, int dtype, int N, double L, double rc, int M, int P,
              double *t_real, double *t_k) {
-  const double nc = std::fmin(std::floor(L / rc), 64.0);
+  const int reach = sek::rs_reach(L, rc, N);
+  const double nc = sek::rs_cells_per_side(L, rc, reach);
   const double ncells = nc * nc * nc;
   const double cs = L / nc;
   const double L3 = L * L * L;
-  const double ntest = 27.0 * cs * cs * cs * N / L3;
+  const double w = 2.0 * reach + 1.0;  // neighbour cells searched per side
+  const double ntest = w * w * w * cs * cs * cs * N / L3;
   const double res = rs_resident(dtype, ncells);
   const double q = std::ceil(ncells / res) * res / ncells;
   const double nbar = 4.0 / 3.0 * kPi * rc * rc * rc * N / L3;
@@ -246,13 +250,13 @@ se_status se_cost_model_mi355x(int dtype, se_cost_model *m) {
   // Non-negative least-squares fits of the model to se_kspace and se_rs_eval
   // times on an MI355X (calibrate.py of this package; 60 k-space and 15
   // real-space configurations per precision).
-  // Largest relative deviation of the fit: 26% (FP32), 25% (FP64).
+  // Largest relative deviation of the fit: 29% (FP32), 25% (FP64).
   if (dtype == SE_FP32) {
-    *m = se_cost_model{2.3131e-05, 0.0, 2.2287e-12, 8.2460e-09, 7.3007e-13,
-                       3.6741e-05, 8.8837e-11, 3.2826e-13, 2.2196e-12, 1.4448e-11, 0.0};
+    *m = se_cost_model{2.2373e-05, 8.7386e-12, 1.1716e-12, 7.8036e-09, 8.0868e-13,
+                       3.5440e-05, 9.9003e-11, 3.2998e-13, 2.2721e-12, 1.4419e-11, 0.0};
   } else if (dtype == SE_FP64) {
-    *m = se_cost_model{2.9351e-05, 0.0, 8.7526e-12, 1.6545e-08, 1.9063e-12,
-                       3.6234e-05, 1.4825e-10, 5.9724e-13, 6.8787e-12, 0.0, 1.9454e-12};
+    *m = se_cost_model{2.6680e-05, 0.0, 6.6887e-12, 1.7401e-08, 2.1290e-12,
+                       3.6009e-05, 1.4799e-10, 6.0737e-13, 6.8980e-12, 0.0, 1.9966e-12};
   } else {
     return bad("unknown dtype");
   }

@@ -44,27 +44,32 @@ def _parity(x, q, L, xi, rc, dtype):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_ions_1k(dtype):
-    """1000 ions in L = 10, xi = 1.5, rc = 2.4 (4 cells per side)."""
+    """1000 ions in L = 10, xi = 1.5, rc = 2.4 (4 cells per side searched 3
+    wide: 2 particles per cell of the finer list are too few for it)."""
     x, q, spec = cached_system("ions_1k")
     _parity(x, q, spec.L, spec.xi, 2.4, dtype)
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_water_L40(dtype):
-    """6411-atom water, xi = 0.3, rc = 9 (4 cells per side, molecules split
-    across cells)."""
+    """6411-atom water, xi = 0.3, rc = 9 (8 cells per side of edge 5 >= rc/2,
+    searched 5 wide; molecules split across cells)."""
     x, q, spec = cached_system("water_L40")
     _parity(x, q, spec.L, spec.xi, 9.0, dtype)
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_minimum_cells_and_crowded_cell(dtype):
-    """Three cells per side (rc = L/3: every cell is everyone's neighbour)
-    and 700 particles in one cell (more than a work-group holds at once)."""
+@pytest.mark.parametrize("crowd", [700, 2000])
+def test_minimum_cells_and_crowded_cell(crowd, dtype):
+    """rc = L/3, the fewest cells each list allows, with `crowd` particles in
+    one cell (more than a work-group takes at once) and 200 spread out:
+    900 particles use three cells per side searched 3 wide (every cell is
+    everyone's neighbour), 2200 (10 per cell of the finer list) six cells
+    per side searched 5 wide."""
     rng = np.random.default_rng(3)
     L = 12.0
-    x = np.concatenate([rng.random((700, 3)) * 1.5 + 2.0, rng.random((200, 3)) * L])
-    q = rng.standard_normal(900)
+    x = np.concatenate([rng.random((crowd, 3)) * 1.5 + 2.0, rng.random((200, 3)) * L])
+    q = rng.standard_normal(crowd + 200)
     _parity(x, q, L, 0.8, L / 3, dtype)
 
 

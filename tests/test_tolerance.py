@@ -187,6 +187,32 @@ def test_library_choice_matches_oracle_on_paper_model(T, kind, eps):
     assert ch["eta"] <= 0.5
 
 
+def _cell_list(N, L, rc):
+    """The library's real-space cell list for N particles: (searched cells
+    per side, cells per side).  Cells of edge >= rc searched 3 wide, or of
+    edge >= rc/2 searched 5 wide where those hold >= 10 particles on average
+    (>= 5 when the coarse list has fewer than 1024 cells); 64 per side at
+    most."""
+    nc1 = math.floor(L / rc)
+    if nc1 >= 64:
+        return 3, 64
+    nc2 = min(math.floor(2 * L / rc), 64)
+    occ = N / nc2 ** 3
+    return (5, nc2) if occ >= 10 or (occ >= 5 and nc1 ** 3 < 1024) else (3, nc1)
+
+
+def test_cell_list_rule_cases():
+    # water at rc = 10: 12.5 particles per fine cell; 10^6 ions in L = 220:
+    # 11.7; 20k particles at rc = 8 in L = 58.5: 7.3 with 343 coarse cells;
+    # rc = 4 there: 0.8 per fine cell
+    assert _cell_list(100_200, 100.0, 10.0) == (5, 20)
+    assert _cell_list(1_000_000, 220.0, 10.0) == (5, 44)
+    assert _cell_list(20_000, 58.48, 8.0) == (5, 14)
+    assert _cell_list(20_000, 58.48, 4.0) == (3, 14)
+    assert _cell_list(100_000, 100.0, 8.0) == (3, 12)
+    assert _cell_list(10 ** 6, 700.0, 10.0) == (3, 64)
+
+
 def test_library_choice_with_gpu_terms(T):
     """Fixed, per-atom and per-tested-pair terms: the choice is the argmin of
     the model written out here over the same cutoffs."""
@@ -210,8 +236,8 @@ def test_library_choice_with_gpu_terms(T):
                   and P * L * L * xi * xi / (0.95 ** 2 * math.pi * m * m) <= 0.5), None)
         if M is None:
             continue
-        nc = min(math.floor(L / rc), 64)
-        ntest = 27 * (L / nc) ** 3 * N / L ** 3
+        w, nc = _cell_list(N, L, rc)
+        ntest = w ** 3 * (L / nc) ** 3 * N / L ** 3
         res = 1280 if nc ** 3 > 1024 else 1024  # FP32 pair work-groups resident at once
         q = math.ceil(nc ** 3 / res) * res / nc ** 3
         t = (model["real_fixed"] + model["real_atom"] * N + model["real_cell"] * nc ** 3
@@ -227,12 +253,13 @@ def test_library_choice_with_gpu_terms(T):
 def test_library_cost_terms(T):
     """Each term of se_cost_predict alone, at water-like sizes: M = 96, P = 8
     in FP32 uses 12^3 tiles of edge 12 (blocks of 19^3 points); rc = 10 in
-    L = 100 gives 10^3 cells of edge 10."""
+    L = 100 gives 20^3 cells of edge 5 searched 5 wide (12.5 particles per
+    cell), in 7 rounds of 1280 work-groups."""
     N, L, rc, M, P = 100_200, 100.0, 10.0, 96, 8
     names = [n for n, _ in __import__("paper_1712_04718_amd._lib", fromlist=["x"]).SeCostModel._fields_]
     want = {"real_fixed": (1, 0), "real_atom": (N, 0),
             "real_pair": (N * 4 / 3 * math.pi * rc ** 3 * N / L ** 3, 0),
-            "real_cell": (1000, 0), "real_test": (N * 27 * 1000 * N / L ** 3 * 1024 / 1000, 0),
+            "real_cell": (8000, 0), "real_test": (N * 125 * 125 * N / L ** 3 * 7 * 1280 / 8000, 0),
             "k_fixed": (0, 1), "k_atom": (0, N), "k_window": (0, N * 512),
             "k_block": (0, 512 * 19 ** 3), "k_grid": (0, M ** 3),
             "k_fft": (0, M ** 3 / 2 * math.log(M ** 3 / 2))}
@@ -246,16 +273,17 @@ def test_library_cost_terms(T):
 @pytest.mark.parametrize("dtype,resident", [("f32", 1280), ("f64", 512)])
 def test_library_real_space_rounds(T, dtype, resident):
     """The work-group rounds factor of the tested-pairs term above 1024
-    cells (L = 220, rc = 10: 22^3 cells): FP32 holds 1280 pair work-groups at
-    once (five per CU with the smaller stage), FP64 512."""
+    cells (L = 220, rc = 10, 10^6 particles: 44^3 cells of edge 5, searched 5
+    wide): FP32 holds 1280 pair work-groups at once (five per CU with the
+    smaller stage), FP64 512."""
     N, L, rc = 1_000_000, 220.0, 10.0
     names = [n for n, _ in __import__("paper_1712_04718_amd._lib", fromlist=["x"]).SeCostModel._fields_]
     unit = {k: 0.0 for k in names}
     unit["real_test"] = 1.0
     tr, _ = T.predict(unit, dtype, N, L, rc, 192, 8)
-    cells = 22 ** 3
+    cells = 44 ** 3
     q = math.ceil(cells / resident) * resident / cells
-    assert tr == pytest.approx(N * 27 * (L / 22) ** 3 * N / L ** 3 * q, rel=1e-12)
+    assert tr == pytest.approx(N * 125 * (L / 44) ** 3 * N / L ** 3 * q, rel=1e-12)
 
 
 def test_library_argument_errors(T):
