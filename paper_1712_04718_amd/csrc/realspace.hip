@@ -161,6 +161,8 @@ __global__ void __launch_bounds__(kRsThreads)
 k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ meta,
            const int *__restrict__ offsets, int nc, R cs, R xi, R rc2, R *__restrict__ phi,
            R *__restrict__ F, double *__restrict__ epart) {
+  // a batch of tests appends at most kBatch entries after a flush check that
+  // left at most QN - kBatch, so qn never exceeds QN
   static_assert(QN >= kBatch, "a batch of tests must fit the queue");
   constexpr int W = 2 * RCH + 1, NB = W * W * W;  // neighbour cells, home at NB / 2
   static_assert(NB <= 128, "the prefix sum takes two neighbour cells per lane of one wave");
@@ -259,9 +261,12 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
       int qn = 0;
       auto flush = [&]() {
         for (int m0 = 0; __any(m0 < qn); m0 += kBatch) {
+          // rows past the queue (QN need not be a multiple of kBatch) are
+          // not read; such entries are beyond qn <= QN and masked below
           int idx[kBatch];
 #pragma unroll
-          for (int u = 0; u < kBatch; ++u) idx[u] = queue[(m0 + u) * kRsThreads + tid];
+          for (int u = 0; u < kBatch; ++u)
+            idx[u] = m0 + u < QN ? queue[(m0 + u) * kRsThreads + tid] : 0;
           Staged<R> c[kBatch];
 #pragma unroll
           for (int u = 0; u < kBatch; ++u) c[u] = stage[min(static_cast<unsigned>(idx[u]),

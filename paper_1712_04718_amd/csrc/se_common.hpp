@@ -50,9 +50,6 @@ __device__ inline int xcd_local(int b, int G) {
   return b < q * kXcds ? (b % kXcds) * q + b / kXcds : b;
 }
 
-// v mod M for v in [-M, 3M), branch-free.  Every grid index of a staged tile
-// block lies in [-(S-1), M + T + S - 3], inside that range whenever S <= M and
-// T + S - 3 < 2M (the plan checks both).
 // Anchor of a coordinate u in grid units: floor(u) reduced mod M into
 // [0, M), and the offset u - floor(u).  A non-finite u (or one beyond the
 // integer range) takes anchor 0 while its offset stays NaN, so the outputs
@@ -68,6 +65,9 @@ __device__ inline int anchor_mod(double u, int M, double *frac) {
   return static_cast<int>(i < 0 ? i + M : i);
 }
 
+// v mod M for v in [-M, 3M), branch-free.  Every grid index of a staged tile
+// block lies in [-(S-1), M + T + S - 3], inside that range whenever S <= M and
+// T + S - 3 < 2M (the plan checks both).
 __device__ inline int wrap_near(int v, int M) {
   v = v < 0 ? v + M : v;
   v = v >= M ? v - M : v;

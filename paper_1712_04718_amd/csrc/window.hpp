@@ -56,11 +56,13 @@ inline WindowConsts window_consts(double cg, double beta, double dcoef) {
 
 // All S factors of one axis (and optionally their derivatives).
 //
-// FP32 evaluates every Gaussian factor directly with an accurate expf: a
-// recurrence started from the tail factors (which carry the largest
-// argument-rounding error) would pass that relative error on to the large
-// central factors.  FP64 uses the fast Gaussian gridding recurrence, whose
-// accumulated rounding stays near 1e-15.
+// FP32 writes each Gaussian factor around the anchor point as A B^k C_k
+// (three exponentials per axis, products built outward from the largest
+// factor, so rounding grows only towards the small tail factors): the
+// recurrence of eqs. (4.10)-(4.11) started at the stencil end would pass the
+// relative rounding of its first, smallest factor on to the large central
+// ones.  FP64 uses that recurrence, whose accumulated rounding stays near
+// 1e-15.
 template <typename R, int WIN, int S, bool DERIV>
 __device__ inline void window_axis(R d, const WindowConsts &wc, R (&g)[S], R (&dg)[S]) {
   if constexpr (WIN == kGauss) {
