@@ -158,22 +158,27 @@ def runtime_estimate(model: dict, N: int, L: float, rc: float, M: int, P: int):
 
 
 def choose(kind: str, eps: float, N: int, Q: float, L: float, rcs, grid_sizes, model: dict,
-           P_min: int = 4, P_max: int = 16, c: float = 0.95, eta_max: float = 1.0):
+           P_min: int = 4, P_max: int = 16, c: float = 0.95, eta_max: float = 1.0,
+           P_fixed: int | None = None):
     """For each cutoff rc in ``rcs``: xi from eq. 2.3, k_inf from eq. 2.4,
     M the smallest of ``grid_sizes`` with M >= 2 k_inf (section 5.3 takes
     M = 2 k_inf) and eta = P L^2 xi^2/(c^2 pi M^2) below 1 (section 4) and
     at most eta_max, P from section 5 (raised to P_min, cutoff skipped above
-    P_max);
+    P_max), or ``P_fixed`` at every cutoff (section 7's experiment takes P
+    from its relative error target, independent of xi);
     keep the cutoff with the least t_real + t_fourier (section 7).  Returns a
     dict, or None when no cutoff is feasible (M or P out of range)."""
     best = None
     for rc in rcs:
         xi = xi_for(kind, eps, Q, L, rc)
         kinf = kinf_for(kind, eps, Q, L, xi)
-        P = se_support_for(kind, eps, Q, L, xi, c)
-        if P > P_max:
-            continue
-        P = max(P, P_min)
+        if P_fixed is not None:
+            P = int(P_fixed)
+        else:
+            P = se_support_for(kind, eps, Q, L, xi, c)
+            if P > P_max:
+                continue
+            P = max(P, P_min)
         M = None
         for m in sorted(grid_sizes):
             eta = P * L ** 2 * xi ** 2 / (c * c * math.pi * m * m)

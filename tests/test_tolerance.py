@@ -122,6 +122,72 @@ def test_choice_is_cheapest_feasible_by_exhaustive_search():
         assert best <= t * 1.05  # the xi grid lands next to the selection's xi
 
 
+def _section7_optimum(model=None):
+    """Optima of the section 7 selection for the two printed cases: the
+    support P from the relative form of the remark closing section 5.3,
+    fixed over xi as in the experiment (P = 10 at 1e-5, P = 20 at 1e-12), the
+    absolute tolerance the one eq. 2.1c assigns to the printed (xi, rc)."""
+    rcs = np.linspace(0.3, 1.5, 1201)
+    sizes = list(range(8, 1025, 2))
+    out = []
+    for xi_p, rc_p, rel in ((6.75, 0.60, 1e-5), (6.31, 0.90, 1e-12)):
+        eps = O.real_error("force", Q81, L81, xi_p, rc_p)
+        P = O.se_support_for_relative(rel)
+        out.append(O.choose("force", eps, N81, Q81, L81, rcs, sizes,
+                            model or O.PAPER_CPU_MODEL, P_fixed=P))
+    return out
+
+
+def _near_printed(ch, xi_p, rc_p):
+    return abs(ch["rc"] - rc_p) <= 0.08 and abs(ch["xi"] / xi_p - 1) <= 0.10
+
+
+def test_runtime_model_reproduces_section7_optima(monkeypatch):
+    """Section 7 prints the cheapest Ewald parameter for 81,000 uniform unit
+    charges in L = 9.3222: xi ~ 6.75 (rc = 0.60) at a relative force error of
+    1e-5 with P in {8, 10}, M in 50..250, and xi ~ 6.31 (rc = 0.90) at 1e-12
+    with P in {20, 22}, M in 100..280.  The model (c_real nbar N,
+    c_fft (M^3/2) ln(M^3/2) + c_sp-ga N P^3 + c_solve M^3, constants of the
+    text) and the argmin over a fine rc grid must land within 0.08 of the
+    printed rc and 10% of the printed xi, with M inside the printed range.
+    Only the real-space side of the printed pair enters (through eq. 2.1c),
+    so where the optimum falls is the model's doing: a tenfold c_real, a
+    dropped 4 pi/3 in the neighbour count, M^2 for M^3, or c_real and c_fft
+    swapped each move it outside those bounds (checked below).  With P fixed
+    over xi the N P^3 term is a constant and does not place the optimum."""
+    first, second = _section7_optimum()
+    assert _near_printed(first, 6.75, 0.60) and 50 <= first["M"] <= 250, first
+    assert _near_printed(second, 6.31, 0.90) and 100 <= second["M"] <= 280, second
+    assert abs(second["xi"] / first["xi"] - 1) < 0.10  # weak dependence on the tolerance
+
+    base = O.runtime_estimate
+
+    def m_squared(model, N, L, rc, M, P):
+        tr, _ = base(model, N, L, rc, M, P)
+        M2 = float(M) ** 2
+        return tr, (model["c_fft"] * M2 / 2 * math.log(M2 / 2) + model["c_sg"] * N * P ** 3
+                    + model["c_solve"] * M2)
+
+    def swapped(model, N, L, rc, M, P):
+        m = dict(model, c_real=model["c_fft"], c_fft=model["c_real"])
+        return base(m, N, L, rc, M, P)
+
+    mistakes = [
+        ("tenfold c_real", dict(O.PAPER_CPU_MODEL, c_real=10 * O.PAPER_CPU_MODEL["c_real"]),
+         None, None),
+        ("no 4 pi / 3", None, "neighbours", lambda N, L, rc: rc ** 3 / L ** 3 * N),
+        ("M^2 for M^3", None, "runtime_estimate", m_squared),
+        ("c_real <-> c_fft", None, "runtime_estimate", swapped),
+    ]
+    for name, model, attr, fn in mistakes:
+        with monkeypatch.context() as mp:
+            if attr:
+                mp.setattr(O, attr, fn)
+            bad = _section7_optimum(model)
+        assert not (_near_printed(bad[0], 6.75, 0.60) and _near_printed(bad[1], 6.31, 0.90)), \
+            (name, bad)
+
+
 # ------------------------------------------------ library host functions
 
 @pytest.fixture(scope="module")
