@@ -11,8 +11,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import (DEV, TOL, as_oracle_inputs, cached_system, errors, gpu_kspace,
-                      oracle_kspace, to_dev)
+from gpu_util import (DEV, TOL, array_errors, as_oracle_inputs, cached_system, errors,
+                      gpu_kspace, oracle_kspace, to_dev)
 from oracle import se_oracle as O
 from paper_1712_04718_amd import SEPlan
 
@@ -152,8 +152,9 @@ def test_add_self_flag(dtype):
     xi = 1.2
     assert abs((E1 - E0) - (-xi / math.sqrt(math.pi) * np.sum(qo * qo))) < TOL[dtype] * abs(E0)
     assert np.max(np.abs((p1 - p0) - (-2 * xi / math.sqrt(math.pi) * qo))) < TOL[dtype] * 10 * np.abs(p0).max()
-    # float atomics make repeated evaluations agree to rounding, not bitwise
-    assert O.rel_rms(F1, F0) < TOL[dtype]
+    # the self terms leave the forces alone: the spread accumulates in fixed
+    # point, so the two evaluations agree bit for bit
+    assert np.array_equal(F1, F0)
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -212,12 +213,13 @@ def _sampled_parity(name, P, dtype, window="gaussian", M=None, nsample=2000, tol
         phio, Fo = O.se_gather(xo[idx], qo[idx], L, M, P, xi, eta, Phi)
     else:
         phio, Fo = O.spme_gather(xo[idx], qo[idx], L, M, P, Phi)
-    eE = abs(E.item() - Eo) / abs(Eo)
-    ephi = O.rel_rms(phi.double().cpu().numpy()[idx], phio)
-    eF = O.rel_rms(F.double().cpu().numpy()[idx], Fo)
-    print(f"[full] {name} P={P} {dtype}: E {eE:.2e} phi {ephi:.2e} F {eF:.2e}", flush=True)
+    e = (abs(E.item() - Eo) / abs(Eo),) + \
+        array_errors(phi.double().cpu().numpy()[idx], phio) + \
+        array_errors(F.double().cpu().numpy()[idx], Fo)
+    print(f"[full] {name} P={P} {dtype}: E {e[0]:.2e} phi {e[1]:.2e} F {e[3]:.2e} "
+          f"(max/10: phi {e[2]:.2e} F {e[4]:.2e})", flush=True)
     lim = tol if tol is not None else TOL[dtype]
-    assert max(eE, ephi, eF) < lim, (eE, ephi, eF)
+    assert max(e) < lim, e
 
 
 @pytest.mark.parametrize("P,dtype", [(6, torch.float32), (10, torch.float32),
@@ -275,8 +277,8 @@ def test_potential_and_field_at_points(window, M, P, dtype):
     else:
         _, _, _, _, Phi = O.spme_kspace(xo, qo, L, xi, M, P, return_grids=True)
         ref_phi, ref_field = O.spme_gather(xto, ones, L, M, P, Phi)
-    e = (O.rel_rms(phi_t.double().cpu().numpy(), ref_phi),
-         O.rel_rms(field_t.double().cpu().numpy(), ref_field))
+    e = (array_errors(phi_t.double().cpu().numpy(), ref_phi)
+         + array_errors(field_t.double().cpu().numpy(), ref_field))
     assert max(e) < TOL[dtype], e
     # on top of a source: phi of that source and its force per unit charge
     pt, ft = phi_t[600:].double(), field_t[600:].double()
@@ -318,14 +320,14 @@ def test_wide_support_reaches_the_exact_sum():
     torch.cuda.synchronize()
     Ed, phid, Fd = O.ewald_kspace_direct(x, q, L, xi)
     assert abs(E.item() - Ed) / abs(Ed) < 1e-12
-    assert O.rel_rms(phi.cpu().numpy(), phid) < 1e-12
-    assert O.rel_rms(F.cpu().numpy(), Fd) < 1e-12
+    assert max(array_errors(phi.cpu().numpy(), phid)) < 1e-12
+    assert max(array_errors(F.cpu().numpy(), Fd)) < 1e-12
     np.testing.assert_array_equal(gx.cpu().numpy(), -F.cpu().numpy())
     np.testing.assert_array_equal(gq.cpu().numpy(), phi.cpu().numpy())
     xa = np.concatenate([x, xt.cpu().numpy()])
     qa = np.concatenate([q, np.zeros(len(xt))])
     _, phia, _ = O.ewald_kspace_direct(xa, qa, L, xi)
-    assert O.rel_rms(phi_t.cpu().numpy(), phia[len(x):]) < 1e-12
+    assert max(array_errors(phi_t.cpu().numpy(), phia[len(x):])) < 1e-12
     assert field_t.shape == (40, 3)
     plan.close()
 
@@ -373,7 +375,7 @@ def test_ik_forces(window, M, P, dtype):
     else:
         grids = O.field_grids(O.spme_spread(xo, qo, L, M, P), O.spme_influence(L, xi, M, P), L)
         Ft = [O.spme_gather(xto, ones, L, M, P, g, want_F=False)[0] for g in grids]
-    assert O.rel_rms(field_t.double().cpu().numpy(), np.stack(Ft, axis=1)) < TOL[dtype]
+    assert max(array_errors(field_t.double().cpu().numpy(), np.stack(Ft, axis=1))) < TOL[dtype]
     for p in (plan, ref):
         p.close()
 

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import DEV, TOL, as_oracle_inputs, cached_system, to_dev
+from gpu_util import DEV, TOL, array_errors, as_oracle_inputs, cached_system, to_dev
 from oracle import se_oracle as O
 from paper_1712_04718_amd import RealSpacePlan, SEPlan, _lib, ewald_total
 from workloads import nacl_lattice
@@ -30,8 +30,10 @@ def _rs(x, q, L, xi, rc, dtype):
 
 
 def _errors(gpu, ref):
+    """|E - E*| / |E*|, then the rms and largest-element errors of phi and F
+    (gpu_util.array_errors), all to be held below the tolerance."""
     (E, phi, F), (Eo, phio, Fo) = gpu, ref
-    return (abs(E - Eo) / abs(Eo), O.rel_rms(phi, phio), O.rel_rms(F, Fo))
+    return (abs(E - Eo) / abs(Eo),) + array_errors(phi, phio) + array_errors(F, Fo)
 
 
 def _parity(x, q, L, xi, rc, dtype):
@@ -99,10 +101,37 @@ def test_full_water_L100_sampled():
     xo, qo = as_oracle_inputs(xt, qt)
     idx = np.random.default_rng(8).choice(len(q), size=2000, replace=False)
     phio, Fo = O.ewald_real_targets(xo, qo, spec.L, spec.xi, 10.0, idx)
-    ephi = O.rel_rms(phi.double().cpu().numpy()[idx], phio)
-    eF = O.rel_rms(F.double().cpu().numpy()[idx], Fo)
-    print(f"[realspace] water_L100: phi {ephi:.2e} F {eF:.2e}", flush=True)
-    assert max(ephi, eF) < TOL[torch.float32]
+    e = array_errors(phi.double().cpu().numpy()[idx], phio) + \
+        array_errors(F.double().cpu().numpy()[idx], Fo)
+    print(f"[realspace] water_L100: phi {e[0]:.2e} F {e[2]:.2e} (max/10: {e[1]:.2e}, "
+          f"{e[3]:.2e})", flush=True)
+    assert max(e) < TOL[torch.float32], e
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_sparse_cells_sampled(dtype):
+    """20,000 random ions in L = 60 with rc = 5: 1728 cells of edge 5 hold
+    about 12 each, the half-edge cells fewer than 2, so the 27-cell list is
+    taken, and with more cells than four work-groups per CU the FP32 pair
+    kernel runs its 512-particle stage with the 12-entry queue; 2000 sampled
+    atoms against the oracle's direct sum."""
+    L, xi, rc, N = 60.0, 0.5, 5.0, 20000
+    rng = np.random.default_rng(77)
+    x = rng.random((N, 3)) * L
+    q = np.where(np.arange(N) < N // 2, 1.0, -1.0)
+    print(f"[realspace] sparse cells N={N} L={L} rc={rc} {dtype}", flush=True)
+    xt, qt = to_dev(x, q, dtype)
+    plan = RealSpacePlan(L, xi, rc, dtype=dtype, n_max=N)
+    E, phi, F = plan.eval(xt, qt)
+    torch.cuda.synchronize()
+    xo, qo = as_oracle_inputs(xt, qt)
+    idx = np.random.default_rng(9).choice(N, size=2000, replace=False)
+    phio, Fo = O.ewald_real_targets(xo, qo, L, xi, rc, idx)
+    e = array_errors(phi.double().cpu().numpy()[idx], phio) + \
+        array_errors(F.double().cpu().numpy()[idx], Fo)
+    print(f"[realspace] sparse cells {dtype}: {e}", flush=True)
+    assert max(e) < TOL[dtype], e
     plan.close()
 
 
