@@ -58,12 +58,15 @@ typedef enum {
     SE_ERR_GRID = 2,         /* M not even, not 2^a 3^b 5^c, out of range, or M < P */
     SE_ERR_ETA = 3,          /* Gaussian shape eta outside (0,1) (section 4) */
     SE_ERR_UNSUPPORTED = 4,  /* window/precision/P combination not built */
-    SE_ERR_WORKSPACE = 5,    /* device allocation failed */
+    SE_ERR_WORKSPACE = 5,    /* device allocation failed, or a workspace too
+                                small or misaligned for the plan           */
     SE_ERR_HIP = 6,          /* HIP runtime error while enqueueing; the
                                 plan's workspace is then in an undefined
                                 state (a launch may be missing from the
                                 sequence): destroy the plan               */
-    SE_ERR_STATE = 7         /* se_gather/se_backward before any se_forward */
+    SE_ERR_STATE = 7         /* se_gather/se_backward before any se_forward,
+                                or se_forward on a plan awaiting its
+                                caller-owned workspace                     */
 } se_status;
 
 typedef enum { SE_WINDOW_GAUSSIAN = 0, SE_WINDOW_BSPLINE = 1 } se_window;
@@ -84,6 +87,12 @@ typedef enum { SE_FP32 = 0, SE_FP64 = 1 } se_dtype;
                                 comparison: se_backward keeps the analytic
                                 adjoint (the exact gradient of E).  Tiled
                                 supports only (SE P <= 16, SPME).            */
+#define SE_FLAG_CALLER_WORKSPACE 8u  /* se_plan_create allocates no device
+                                memory: the caller attaches a workspace of
+                                se_plan_workspace_size bytes with
+                                se_plan_set_workspace before the first
+                                se_forward (e.g. memory of a framework's
+                                caching allocator)                           */
 
 /* Kernel stages of one evaluation (se_plan_stage_times), in launch order
    apart from the fused plane passes at the end. */
@@ -143,9 +152,29 @@ se_status se_plan_workspace_size(const se_params *prm, int n_max, size_t *bytes)
 
 /* Create a plan on the current HIP device for up to n_max particles.
  * hip_stream is a hipStream_t (NULL = the default stream).  The plan owns
- * its device workspace (allocated here, freed by se_plan_destroy). */
+ * its device workspace (one allocation of se_plan_workspace_size bytes,
+ * made here and freed by se_plan_destroy), unless prm->flags holds
+ * SE_FLAG_CALLER_WORKSPACE: then nothing is allocated on the device (and,
+ * without SE_FLAG_TIMING, no HIP call is made) until se_plan_set_workspace. */
 se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream,
                          se_plan **out);
+
+/* Attach a caller-owned workspace to a plan created with
+ * SE_FLAG_CALLER_WORKSPACE.  The workspace holds everything an evaluation
+ * keeps on the device: the grid (G, then the scaled grid Phi of eq. 4.9 that
+ * se_gather and se_backward read), the spread tile blocks, the half
+ * spectrum, the sorted particles and the plan's tables.  dev_ptr: device memory on the plan's device, at least
+ * se_plan_workspace_size(prm, n_max) bytes, 256-byte aligned; the caller
+ * keeps it allocated and does not touch it while the plan's enqueued work
+ * may use it, and frees it after se_plan_destroy (or after attaching another
+ * workspace and waiting for the plan's stream).  The tables are written and
+ * the tile counters cleared by a kernel enqueued on the plan's stream; the
+ * stored grid of an earlier forward pass is not carried over
+ * (se_gather/se_backward then return SE_ERR_STATE until the next se_forward).
+ * SE_ERR_WORKSPACE if bytes is too small or dev_ptr misaligned, SE_ERR_ARG
+ * for a NULL argument or a plan that owns its workspace; checked on the host
+ * before any HIP call. */
+se_status se_plan_set_workspace(se_plan *plan, void *dev_ptr, size_t bytes);
 
 /* Change the stream later calls enqueue on. */
 se_status se_plan_set_stream(se_plan *plan, void *hip_stream);

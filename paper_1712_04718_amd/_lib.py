@@ -19,6 +19,7 @@ SE_FP64 = 1
 SE_FLAG_ADD_SELF = 1
 SE_FLAG_TIMING = 2
 SE_FLAG_IK_FORCE = 4
+SE_FLAG_CALLER_WORKSPACE = 8
 STAGES = ("bin_count", "bin_scan", "bin_scatter", "spread", "fold", "fft_x", "fft_y",
           "fft_z_scale", "ifft_y", "ifft_x", "gather", "fft_xy", "ifft_yx")
 
@@ -30,7 +31,8 @@ STATUS_NAMES = {
 # Every entry point the header declares.
 EXPORTS = (
     "se_status_string", "se_last_error", "se_params_check", "se_plan_workspace_size",
-    "se_plan_create", "se_plan_set_stream", "se_plan_eta", "se_plan_destroy",
+    "se_plan_create", "se_plan_set_workspace", "se_plan_set_stream", "se_plan_eta",
+    "se_plan_destroy",
     "se_forward", "se_gather", "se_kspace", "se_backward", "se_plan_stage_times",
     "se_plan_reserve_targets", "se_eval_targets",
     "se_rs_plan_create", "se_rs_plan_set_stream", "se_rs_eval", "se_rs_plan_destroy",
@@ -103,6 +105,8 @@ def load() -> ctypes.CDLL:
     lib.se_plan_workspace_size.argtypes = [pp, i, ctypes.POINTER(ctypes.c_size_t)]
     lib.se_plan_create.restype = i
     lib.se_plan_create.argtypes = [pp, i, vp, ctypes.POINTER(vp)]
+    lib.se_plan_set_workspace.restype = i
+    lib.se_plan_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
     lib.se_plan_set_stream.restype = i
     lib.se_plan_set_stream.argtypes = [vp, vp]
     lib.se_plan_eta.restype = i

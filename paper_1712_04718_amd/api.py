@@ -40,7 +40,13 @@ class SEPlan:
     ``gather`` and ``backward``."""
 
     def __init__(self, M, P, L, xi, window="gaussian", dtype=torch.float32, c=0.95,
-                 n_max=1 << 20, add_self=False, device=None, timing=False, ik_force=False):
+                 n_max=1 << 20, add_self=False, device=None, timing=False, ik_force=False,
+                 workspace=None):
+        """``workspace``: None (the library allocates the plan's device
+        memory), True (a uint8 tensor from PyTorch's caching allocator of
+        the size the library asks for), or such a tensor supplied by the
+        caller (contiguous, on the plan's device, large enough, 256-byte
+        aligned); the plan keeps a reference to it."""
         if not torch.cuda.is_available():
             raise RuntimeError("SEPlan needs a GPU (no HIP device visible)")
         if dtype not in _DTYPES:
@@ -56,13 +62,26 @@ class SEPlan:
         self.dtype = dtype
         self.n_max = int(n_max)
         flags = ((_lib.SE_FLAG_ADD_SELF if add_self else 0) | (_lib.SE_FLAG_TIMING if timing else 0)
-                 | (_lib.SE_FLAG_IK_FORCE if ik_force else 0))
+                 | (_lib.SE_FLAG_IK_FORCE if ik_force else 0)
+                 | (_lib.SE_FLAG_CALLER_WORKSPACE if workspace is not None else 0))
         self.params = _lib.make_params(M, P, L, xi, c, _WINDOWS[window], _DTYPES[dtype], flags)
         self._plan = ctypes.c_void_p(None)
+        self.workspace = None
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
             _lib.check(self.lib.se_plan_create(ctypes.byref(self.params), self.n_max,
                                                ctypes.c_void_p(stream), ctypes.byref(self._plan)))
+            if workspace is not None:
+                st, nbytes = _lib.workspace_size(self.params, self.n_max)
+                _lib.check(st)
+                if workspace is True:
+                    workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+                if (not isinstance(workspace, torch.Tensor) or workspace.device != self.device
+                        or not workspace.is_contiguous()):
+                    raise ValueError(f"workspace must be a contiguous tensor on {self.device}")
+                _lib.check(self.lib.se_plan_set_workspace(
+                    self._plan, _ptr(workspace), workspace.numel() * workspace.element_size()))
+                self.workspace = workspace
         eta = ctypes.c_double(0.0)
         _lib.check(self.lib.se_plan_eta(self._plan, ctypes.byref(eta)))
         self.eta = eta.value

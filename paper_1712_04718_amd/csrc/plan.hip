@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -85,26 +86,6 @@ sek::FftPlan radix_plan(int M) {
   return pl;
 }
 
-// Cardinal B-spline M_p at integer arguments 1..p-1 (section 6.1 recursion).
-double bspline_at(int p, double u) {
-  if (p == 2) return (u >= 0.0 && u <= 2.0) ? 1.0 - std::fabs(u - 1.0) : 0.0;
-  return u / (p - 1) * bspline_at(p - 1, u) + (p - u) / (p - 1) * bspline_at(p - 1, u - 1.0);
-}
-
-// |b(n)|^2 of the SPME influence function: 1 / |sum_{l=0}^{p-2} M_p(l+1) e^{2 pi i n l/M}|^2,
-// 0 where the sum vanishes (odd p at n = M/2).
-double spme_bmod2(int p, int M, int n) {
-  double re = 0.0, im = 0.0;
-  for (int l = 0; l <= p - 2; ++l) {
-    const double v = bspline_at(p, l + 1.0);
-    const double ang = 2.0 * M_PI * static_cast<double>(n) * l / M;
-    re += v * std::cos(ang);
-    im += v * std::sin(ang);
-  }
-  const double d = re * re + im * im;
-  return d > 1e-10 ? 1.0 / d : 0.0;
-}
-
 se_status check_params(const se_params *prm, double *eta_out) {
   if (!prm) return fail(SE_ERR_ARG, "params is NULL");
   const se_params &p = *prm;
@@ -114,7 +95,7 @@ se_status check_params(const se_params *prm, double *eta_out) {
   if (p.window != SE_WINDOW_GAUSSIAN && p.window != SE_WINDOW_BSPLINE)
     return fail(SE_ERR_ARG, "unknown window %d", p.window);
   if (p.dtype != SE_FP32 && p.dtype != SE_FP64) return fail(SE_ERR_ARG, "unknown dtype %d", p.dtype);
-  if (p.flags & ~(SE_FLAG_ADD_SELF | SE_FLAG_TIMING | SE_FLAG_IK_FORCE))
+  if (p.flags & ~(SE_FLAG_ADD_SELF | SE_FLAG_TIMING | SE_FLAG_IK_FORCE | SE_FLAG_CALLER_WORKSPACE))
     return fail(SE_ERR_ARG, "unknown flags 0x%x", p.flags);
   if (p.M < 8 || p.M > 512 || (p.M & 1) || !only_235(p.M))
     return fail(SE_ERR_GRID, "M=%d must be even, 8..512 and of the form 2^a 3^b 5^c", p.M);
@@ -143,36 +124,40 @@ struct Sizes {
       part, tw, f, k2, total;
 };
 
-// (tile * 64 + index) pairs of the tile blocks covering each grid index along
-// one axis: block of tile t starts at grid index t*T + OFF and spans TS points
-// (periodically wrapped).
-std::vector<std::vector<int>> cover_lists(int M, int T, int S, int off) {
-  const int ntx = (M + T - 1) / T, TS = T + S - 1;
-  std::vector<std::vector<int>> lists(M);
-  for (int t = 0; t < ntx; ++t)
-    for (int l = 0; l < TS; ++l) {
-      int g = (t * T + off + l) % M;
-      if (g < 0) g += M;
-      lists[g].push_back(t * 64 + l);
-    }
-  return lists;
-}
-
 int stencil_offset(const se_params &p) {
   return p.window == SE_WINDOW_GAUSSIAN ? -(p.P / 2 - 1) : -(p.P - 1);
 }
 
+// Tile blocks covering grid index g along one axis: block of tile t starts at
+// grid index t*T + off and spans TS = T + S - 1 points (periodically wrapped).
+// Counted without allocating (the no-allocation entry point sizes its
+// scratch with it).
+int cover_count_at(int M, int T, int S, int off, int g) {
+  const int ntx = (M + T - 1) / T, TS = T + S - 1;
+  int n = 0;
+  for (int t = 0; t < ntx; ++t)
+    for (int l = 0; l < TS; ++l) {
+      int v = (t * T + off + l) % M;
+      if (v < 0) v += M;
+      n += v == g;
+    }
+  return n;
+}
+
 size_t max_cover(const se_params &p, int T) {
-  size_t kc = 0;
-  for (const auto &l : cover_lists(p.M, T, p.P, stencil_offset(p))) kc = std::max(kc, l.size());
-  return kc;
+  if (T <= 0) return 0;
+  int kc = 0;
+  for (int g = 0; g < p.M; ++g)
+    kc = std::max(kc, cover_count_at(p.M, T, p.P, stencil_offset(p), g));
+  return static_cast<size_t>(kc);
 }
 
 Sizes sizes_of(const se_params &p, int n_max, int ntiles, int bin_blocks, int zblocks, int T) {
   const size_t rs = real_size(p), M = p.M, K = M / 2 + 1;
   const size_t n = n_max > 0 ? n_max : 1;
   Sizes s{};
-  // every buffer gets at least 256 bytes (the untiled path has no tiles)
+  // every buffer gets at least 256 bytes (the untiled path has no tiles) and
+  // starts on a 256-byte boundary of the workspace
   auto al = [](size_t b) { return ((b ? b : 1) + 255) & ~static_cast<size_t>(255); };
   const size_t TS = T + p.P - 1;
   s.grid = al(M * M * M * rs);
@@ -198,6 +183,127 @@ Sizes sizes_of(const se_params &p, int n_max, int ntiles, int bin_blocks, int zb
   return s;
 }
 
+// The plan's buffers as consecutive pieces of one workspace (base 256-byte
+// aligned), in the order of Sizes.
+sek::DeviceBuffers carve(const Sizes &s, void *base) {
+  sek::DeviceBuffers b{};
+  char *c = static_cast<char *>(base);
+  auto take = [&c](size_t n) {
+    void *r = c;
+    c += n;
+    return r;
+  };
+  b.grid = take(s.grid);
+  b.ghost = take(s.ghost);
+  b.cover = static_cast<int *>(take(s.cover));
+  b.cover_count = static_cast<int *>(take(s.cover_count));
+  b.spec = take(s.spec);
+  b.spec2 = take(s.spec2);
+  b.field = take(s.field);
+  b.sorted = take(s.sorted);
+  b.meta = static_cast<int2 *>(take(s.meta));
+  b.key = static_cast<int2 *>(take(s.key));
+  b.counts = static_cast<int *>(take(s.counts));
+  b.offsets = static_cast<int *>(take(s.offsets));
+  b.part = static_cast<double *>(take(s.part));
+  b.twiddle = take(s.tw);
+  b.axis_f = take(s.f);
+  b.axis_k2 = take(s.k2);
+  b.bytes = s.total;
+  return b;
+}
+
+// Cardinal B-spline M_p at the integers 0..p (section 6.1 recursion from
+// M_2(u) = 1 - |u - 1| on [0, 2]): v[u] = M_p(u).
+__device__ void bspline_integers(int p, double (&v)[sek::kMaxSplineOrder + 1]) {
+  for (int u = 0; u <= sek::kMaxSplineOrder; ++u) v[u] = (u == 1) ? 1.0 : 0.0;
+  for (int n = 3; n <= p; ++n)
+    for (int u = n; u >= 1; --u)
+      v[u] = (u * v[u] + (n - u) * v[u - 1]) / (n - 1);
+}
+
+// Tables of a plan, computed on the device (so that a plan and the
+// no-allocation entry point hold the same bits), and the tile counters
+// cleared:
+//   twiddle[j] = e^{-2 pi i j/M};
+//   axis_k2[n] = k_n^2, k_n = 2 pi n~/L with n~ = n or n - M (Nyquist |n~| = M/2);
+//   axis_f[n] = e^{-(1-eta) k_n^2/4xi^2} (SE, eq. 4.6) or
+//               |b(n)|^2 e^{-k_n^2/4xi^2} (SPME, eq. 6.2) with
+//               |b(n)|^2 = 1/|sum_{l=0}^{p-2} M_p(l+1) e^{2 pi i n l/M}|^2,
+//               0 where the sum vanishes (odd p at n = M/2);
+//   cover[g][k], cover_count[g]: the tile blocks covering grid index g
+//               along one axis (tile * 64 + index inside the block).
+template <typename R>
+__global__ void __launch_bounds__(sek::kThreads)
+k_plan_tables(int M, double L, double xi, double eta, int bspline, int P, int T, int off,
+              int KC, R *__restrict__ twiddle, double *__restrict__ axis_f,
+              double *__restrict__ axis_k2, int *__restrict__ cover, int *__restrict__ cover_count,
+              int *__restrict__ counts, int ncounts) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncounts; i += stride) counts[i] = 0;
+  for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < M; n += stride) {
+    const double ang = 2.0 * M_PI * n / M;
+    twiddle[2 * n] = static_cast<R>(cos(ang));
+    twiddle[2 * n + 1] = static_cast<R>(-sin(ang));
+    const int ns = (2 * n <= M) ? n : n - M;
+    const double k = 2.0 * M_PI * ns / L;
+    const double k2 = k * k;
+    axis_k2[n] = k2;
+    if (!bspline) {
+      axis_f[n] = exp(-(1.0 - eta) * k2 / (4.0 * xi * xi));
+    } else {
+      double v[sek::kMaxSplineOrder + 1];
+      bspline_integers(P, v);
+      double re = 0.0, im = 0.0;
+      for (int l = 0; l <= P - 2; ++l) {
+        const double a = 2.0 * M_PI * static_cast<double>(n) * l / M;
+        re += v[l + 1] * cos(a);
+        im += v[l + 1] * sin(a);
+      }
+      const double d = re * re + im * im;
+      axis_f[n] = (d > 1e-10 ? 1.0 / d : 0.0) * exp(-k2 / (4.0 * xi * xi));
+    }
+    if (T > 0) {
+      const int ntx = (M + T - 1) / T, TS = T + P - 1;
+      int c = 0;
+      for (int t = 0; t < ntx; ++t)
+        for (int l = 0; l < TS; ++l) {
+          int g = (t * T + off + l) % M;
+          if (g < 0) g += M;
+          if (g == n && c < KC) cover[n * KC + c++] = t * 64 + l;
+        }
+      for (int k = c; k < KC; ++k) cover[n * KC + k] = 0;
+      cover_count[n] = c;
+    }
+  }
+}
+
+// Point the plan at a workspace of sz.total bytes and enqueue its tables
+// and the clearing of its tile counters on the plan's stream.
+hipError_t attach(se_plan &pl, const Sizes &sz, void *base) {
+  pl.buf = carve(sz, base);
+  const int M = pl.prm.M;
+  const int KC = pl.T > 0 ? static_cast<int>(max_cover(pl.prm, pl.T)) : 0;
+  if (pl.T > 0)
+    pl.fold = sek::FoldTables{pl.buf.cover, pl.buf.cover_count, KC, pl.T + pl.prm.P - 1, pl.ntx};
+  const int ncounts = pl.ntiles * sek::kCountStride;
+  const int blocks = std::max(1, std::min(256, (std::max(M, ncounts) + sek::kThreads - 1) / sek::kThreads));
+  const bool bs = pl.prm.window == SE_WINDOW_BSPLINE;
+  if (pl.prm.dtype == SE_FP64)
+    k_plan_tables<double><<<blocks, sek::kThreads, 0, pl.stream>>>(
+        M, pl.prm.L, pl.prm.xi, pl.eta, bs, pl.prm.P, pl.T, stencil_offset(pl.prm), KC,
+        static_cast<double *>(pl.buf.twiddle), static_cast<double *>(pl.buf.axis_f),
+        static_cast<double *>(pl.buf.axis_k2), pl.buf.cover, pl.buf.cover_count, pl.buf.counts,
+        ncounts);
+  else
+    k_plan_tables<float><<<blocks, sek::kThreads, 0, pl.stream>>>(
+        M, pl.prm.L, pl.prm.xi, pl.eta, bs, pl.prm.P, pl.T, stencil_offset(pl.prm), KC,
+        static_cast<float *>(pl.buf.twiddle), static_cast<double *>(pl.buf.axis_f),
+        static_cast<double *>(pl.buf.axis_k2), pl.buf.cover, pl.buf.cover_count, pl.buf.counts,
+        ncounts);
+  return hipGetLastError();
+}
+
 void derive(se_plan &pl) {
   const se_params &p = pl.prm;
   pl.h = p.L / p.M;
@@ -221,18 +327,10 @@ void derive(se_plan &pl) {
   const int bz = 1 << pl.fft_lgb[sek::kPassZ];
   pl.zfft_blocks = (p.M * (p.M / 2 + 1) + bz - 1) / bz;
   pl.fft = radix_plan(p.M);
-}
-
-template <typename R>
-hipError_t upload_twiddles(se_plan &pl) {
-  const int M = pl.prm.M;
-  std::vector<R> tw(2 * M);
-  for (int j = 0; j < M; ++j) {
-    const double ang = 2.0 * M_PI * j / M;
-    tw[2 * j] = static_cast<R>(std::cos(ang));
-    tw[2 * j + 1] = static_cast<R>(-std::sin(ang));
+  if (pl.T > 0) {
+    const int TS = pl.T + p.P - 1;
+    pl.fold_by_tiles = (p.M % pl.T == 0) && (TS <= p.M) && (pl.ntx >= (TS + pl.T - 1) / pl.T);
   }
-  return hipMemcpy(pl.buf.twiddle, tw.data(), sizeof(R) * 2 * M, hipMemcpyHostToDevice);
 }
 
 void destroy_events(se_plan &pl) {
@@ -256,13 +354,55 @@ void free_targets(se_plan &pl) {
 void free_all(se_plan &pl) {
   destroy_events(pl);
   free_targets(pl);
-  void *ptrs[] = {pl.buf.grid, pl.buf.ghost, pl.buf.cover, pl.buf.cover_count, pl.buf.spec,
-                  pl.buf.spec2, pl.buf.field,
-                  pl.buf.sorted, pl.buf.meta, pl.buf.key, pl.buf.counts, pl.buf.offsets,
-                  pl.buf.part, pl.buf.twiddle, pl.buf.axis_f, pl.buf.axis_k2};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+  if (pl.owned) (void)hipFree(pl.owned);
+  pl.owned = nullptr;
   pl.buf = sek::DeviceBuffers{};
+}
+
+// Plans the caller creates without a workspace refuse to enqueue until one
+// is attached.
+se_status need_workspace(const se_plan *plan) {
+  if (plan->buf.grid) return SE_OK;
+  return fail(SE_ERR_STATE, "no workspace attached (plan created with SE_FLAG_CALLER_WORKSPACE: "
+                            "call se_plan_set_workspace first)");
+}
+
+se_status forward_impl(se_plan &plan, int N, const void *x, const void *q, double *E_dev) {
+  if (N < 0 || N > plan.n_max) return fail(SE_ERR_ARG, "N=%d outside [0, n_max=%d]", N, plan.n_max);
+  if (N > 0 && (!x || !q)) return fail(SE_ERR_ARG, "x or q is NULL");
+  if (!E_dev) return fail(SE_ERR_ARG, "E_dev is NULL");
+  hipError_t e;
+  if (plan.direct) {
+    if ((e = sek::launch_direct_forward(plan, N, x, q)) != hipSuccess)
+      return hip_fail(e, "spreading (untiled)");
+  } else {
+    if ((e = sek::launch_bin(plan, N, x, q)) != hipSuccess) return hip_fail(e, "binning");
+    if ((e = sek::launch_spread(plan)) != hipSuccess) return hip_fail(e, "spreading");
+  }
+  if ((e = sek::launch_fft_forward_scale_inverse(plan, E_dev)) != hipSuccess)
+    return hip_fail(e, "FFT/scaling");
+  plan.last_N = N;
+  return SE_OK;
+}
+
+se_status gather_impl(se_plan &plan, void *phi, void *F) {
+  if (plan.last_N < 0) return fail(SE_ERR_STATE, "se_gather before se_forward");
+  hipError_t e = sek::launch_gather(plan, plan.last_N, nullptr, sek::kGatherPotentialForce, phi, F);
+  return e == hipSuccess ? SE_OK : hip_fail(e, "gathering");
+}
+
+// A plan refused because no tile edge fits, or because the staged tile
+// blocks would wrap the grid more than the kernels handle: staged blocks
+// index the grid in [-(P-1), M + T + P - 3], wrapped without division (holds
+// for every M >= 8 with P <= M at the tile edges chosen).
+se_status check_tiling(const se_plan &pl) {
+  if (pl.T == 0 && !pl.direct)
+    return fail(SE_ERR_UNSUPPORTED, "support %d in this precision needs more LDS than a CU has",
+                pl.prm.P);
+  if (!pl.direct && pl.T + pl.prm.P - 3 >= 2 * pl.prm.M)
+    return fail(SE_ERR_GRID, "tile edge %d with support %d needs a larger grid than M=%d", pl.T,
+                pl.prm.P, pl.prm.M);
+  return SE_OK;
 }
 
 }  // namespace
@@ -287,9 +427,9 @@ const char *se_status_string(se_status s) {
     case SE_ERR_GRID: return "SE_ERR_GRID: unsupported grid size";
     case SE_ERR_ETA: return "SE_ERR_ETA: Gaussian shape eta outside (0,1)";
     case SE_ERR_UNSUPPORTED: return "SE_ERR_UNSUPPORTED: window/support/precision not built";
-    case SE_ERR_WORKSPACE: return "SE_ERR_WORKSPACE: device allocation failed";
+    case SE_ERR_WORKSPACE: return "SE_ERR_WORKSPACE: device allocation failed or workspace too small";
     case SE_ERR_HIP: return "SE_ERR_HIP: HIP runtime error";
-    case SE_ERR_STATE: return "SE_ERR_STATE: no forward pass on this plan yet";
+    case SE_ERR_STATE: return "SE_ERR_STATE: no forward pass (or no workspace) on this plan yet";
   }
   return "unknown se_status";
 }
@@ -307,10 +447,8 @@ se_status se_plan_workspace_size(const se_params *prm, int n_max, size_t *bytes)
   tmp.prm = *prm;
   tmp.n_max = n_max;
   derive(tmp);
-  if (tmp.T == 0 && !tmp.direct)
-    return fail(SE_ERR_UNSUPPORTED, "support %d in this precision needs more LDS than a CU has",
-                prm->P);
-  *bytes = sizes_of(*prm, n_max, tmp.ntiles, tmp.bin_blocks, tmp.zfft_blocks, tmp.T).total;
+  if ((s = check_tiling(tmp)) != SE_OK) return s;
+  *bytes = sizes_of(tmp.prm, n_max, tmp.ntiles, tmp.bin_blocks, tmp.zfft_blocks, tmp.T).total;
   return SE_OK;
 }
 
@@ -329,91 +467,34 @@ se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_p
   pl->stream = static_cast<hipStream_t>(hip_stream);
   pl->last_N = -1;
   derive(*pl);
-  if (pl->T == 0 && !pl->direct) {
+  if ((s = check_tiling(*pl)) != SE_OK) {
     delete pl;
-    return fail(SE_ERR_UNSUPPORTED, "support %d in this precision needs more LDS than a CU has",
-                prm->P);
+    return s;
   }
-  // staged tile blocks index the grid in [-(P-1), M + T + P - 3]; the kernels
-  // wrap that range without division (holds for every M >= 8 with P <= M)
-  if (!pl->direct && pl->T + pl->prm.P - 3 >= 2 * pl->prm.M) {
-    const int T = pl->T;
-    delete pl;
-    return fail(SE_ERR_GRID, "tile edge %d with support %d needs a larger grid than M=%d", T,
-                prm->P, prm->M);
-  }
-  hipError_t e = hipGetDevice(&pl->device);
-  if (e != hipSuccess) {
-    delete pl;
-    return hip_fail(e, "hipGetDevice");
-  }
-
-  const Sizes sz = sizes_of(pl->prm, n_max, pl->ntiles, pl->bin_blocks, pl->zfft_blocks, pl->T);
-  struct { void **p; size_t n; } allocs[] = {
-      {&pl->buf.grid, sz.grid},     {&pl->buf.ghost, sz.ghost},
-      {reinterpret_cast<void **>(&pl->buf.cover), sz.cover},
-      {reinterpret_cast<void **>(&pl->buf.cover_count), sz.cover_count},
-      {&pl->buf.spec, sz.spec},     {&pl->buf.spec2, sz.spec2},
-      {&pl->buf.field, sz.field},
-      {&pl->buf.sorted, sz.sorted}, {reinterpret_cast<void **>(&pl->buf.meta), sz.meta},
-      {reinterpret_cast<void **>(&pl->buf.key), sz.key},
-      {reinterpret_cast<void **>(&pl->buf.counts), sz.counts},
-      {reinterpret_cast<void **>(&pl->buf.offsets), sz.offsets},
-      {reinterpret_cast<void **>(&pl->buf.part), sz.part},
-      {&pl->buf.twiddle, sz.tw},    {&pl->buf.axis_f, sz.f},
-      {&pl->buf.axis_k2, sz.k2}};
-  for (auto &a : allocs) {
-    e = hipMalloc(a.p, a.n);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      free_all(*pl);
-      delete pl;
-      return fail(SE_ERR_WORKSPACE, "hipMalloc(%zu) failed: %s", a.n, hipGetErrorString(e));
-    }
-  }
-  pl->buf.bytes = sz.total;
-
-  // tables (double precision on the host)
-  const int M = pl->prm.M;
-  std::vector<double> f(M), k2(M);
-  for (int n = 0; n < M; ++n) {
-    const int ns = (2 * n <= M) ? n : n - M;  // signed frequency; Nyquist gets |n| = M/2
-    const double k = 2.0 * M_PI * ns / pl->prm.L;
-    k2[n] = k * k;
-    const double xi2 = pl->prm.xi * pl->prm.xi;
-    if (pl->prm.window == SE_WINDOW_GAUSSIAN)
-      f[n] = std::exp(-(1.0 - pl->eta) * k2[n] / (4.0 * xi2));             // eq. (4.6)
-    else
-      f[n] = spme_bmod2(pl->prm.P, M, n) * std::exp(-k2[n] / (4.0 * xi2));  // eq. (6.2)
-  }
-  e = hipMemcpy(pl->buf.axis_f, f.data(), sizeof(double) * M, hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(pl->buf.axis_k2, k2.data(), sizeof(double) * M, hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = pl->prm.dtype == SE_FP64 ? upload_twiddles<double>(*pl) : upload_twiddles<float>(*pl);
   pl->timing = (pl->prm.flags & SE_FLAG_TIMING) != 0;
+  const bool caller_ws = (pl->prm.flags & SE_FLAG_CALLER_WORKSPACE) != 0;
+  if (caller_ws && !pl->timing) {  // nothing on the device until a workspace is attached
+    *out = pl;
+    return SE_OK;
+  }
+  pl->touched = true;
+  hipError_t e = hipSuccess;
   for (int i = 0; i < SE_NUM_STAGES && pl->timing && e == hipSuccess; ++i)
     for (int k = 0; k < sek::kTimingSlots && e == hipSuccess; ++k) {
       e = hipEventCreate(&pl->timers[i].begin[k]);
       if (e == hipSuccess) e = hipEventCreate(&pl->timers[i].end[k]);
     }
-  if (e == hipSuccess) e = hipMemset(pl->buf.counts, 0, sz.counts);
-  if (e == hipSuccess && !pl->direct) {
-    const auto lists = cover_lists(M, pl->T, pl->prm.P, stencil_offset(pl->prm));
-    size_t kc = 0;
-    for (const auto &l : lists) kc = std::max(kc, l.size());
-    std::vector<int> cover(M * kc, 0), count(M);
-    for (int g = 0; g < M; ++g) {
-      count[g] = static_cast<int>(lists[g].size());
-      for (size_t k = 0; k < lists[g].size(); ++k) cover[g * kc + k] = lists[g][k];
+  if (e == hipSuccess && !caller_ws) {
+    const Sizes sz = sizes_of(pl->prm, n_max, pl->ntiles, pl->bin_blocks, pl->zfft_blocks, pl->T);
+    e = hipMalloc(&pl->owned, sz.total);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      pl->owned = nullptr;
+      free_all(*pl);
+      delete pl;
+      return fail(SE_ERR_WORKSPACE, "hipMalloc(%zu) failed: %s", sz.total, hipGetErrorString(e));
     }
-    e = hipMemcpy(pl->buf.cover, cover.data(), sizeof(int) * cover.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-      e = hipMemcpy(pl->buf.cover_count, count.data(), sizeof(int) * M, hipMemcpyHostToDevice);
-    pl->fold = sek::FoldTables{pl->buf.cover, pl->buf.cover_count, static_cast<int>(kc),
-                               pl->T + pl->prm.P - 1, pl->ntx};
-    const int TS = pl->T + pl->prm.P - 1;
-    pl->fold_by_tiles = (M % pl->T == 0) && (TS <= M) && (pl->ntx >= (TS + pl->T - 1) / pl->T);
+    e = attach(*pl, sz, pl->owned);
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -422,6 +503,28 @@ se_status se_plan_create(const se_params *prm, int n_max, void *hip_stream, se_p
     return hip_fail(e, "plan set-up");
   }
   *out = pl;
+  return SE_OK;
+}
+
+se_status se_plan_set_workspace(se_plan *plan, void *dev_ptr, size_t bytes) {
+  if (!plan) return fail(SE_ERR_ARG, "plan is NULL");
+  if (!(plan->prm.flags & SE_FLAG_CALLER_WORKSPACE))
+    return fail(SE_ERR_ARG, "the plan owns its workspace (created without SE_FLAG_CALLER_WORKSPACE)");
+  if (!dev_ptr) return fail(SE_ERR_ARG, "dev_ptr is NULL");
+  const Sizes sz =
+      sizes_of(plan->prm, plan->n_max, plan->ntiles, plan->bin_blocks, plan->zfft_blocks, plan->T);
+  if (bytes < sz.total)
+    return fail(SE_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu the plan needs",
+                bytes, sz.total);
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0)
+    return fail(SE_ERR_WORKSPACE, "workspace address is not a multiple of 256 bytes");
+  plan->touched = true;
+  hipError_t e = attach(*plan, sz, dev_ptr);
+  if (e != hipSuccess) {
+    plan->buf = sek::DeviceBuffers{};
+    return hip_fail(e, "workspace tables");
+  }
+  plan->last_N = -1;  // the stored grid was in the previous workspace
   return SE_OK;
 }
 
@@ -456,7 +559,7 @@ se_status se_plan_stage_times(se_plan *plan, double *ms, int n) {
 
 se_status se_plan_destroy(se_plan *plan) {
   if (!plan) return SE_OK;
-  hipError_t e = hipStreamSynchronize(plan->stream);
+  hipError_t e = plan->touched ? hipStreamSynchronize(plan->stream) : hipSuccess;
   free_all(*plan);
   delete plan;
   return e == hipSuccess ? SE_OK : hip_fail(e, "hipStreamSynchronize");
@@ -464,28 +567,13 @@ se_status se_plan_destroy(se_plan *plan) {
 
 se_status se_forward(se_plan *plan, int N, const void *x, const void *q, double *E_dev) {
   if (!plan) return fail(SE_ERR_ARG, "plan is NULL");
-  if (N < 0 || N > plan->n_max) return fail(SE_ERR_ARG, "N=%d outside [0, n_max=%d]", N, plan->n_max);
-  if (N > 0 && (!x || !q)) return fail(SE_ERR_ARG, "x or q is NULL");
-  if (!E_dev) return fail(SE_ERR_ARG, "E_dev is NULL");
-  hipError_t e;
-  if (plan->direct) {
-    if ((e = sek::launch_direct_forward(*plan, N, x, q)) != hipSuccess)
-      return hip_fail(e, "spreading (untiled)");
-  } else {
-    if ((e = sek::launch_bin(*plan, N, x, q)) != hipSuccess) return hip_fail(e, "binning");
-    if ((e = sek::launch_spread(*plan)) != hipSuccess) return hip_fail(e, "spreading");
-  }
-  if ((e = sek::launch_fft_forward_scale_inverse(*plan, E_dev)) != hipSuccess)
-    return hip_fail(e, "FFT/scaling");
-  plan->last_N = N;
-  return SE_OK;
+  se_status s = need_workspace(plan);
+  return s != SE_OK ? s : forward_impl(*plan, N, x, q, E_dev);
 }
 
 se_status se_gather(se_plan *plan, void *phi, void *F) {
   if (!plan) return fail(SE_ERR_ARG, "plan is NULL");
-  if (plan->last_N < 0) return fail(SE_ERR_STATE, "se_gather before se_forward");
-  hipError_t e = sek::launch_gather(*plan, plan->last_N, nullptr, sek::kGatherPotentialForce, phi, F);
-  return e == hipSuccess ? SE_OK : hip_fail(e, "gathering");
+  return gather_impl(*plan, phi, F);
 }
 
 se_status se_kspace(se_plan *plan, int N, const void *x, const void *q, double *E_dev, void *phi,
@@ -498,6 +586,7 @@ se_status se_kspace(se_plan *plan, int N, const void *x, const void *q, double *
 se_status se_plan_reserve_targets(se_plan *plan, int nt_max) {
   if (!plan) return fail(SE_ERR_ARG, "plan is NULL");
   if (nt_max < 1) return fail(SE_ERR_ARG, "nt_max must be >= 1 (got %d)", nt_max);
+  plan->touched = true;
   hipError_t e = hipStreamSynchronize(plan->stream);  // earlier target work may use the old buffers
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   free_targets(*plan);

@@ -182,7 +182,9 @@ struct se_plan {
   int fft_threads; // threads per FFT work-group
 
   sek::FftPlan fft;
-  sek::DeviceBuffers buf;
+  sek::DeviceBuffers buf;  // pieces of one workspace (owned, or the caller's)
+  void *owned = nullptr;   // the workspace the plan allocated itself, if any
+  bool touched = false;    // device work or memory exists (destroy synchronises)
   sek::TargetBuffers tgt;
   sek::FoldTables fold;
   bool fold_by_tiles;  // tiles partition the grid: tile-structured fold
@@ -266,6 +268,7 @@ constexpr int kGatherAdjoint = 1;         // out_pot = gE phi, out_vec = -gE F
 constexpr int kGatherTargets = 2;         // points of plan.tgt: phi (no self term), -grad phi
 constexpr int kGatherIkX = 3;             // +d (d = 0, 1, 2): out_vec[3 n + d] = scale q * (field d at n)
 
+constexpr int kMaxSplineOrder = 8;  // largest SPME order built
 constexpr int kThreads = 256;      // work-group size of the binning, fold and FFT kernels
 constexpr int kTileThreads = 512;  // work-group size of the tile spread and gather kernels
 

@@ -51,7 +51,7 @@ def test_eta_matches_paper_formula():
 
 @pytest.mark.parametrize("kw,status", [
     (dict(L=0.0), 1), (dict(L=-1.0), 1), (dict(xi=0.0), 1), (dict(L=float("nan")), 1),
-    (dict(window=7), 1), (dict(dtype=3), 1), (dict(flags=8), 1),
+    (dict(window=7), 1), (dict(dtype=3), 1), (dict(flags=32), 1),
     (dict(M=33), 2), (dict(M=14), 2), (dict(M=6), 2), (dict(M=1024), 2), (dict(M=10, P=12), 2),
     (dict(P=7), 4), (dict(P=18), 4), (dict(P=2), 4), (dict(P=26, dtype=1), 4),
     (dict(P=19, dtype=1), 4), (dict(P=18, dtype=1, xi=0.2, flags=4), 4), (dict(flags=16), 1),
@@ -109,3 +109,33 @@ def test_target_entry_points_reject_bad_arguments():
     lib = _lib.load()
     assert _lib.STATUS_NAMES[lib.se_plan_reserve_targets(None, 10)] == "SE_ERR_ARG"
     assert _lib.STATUS_NAMES[lib.se_eval_targets(None, 1, None, None, None)] == "SE_ERR_ARG"
+
+
+def test_caller_workspace_host_checks():
+    """A plan created with SE_FLAG_CALLER_WORKSPACE allocates nothing and
+    makes no HIP call until a workspace is attached, so its checks run here:
+    a buffer smaller than se_plan_workspace_size or not 256-byte aligned is
+    SE_ERR_WORKSPACE, a NULL one SE_ERR_ARG, and forward/gather before any
+    workspace SE_ERR_STATE (all before any HIP call)."""
+    import ctypes
+    lib = _lib.load()
+    prm = _lib.make_params(32, 8, 10.0, 1.5, flags=_lib.SE_FLAG_CALLER_WORKSPACE)
+    st, need = _lib.workspace_size(prm, 1000)
+    assert st == 0 and need > 0
+    plan = ctypes.c_void_p(None)
+    assert lib.se_plan_create(ctypes.byref(prm), 1000, None, ctypes.byref(plan)) == 0
+    try:
+        name = lambda st: _lib.STATUS_NAMES[st]  # noqa: E731
+        fake = ctypes.c_void_p(1 << 40)  # never dereferenced: every check fails first
+        assert name(lib.se_plan_set_workspace(plan, fake, need - 1)) == "SE_ERR_WORKSPACE"
+        assert "smaller" in lib.se_last_error().decode()
+        assert name(lib.se_plan_set_workspace(plan, ctypes.c_void_p((1 << 40) + 64), need)) \
+            == "SE_ERR_WORKSPACE"
+        assert "256" in lib.se_last_error().decode()
+        assert name(lib.se_plan_set_workspace(plan, None, need)) == "SE_ERR_ARG"
+        assert name(lib.se_plan_set_workspace(None, fake, need)) == "SE_ERR_ARG"
+        E = ctypes.c_void_p(1 << 40)
+        assert name(lib.se_forward(plan, 0, None, None, E)) == "SE_ERR_STATE"
+        assert name(lib.se_gather(plan, None, None)) == "SE_ERR_STATE"
+    finally:
+        assert lib.se_plan_destroy(plan) == 0
