@@ -329,16 +329,16 @@ hipError_t bin_impl(const BinJob &j, se_plan *timing) {
       if (static_cast<long long>(N) >= 256LL * j.ncells) {
         constexpr int PPT = 8;
         parts = (N + kThreads * PPT - 1) / (kThreads * PPT);
-        k_bin_count_lds<R, PPT><<<parts, kThreads, lds, j.stream>>>(
+        launch_on(timing, k_bin_count_lds<R, PPT>, parts, kThreads, lds, j.stream, 
             N, xr, qr, j.h, j.M, j.T, j.ntx, j.ncells, j.counts, j.key, j.qsq_part);
       } else {
         parts = blocks1;
-        k_bin_count_lds<R, 1><<<parts, kThreads, lds, j.stream>>>(
+        launch_on(timing, k_bin_count_lds<R, 1>, parts, kThreads, lds, j.stream, 
             N, xr, qr, j.h, j.M, j.T, j.ntx, j.ncells, j.counts, j.key, j.qsq_part);
       }
     } else {
       parts = blocks1;
-      k_bin_count_run<R><<<parts, kThreads, 0, j.stream>>>(
+      launch_on(timing, k_bin_count_run<R>, parts, kThreads, 0, j.stream, 
           N, xr, qr, j.h, j.M, j.T, j.ntx, j.counts, j.key, j.qsq_part);
     }
     e = hipGetLastError();
@@ -352,18 +352,18 @@ hipError_t bin_impl(const BinJob &j, se_plan *timing) {
   if (j.fused_scan && j.ncells <= kLdsTilesMax && scan_reads <= (1LL << 20)) {
     // the consumer of the tiles resets the counts
     if (timing) stage_begin(*timing, SE_STAGE_BIN_SCATTER);
-    k_bin_scatter_scan<R><<<max(blocks1, 1), kThreads, sizeof(int) * (j.ncells + 1), j.stream>>>(
+    launch_on(timing, k_bin_scatter_scan<R>, max(blocks1, 1), kThreads, sizeof(int) * (j.ncells + 1), j.stream, 
         N, xr, qr, j.h, j.M, j.T, j.key, j.counts, j.ncells, j.offsets,
         static_cast<SortedParticle<R> *>(j.sorted), j.meta);
     if (timing) stage_end(*timing, SE_STAGE_BIN_SCATTER);
     return hipGetLastError();
   }
   if (timing) stage_begin(*timing, SE_STAGE_BIN_SCAN);
-  k_bin_scan<<<1, kScanThreads, 0, j.stream>>>(j.counts, j.offsets, j.ncells);
+  launch_on(timing, k_bin_scan, 1, kScanThreads, 0, j.stream, j.counts, j.offsets, j.ncells);
   if (timing) stage_end(*timing, SE_STAGE_BIN_SCAN);
   if ((e = hipGetLastError()) != hipSuccess || N == 0) return e;
   if (timing) stage_begin(*timing, SE_STAGE_BIN_SCATTER);
-  k_bin_scatter<R><<<blocks1, kThreads, 0, j.stream>>>(
+  launch_on(timing, k_bin_scatter<R>, blocks1, kThreads, 0, j.stream, 
       N, xr, qr, j.h, j.M, j.T, j.key, j.offsets, static_cast<SortedParticle<R> *>(j.sorted),
       j.meta);
   if (timing) stage_end(*timing, SE_STAGE_BIN_SCATTER);

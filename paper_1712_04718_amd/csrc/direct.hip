@@ -158,8 +158,8 @@ template <int S>
 hipError_t direct_spread_S(se_plan &p, int N) {
   const WindowConsts wc = window_consts(p.cg, p.beta, 0.0);
   const long long threads = static_cast<long long>(N) * S;
-  k_direct_spread<S><<<static_cast<unsigned>((threads + kThreads - 1) / kThreads), kThreads, 0,
-                       p.stream>>>(N, static_cast<const SortedParticle<double> *>(p.buf.sorted),
+  launch_on(&p, k_direct_spread<S>, static_cast<unsigned>((threads + kThreads - 1) / kThreads), kThreads, 0,
+                       p.stream, N, static_cast<const SortedParticle<double> *>(p.buf.sorted),
                                    p.buf.meta, p.prm.M, wc, static_cast<double *>(p.buf.grid));
   return hipGetLastError();
 }
@@ -168,7 +168,7 @@ template <int S>
 hipError_t direct_gather_S(se_plan &p, int N, const void *pts, const int2 *meta,
                            const double *gscale, int mode, double self, void *pot, void *vec) {
   const WindowConsts wc = window_consts(p.cg, p.beta, 2.0 * p.a * p.h);
-  k_direct_gather<S><<<(N + kDirectWaves - 1) / kDirectWaves, 64 * kDirectWaves, 0, p.stream>>>(
+  launch_on(&p, k_direct_gather<S>, (N + kDirectWaves - 1) / kDirectWaves, 64 * kDirectWaves, 0, p.stream, 
       N, static_cast<const SortedParticle<double> *>(pts), meta,
       static_cast<const double *>(p.buf.grid), p.prm.M, wc, gscale, mode, self,
       static_cast<double *>(pot), static_cast<double *>(vec));
@@ -182,7 +182,7 @@ hipError_t launch_direct_prep(se_plan &p, int N, const void *x, const void *q, v
   const int blocks = (N + kThreads - 1) / kThreads;
   if (parts) *parts = blocks;
   if (N == 0) return hipSuccess;
-  k_direct_prep<double><<<blocks, kThreads, 0, p.stream>>>(
+  launch_on(&p, k_direct_prep<double>, blocks, kThreads, 0, p.stream, 
       N, static_cast<const double *>(x), static_cast<const double *>(q), p.h, p.prm.M,
       static_cast<SortedParticle<double> *>(pts), meta, qsq_part);
   return hipGetLastError();
@@ -194,8 +194,8 @@ hipError_t launch_direct_forward(se_plan &p, int N, const void *x, const void *q
   if (e != hipSuccess) return e;
   stage_begin(p, SE_STAGE_SPREAD);
   const long long ngrid = static_cast<long long>(p.prm.M) * p.prm.M * p.prm.M;
-  k_direct_zero<double><<<static_cast<unsigned>((ngrid + kThreads - 1) / kThreads), kThreads, 0,
-                          p.stream>>>(static_cast<double *>(p.buf.grid), ngrid);
+  launch_on(&p, k_direct_zero<double>, static_cast<unsigned>((ngrid + kThreads - 1) / kThreads), kThreads, 0,
+                          p.stream, static_cast<double *>(p.buf.grid), ngrid);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (N > 0) {
     switch (p.prm.P) {

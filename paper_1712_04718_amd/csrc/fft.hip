@@ -753,7 +753,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
   C *spec = static_cast<C *>(p.buf.spec);
   const C *tw = static_cast<const C *>(p.buf.twiddle);
   stage_begin(p, SE_STAGE_FFT_XY);
-  k_fft_xy_r2c<R, MC, NT, kPlaneSplitFwd><<<nfwd, NT, lds, p.stream>>>(static_cast<const R *>(p.buf.grid), spec, tw);
+  launch_on(&p, k_fft_xy_r2c<R, MC, NT, kPlaneSplitFwd>, nfwd, NT, lds, p.stream, static_cast<const R *>(p.buf.grid), spec, tw);
   stage_end(p, SE_STAGE_FFT_XY);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double tpl = 2.0 * M_PI / p.prm.L;
@@ -763,17 +763,17 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
     // which the potential's z pass then overwrites); not timed
     C *spec2 = static_cast<C *>(p.buf.spec2);
     for (int d = 0; d < 3; ++d) {
-      k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_z, p.stream>>>(
+      launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, p.fft_threads, lds_z, p.stream, 
           spec, spec2, p.fft, LZ, tw, static_cast<const double *>(p.buf.axis_f),
           static_cast<const double *>(p.buf.axis_k2), p.wscale, nullptr, d, tpl);
-      k_fft_yx_c2r<R, MC, NT, kPlaneSplitInv><<<ninv, NT, lds, p.stream>>>(
+      launch_on(&p, k_fft_yx_c2r<R, MC, NT, kPlaneSplitInv>, ninv, NT, lds, p.stream, 
           spec2, static_cast<R *>(p.buf.field) + static_cast<long long>(d) * MC * MC * MC, tw,
           none);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
   stage_begin(p, SE_STAGE_FFT_Z_SCALE);
-  k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_z, p.stream>>>(
+  launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, p.fft_threads, lds_z, p.stream, 
       spec, spec, p.fft, LZ, tw, static_cast<const double *>(p.buf.axis_f),
       static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks, -1, tpl);
   stage_end(p, SE_STAGE_FFT_Z_SCALE);
@@ -782,7 +782,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
   const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.part, p.bin_parts, self_coef,
                      E_dev};
   stage_begin(p, SE_STAGE_IFFT_YX);
-  k_fft_yx_c2r<R, MC, NT, kPlaneSplitInv><<<ninv, NT, lds, p.stream>>>(spec, static_cast<R *>(p.buf.grid), tw, eo);
+  launch_on(&p, k_fft_yx_c2r<R, MC, NT, kPlaneSplitInv>, ninv, NT, lds, p.stream, spec, static_cast<R *>(p.buf.grid), tw, eo);
   stage_end(p, SE_STAGE_IFFT_YX);
   return hipGetLastError();
 }
@@ -809,14 +809,14 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
   const int xblocks = (M * M + 2 * Bx - 1) / (2 * Bx);
   hipError_t e = hipSuccess;
   stage_begin(p, SE_STAGE_FFT_X);
-  k_fft_x_r2c<R, MC, LX><<<xblocks, p.fft_threads, lds_of(lx), p.stream>>>(
+  launch_on(&p, k_fft_x_r2c<R, MC, LX>, xblocks, p.fft_threads, lds_of(lx), p.stream, 
       static_cast<const R *>(p.buf.grid), spec, p.fft, lx, tw);
   stage_end(p, SE_STAGE_FFT_X);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const unsigned yg = static_cast<unsigned>((M * K + By - 1) / By);
   const EnergyOut none{nullptr, 0, nullptr, 0, 0.0, nullptr};
   stage_begin(p, SE_STAGE_FFT_Y);
-  k_fft_y<R, MC, LY, false><<<yg, p.fft_threads, lds_of(ly), p.stream>>>(spec, p.fft, ly, tw, none);
+  launch_on(&p, k_fft_y<R, MC, LY, false>, yg, p.fft_threads, lds_of(ly), p.stream, spec, p.fft, ly, tw, none);
   stage_end(p, SE_STAGE_FFT_Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double tpl = 2.0 * M_PI / p.prm.L;
@@ -825,19 +825,19 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
     // which the potential's z pass then overwrites); not timed
     C *spec2 = static_cast<C *>(p.buf.spec2);
     for (int d = 0; d < 3; ++d) {
-      k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_zof(lz), p.stream>>>(
+      launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, p.fft_threads, lds_zof(lz), p.stream, 
           spec, spec2, p.fft, lz, tw, static_cast<const double *>(p.buf.axis_f),
           static_cast<const double *>(p.buf.axis_k2), p.wscale, nullptr, d, tpl);
-      k_fft_y<R, MC, LY, true><<<yg, p.fft_threads, lds_of(ly), p.stream>>>(spec2, p.fft, ly, tw,
+      launch_on(&p, k_fft_y<R, MC, LY, true>, yg, p.fft_threads, lds_of(ly), p.stream, spec2, p.fft, ly, tw,
                                                                            none);
-      k_fft_x_c2r<R, MC, LX><<<xblocks, p.fft_threads, lds_of(lx), p.stream>>>(
+      launch_on(&p, k_fft_x_c2r<R, MC, LX>, xblocks, p.fft_threads, lds_of(lx), p.stream, 
           spec2, static_cast<R *>(p.buf.field) + static_cast<long long>(d) * M * M * M, p.fft, lx,
           tw);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
   stage_begin(p, SE_STAGE_FFT_Z_SCALE);
-  k_fft_z_scale<R, MC, LZ><<<p.zfft_blocks, p.fft_threads, lds_zof(lz), p.stream>>>(
+  launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, p.fft_threads, lds_zof(lz), p.stream, 
       spec, spec, p.fft, lz, tw, static_cast<const double *>(p.buf.axis_f),
       static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks, -1, tpl);
   stage_end(p, SE_STAGE_FFT_Z_SCALE);
@@ -846,11 +846,11 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
   const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.part, p.bin_parts, self_coef,
                      E_dev};
   stage_begin(p, SE_STAGE_IFFT_Y);
-  k_fft_y<R, MC, LY, true><<<yg, p.fft_threads, lds_of(ly), p.stream>>>(spec, p.fft, ly, tw, eo);
+  launch_on(&p, k_fft_y<R, MC, LY, true>, yg, p.fft_threads, lds_of(ly), p.stream, spec, p.fft, ly, tw, eo);
   stage_end(p, SE_STAGE_IFFT_Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   stage_begin(p, SE_STAGE_IFFT_X);
-  k_fft_x_c2r<R, MC, LX><<<xblocks, p.fft_threads, lds_of(lx), p.stream>>>(
+  launch_on(&p, k_fft_x_c2r<R, MC, LX>, xblocks, p.fft_threads, lds_of(lx), p.stream, 
       spec, static_cast<R *>(p.buf.grid), p.fft, lx, tw);
   stage_end(p, SE_STAGE_IFFT_X);
   return hipGetLastError();

@@ -7,16 +7,20 @@
 // grad_q = gE phi and grad_x = -gE F, with gE read from device memory.
 //
 // One work-group per tile: the (T+S-1)^3 block of the scaled grid Phi that
-// the tile's particles touch is staged in LDS, and the tile's particles are
-// taken in chunks of one per thread:
-//   phase A: each thread computes its particle's window factors (and, for
-//            B-splines, their derivatives) into LDS;
-//   phase B: lane (group, jx) owns the x-offset jx of one particle and sums
-//            over the S^2 (jy, jz) offsets; the S lanes of a particle are
-//            then combined (shuffle tree for S = 4, 8, 16; in LDS otherwise).
-// Per-lane sums over y are compensated (Kahan) for B-splines; for the
-// Gaussian the derivative sums are rearranged around the stencil centre (see
-// phase B) and the lane parts are combined by a pairwise tree.
+// the tile's particles touch is staged in LDS.  Lane (group, jx) of a wave's
+// 64/S particle groups owns the x-offset jx of one particle and sums over
+// the S^2 (jy, jz) offsets; the S lanes of a particle are then combined
+// (shuffle tree for S = 4, 8, 16; in LDS, compensated, otherwise).
+//   Gaussian window (k_gather_lane): the waves take the tile's particles in
+//     a strided loop with no block barrier; each lane evaluates its three
+//     factors (x, y, z at its own offset) and shares the y and z ones with
+//     its group through a per-wave LDS slot.
+//   B-spline window (k_gather): the particles are taken in chunks of one per
+//     thread; phase A computes each particle's factors and derivatives into
+//     LDS (the order-p recursion per axis), phase B sums as above, with the
+//     per-lane sums over y compensated (Kahan).
+// For the Gaussian the derivative sums are rearranged around the stencil
+// centre (see k_gather_lane).
 #include "se_common.hpp"
 #include "window.hpp"
 
@@ -315,12 +319,218 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
   }
 }
 
+// LDS of the Gaussian gather (k_gather_lane): the tile block, the lane
+// partials (supports that are not a power of two), per-wave factor slots
+// (64/S groups of 2S values each) and the offset tables.
+constexpr size_t gather_lane_lds(int real_size, int S, int T) {
+  const size_t TS = T + S - 1;
+  return real_size * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) +
+         ((S & (S - 1)) ? static_cast<size_t>(real_size) * kTileThreads * 4 : 0) +
+         static_cast<size_t>(real_size) * (kTileThreads / 64) * (64 / S) * 2 * S +
+         4 * (TS * TS + TS);
+}
+
+// Gaussian window.  The block of Phi is staged as in k_gather; then each
+// wave takes particle groups in a strided loop without block barriers: lane
+// (group, jx) evaluates three factors of its particle directly,
+// g = beta e^{-cg t^2} at t = jx + OFF - d along x, y and z, keeps its x
+// factor and shares the y and z ones with the group through the wave's LDS
+// slot, so each lane computes three exponentials per particle (instead of
+// one thread computing all 3S in a phase of its own between barriers).
+template <typename R, int S, int T>
+__global__ void __launch_bounds__(kTileThreads)
+k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ sorted,
+              const int2 *__restrict__ meta, const int *__restrict__ offsets, int M, int ntx,
+              WindowConsts wc, const double *__restrict__ gscale, int mode, R self_coef,
+              R *__restrict__ out_pot, R *__restrict__ out_vec) {
+  constexpr int TS = T + S - 1, TS3 = TS * TS * TS;
+  constexpr int GROUPS = 64 / S;
+  constexpr int OFF = Stencil<kGauss, S>::OFF;
+  constexpr int NWAVES = kTileThreads / 64;
+  constexpr bool POW2 = (S & (S - 1)) == 0;
+  constexpr size_t BLK = sizeof(R) * ((TS3 + 3) & ~3);
+  constexpr size_t RED = POW2 ? 0 : sizeof(R) * kTileThreads * 4;
+  constexpr size_t WF = sizeof(R) * NWAVES * GROUPS * 2 * S;
+
+  const int tile = xcd_local(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  R *blk = reinterpret_cast<R *>(h_smem);
+  R *red = reinterpret_cast<R *>(h_smem + BLK);
+  R *wfac = reinterpret_cast<R *>(h_smem + BLK + RED);
+  int *rowtab = reinterpret_cast<int *>(h_smem + BLK + RED + WF), *xtab = rowtab + TS * TS;
+
+  // Stage the block (batched loads into registers, then LDS stores; grid
+  // offsets from row and column tables), as k_gather does.
+  const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
+  const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
+  constexpr int NST = (TS3 + kTileThreads - 1) / kTileThreads;  // elements per thread
+  constexpr int BATCH = sizeof(R) == 4 ? 16 : 8;
+  const int start = offsets[tile], end = offsets[tile + 1];
+  if (start == end) return;  // uniform across the work-group
+  for (int r = tid; r < TS * TS; r += kTileThreads) {
+    const int lz = r / TS, ly = r - lz * TS;
+    rowtab[r] = (wrap_near(bz + lz, M) * M + wrap_near(by + ly, M)) * M;
+  }
+  if (tid < TS) xtab[tid] = wrap_near(bx + tid, M);
+  __syncthreads();
+  const int grp = lane / S, jx = lane - grp * S;
+  const bool active = grp < GROUPS;
+  constexpr int STRIDE = NWAVES * GROUPS;
+  int c = start + wave * GROUPS + grp;
+  // this group's first particle is requested while the block is staged
+  SortedParticle<R> sp{};
+  int2 mt = make_int2(0, 0);
+  if (active && c < end) {
+    sp = sorted[c];
+    mt = meta[c];
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < NST; k0 += BATCH) {
+    R v[BATCH];
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int i = tid + (k0 + k) * kTileThreads;
+      if (k0 + k < NST && i < TS3) {
+        const int r = i / TS, lx = i - r * TS;
+        v[k] = phi_grid[rowtab[r] + xtab[lx]];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int i = tid + (k0 + k) * kTileThreads;
+      if (k0 + k < NST && i < TS3) blk[i] = v[k];
+    }
+  }
+  __syncthreads();
+
+  const R scale = gscale ? static_cast<R>(*gscale) : R(1);
+  const R cg = static_cast<R>(wc.cg), beta = static_cast<R>(wc.beta);
+  const R dc = static_cast<R>(wc.dcoef);
+  R *gslot = wfac + (wave * GROUPS + grp) * 2 * S;  // this group's y and z factors
+  R *wred = red + wave * 64 * 4;
+  for (; active && c < end; c += STRIDE) {
+    const int cn = c + STRIDE;
+    SortedParticle<R> nsp{};
+    int2 nmt = make_int2(0, 0);
+    if (cn < end) {  // the next particle is requested before this one's sums
+      nsp = sorted[cn];
+      nmt = meta[cn];
+    }
+    const R kj = static_cast<R>(jx + OFF);
+    const R tx0 = kj - sp.dx, ty0 = kj - sp.dy, tz0 = kj - sp.dz;
+    R gx;
+    if constexpr (sizeof(R) == 4) {
+      const float c2 = wc.cgl2;
+      gx = beta * exp2_fast(-c2 * tx0 * tx0);
+      gslot[jx] = beta * exp2_fast(-c2 * ty0 * ty0);
+      gslot[S + jx] = beta * exp2_fast(-c2 * tz0 * tz0);
+    } else {
+      gx = beta * exp(-cg * tx0 * tx0);
+      gslot[jx] = beta * exp(-cg * ty0 * ty0);
+      gslot[S + jx] = beta * exp(-cg * tz0 * tz0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // d/dx_m of a Gaussian factor is dc (j + OFF - d) g_j.  With the centred
+    // weights c_j = j + OFF - 1/2 and e = d - 1/2 (|e| <= 1/2):
+    //   sum_j (j + OFF - d) g_j a_j = sum_j c_j g_j a_j - e sum_j g_j a_j,
+    // so the derivative needs one extra weighted sum per axis.
+    R gy[S], gz[S], cy[S], cz[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      gy[j] = gslot[j];
+      gz[j] = gslot[S + j];
+      cy[j] = (static_cast<R>(j + OFF) - R(0.5)) * gy[j];
+      cz[j] = (static_cast<R>(j + OFF) - R(0.5)) * gz[j];
+    }
+    const int packed = mt.x;
+    const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
+    const R *col = blk + (az * TS + ay) * TS + ax + jx;
+    R s0 = R(0), s1 = R(0), s2 = R(0);
+#pragma unroll
+    for (int jy = 0; jy < S; ++jy) {
+      R a0 = R(0), b1 = R(0);
+#pragma unroll
+      for (int jz = 0; jz < S; ++jz) {
+        const R v = col[(jz * TS + jy) * TS];
+        a0 += v * gz[jz];
+        b1 += v * cz[jz];
+      }
+      s0 += gy[jy] * a0;  // sum g_y g_z Phi
+      s1 += cy[jy] * a0;  // sum c_y g_y g_z Phi
+      s2 += gy[jy] * b1;  // sum g_y c_z g_z Phi
+    }
+    const R ey = sp.dy - R(0.5), ez = sp.dz - R(0.5);
+    const R dgx = dc * tx0 * gx;
+    R t0 = gx * s0, t1 = dgx * s0, t2 = dc * gx * (s1 - ey * s0), t3 = dc * gx * (s2 - ez * s0);
+    // the group's slot is rewritten only after every lane has read it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if constexpr (POW2) {
+#pragma unroll
+      for (int o = S / 2; o > 0; o >>= 1) {
+        t0 += __shfl_xor(t0, o);
+        t1 += __shfl_xor(t1, o);
+        t2 += __shfl_xor(t2, o);
+        t3 += __shfl_xor(t3, o);
+      }
+    } else {
+      R *mine = wred + lane * 4;
+      mine[0] = t0;
+      mine[1] = t1;
+      mine[2] = t2;
+      mine[3] = t3;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (jx == 0) {
+        Kahan<R> k0, k1, k2, k3;
+        const R *g = wred + grp * S * 4;
+#pragma unroll
+        for (int l = 0; l < S; ++l) {
+          k0.add(g[4 * l + 0]);
+          k1.add(g[4 * l + 1]);
+          k2.add(g[4 * l + 2]);
+          k3.add(g[4 * l + 3]);
+        }
+        t0 = k0.value();
+        t1 = k1.value();
+        t2 = k2.value();
+        t3 = k3.value();
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (jx == 0) {
+      const R q = sp.q;
+      const int orig = mt.y;
+      if (mode >= kGatherIkX) {
+        out_vec[3 * orig + (mode - kGatherIkX)] = scale * q * t0;
+      } else {
+        const R pot = t0 + self_coef * q;
+        const R fq = (mode == kGatherPotentialForce) ? -scale * q : scale * q;
+        if (out_pot) out_pot[orig] = scale * pot;
+        if (out_vec) {
+          out_vec[3 * orig + 0] = fq * t1;
+          out_vec[3 * orig + 1] = fq * t2;
+          out_vec[3 * orig + 2] = fq * t3;
+        }
+      }
+    }
+    sp = nsp;
+    mt = nmt;
+  }
+}
+
 // One gather launch over the grid `grid`: the plan's particles, or with
 // `tgt` its evaluation points (unit test charges, no self term).
 template <typename R, int WIN, int S, int T>
 hipError_t gather_one(se_plan &p, const void *grid, bool tgt, const double *gscale, int mode,
                       void *pot, void *vec) {
-  const size_t lds = GatherLds<R, WIN, S, T>::TOTAL;
+  constexpr bool kLane = WIN == kGauss;
+  const size_t lds = kLane ? gather_lane_lds(sizeof(R), S, T) : GatherLds<R, WIN, S, T>::TOTAL;
   const double dcoef = (WIN == kGauss) ? 2.0 * p.a * p.h : 1.0 / p.h;
   const WindowConsts wc = window_consts(p.cg, p.beta, dcoef);
   const double self =
@@ -328,17 +538,24 @@ hipError_t gather_one(se_plan &p, const void *grid, bool tgt, const double *gsca
   const void *sorted = tgt ? p.tgt.sorted : p.buf.sorted;
   const int2 *meta = tgt ? p.tgt.meta : p.buf.meta;
   const int *offsets = tgt ? p.tgt.offsets : p.buf.offsets;
+  const void *kern = kLane ? reinterpret_cast<const void *>(&k_gather_lane<R, S, T>)
+                           : reinterpret_cast<const void *>(&k_gather<R, WIN, S, T>);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gather<R, WIN, S, T>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
   if (!tgt) stage_begin(p, SE_STAGE_GATHER);
-  k_gather<R, WIN, S, T><<<p.ntiles, kTileThreads, lds, p.stream>>>(
-      static_cast<const R *>(grid), static_cast<const SortedParticle<R> *>(sorted), meta,
-      offsets, p.prm.M, p.ntx, wc, gscale, mode, static_cast<R>(self), static_cast<R *>(pot),
-      static_cast<R *>(vec));
+  if constexpr (kLane)
+    launch_on(&p, k_gather_lane<R, S, T>, p.ntiles, kTileThreads, lds, p.stream, 
+        static_cast<const R *>(grid), static_cast<const SortedParticle<R> *>(sorted), meta,
+        offsets, p.prm.M, p.ntx, wc, gscale, mode, static_cast<R>(self), static_cast<R *>(pot),
+        static_cast<R *>(vec));
+  else
+    launch_on(&p, k_gather<R, WIN, S, T>, p.ntiles, kTileThreads, lds, p.stream, 
+        static_cast<const R *>(grid), static_cast<const SortedParticle<R> *>(sorted), meta,
+        offsets, p.prm.M, p.ntx, wc, gscale, mode, static_cast<R>(self), static_cast<R *>(pot),
+        static_cast<R *>(vec));
   if (!tgt) stage_end(p, SE_STAGE_GATHER);
   return hipGetLastError();
 }
@@ -388,7 +605,8 @@ hipError_t gather_call(se_plan &p, const GatherCall &g) {
 }  // namespace
 
 size_t gather_lds_bytes(int real_size, int window, int S, int T) {
-  const int win = window == SE_WINDOW_GAUSSIAN ? kGauss : kBspline;
+  if (window == SE_WINDOW_GAUSSIAN) return gather_lane_lds(real_size, S, T);
+  const int win = kBspline;
   const size_t rec = gather_rec(win, S);
   const size_t chunk = gather_chunk(real_size, win, S, T);
   return static_cast<size_t>(gather_fixed_bytes(real_size, S, T)) + real_size * chunk * rec +

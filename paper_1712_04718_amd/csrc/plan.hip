@@ -54,7 +54,7 @@ int real_size(const se_params &p) { return p.dtype == SE_FP64 ? 8 : 4; }
 int choose_tile(const se_params &p) {
   const int rs = real_size(p), S = p.P;
   const auto fits = [&](int T) {
-    return sek::spread_lds_bytes(rs, S, T) <= sek::kMaxLds &&
+    return sek::spread_lds_bytes(rs, p.window, S, T) <= sek::kMaxLds &&
            sek::gather_lds_bytes(rs, p.window, S, T) <= sek::kMaxLds;
   };
   for (int T : {16, 12}) {

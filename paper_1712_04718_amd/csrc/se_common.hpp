@@ -2,6 +2,7 @@
 // Not part of the public ABI (that is include/sekspace.h).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -195,6 +196,8 @@ struct se_plan {
   // optional per-kernel timing (SE_FLAG_TIMING)
   bool timing;
   sek::StageTimer timers[SE_NUM_STAGES];
+  int armed_stage = -1;      // stage whose event pair the next launches carry
+  bool armed_first = false;  // no launch has carried it yet
 };
 
 namespace sek {
@@ -243,22 +246,44 @@ hipError_t launch_fft_forward_scale_inverse(se_plan &plan, double *E_dev);
 hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode,
                          void *out_pot, void *out_vec);
 
-// Event pair around one kernel launch when the plan records timings.
+// Per-stage timing of plans with SE_FLAG_TIMING.  stage_begin arms the
+// stage's next event pair; every launch_on inside the stage carries the pair
+// (hipExtLaunchKernelGGL timestamps exactly that dispatch, as a profiler's
+// kernel trace does): the first launch sets the start, each launch the stop,
+// so a stage of several launches spans them all; stage_end counts the pair
+// if a launch used it.
 inline void stage_begin(se_plan &p, int stage) {
   if (!p.timing) return;
   StageTimer &t = p.timers[stage];
   if (t.issued - t.harvested == kTimingSlots) (void)harvest_oldest(t);
-  (void)hipEventRecord(t.begin[t.issued % kTimingSlots], p.stream);
+  p.armed_stage = stage;
+  p.armed_first = true;
 }
 inline void stage_end(se_plan &p, int stage) {
   if (!p.timing) return;
-  StageTimer &t = p.timers[stage];
-  (void)hipEventRecord(t.end[t.issued % kTimingSlots], p.stream);
-  ++t.issued;
+  if (p.armed_stage == stage && !p.armed_first) ++p.timers[stage].issued;
+  p.armed_stage = -1;
+}
+
+// Launch a kernel (<<<grid, block, lds, stream>>>), with the armed stage's
+// event pair when tp is a timing plan inside stage_begin/stage_end.
+template <typename... KArgs, typename... Args>
+inline void launch_on(se_plan *tp, void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds,
+                      hipStream_t stream, Args... args) {
+  if (tp && tp->timing && tp->armed_stage >= 0) {
+    StageTimer &t = tp->timers[tp->armed_stage];
+    const int slot = static_cast<int>(t.issued % kTimingSlots);
+    hipExtLaunchKernelGGL(kernel, grid, block, static_cast<std::uint32_t>(lds), stream,
+                          tp->armed_first ? t.begin[slot] : nullptr, t.end[slot], 0u,
+                          static_cast<KArgs>(args)...);
+    tp->armed_first = false;
+  } else {
+    kernel<<<grid, block, lds, stream>>>(static_cast<KArgs>(args)...);
+  }
 }
 
 // LDS bytes a spreading / gathering work-group needs (tile edge T, support S).
-size_t spread_lds_bytes(int real_size, int S, int T);
+size_t spread_lds_bytes(int real_size, int window, int S, int T);
 size_t gather_lds_bytes(int real_size, int window, int S, int T);
 constexpr size_t kMaxLds = 160 * 1024;
 

@@ -17,13 +17,19 @@
 // on this chip.)  An FP32 contribution has 24 significant bits while the
 // fixed point spans 30, so exact halves are common: they round to even,
 // which keeps the sum unbiased (rounding halves up would not).
-// Work split: the tile's particles are taken in chunks of one per thread;
+// Work split, Gaussian window (k_spread_lane): each wave holds 64/S particle
+// groups of S lanes; lane (group, jx) owns the x-offset jx of one particle,
+// evaluates the factors it needs itself (its x factor, all S factors along y
+// and z) and adds its S^2 (jy, jz) products.  The exponentials run in the
+// shadow of the LDS atomics, whose issue rate bounds the kernel, and no
+// factor table or barrier sits between the particles and their atomics.
+// B-spline window (k_spread): the tile's particles are taken in chunks of one
+// per thread;
 //   phase A: each thread computes its particle's 3S window factors and
 //            stores them with its charge in LDS (the first chunk while the
 //            tile's max |q| is being reduced);
-//   phase B: each wave holds 64/S particle groups of S lanes; lane
-//            (group, jx) owns the x-offset jx of one particle and adds its
-//            S^2 (jy, jz) products.
+//   phase B: as above, the factors read from LDS (the order-p recursion costs
+//            more than the atomics it would hide behind).
 #include "se_common.hpp"
 #include "window.hpp"
 
@@ -214,6 +220,138 @@ k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ 
   }
 }
 
+// Fixed-point scale of a tile from a bound on sum |q| that does not depend
+// on the order of its particles (that order comes from atomics): qmax =
+// max |q| is exact, each particle contributes the integer
+// u = ceil(|q| / qmax * 2^20) >= |q| / qmax * 2^20, and integer sums are
+// exact, so qmax * sum(u) / 2^20 >= sum |q| is the same on every run.  Two
+// block reductions, one barrier each; red holds 2 NWAVES doubles.  A
+// non-finite charge weighs 0 here (the integer conversion stays defined).
+template <typename R, int NWAVES>
+__device__ inline double tile_bound(const SortedParticle<R> *__restrict__ sorted, int start,
+                                    int end, double *red) {
+  const int tid = threadIdx.x;
+  double m = 0.0;
+  for (int p = start + tid; p < end; p += kTileThreads)
+    m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  double *red_max = red;
+  long long *red_u = reinterpret_cast<long long *>(red + NWAVES);
+  if ((tid & 63) == 0) red_max[tid >> 6] = m;
+  __syncthreads();
+  double qmax = 0.0;
+  for (int w = 0; w < NWAVES; ++w) qmax = fmax(qmax, red_max[w]);
+  long long u = 0;
+  if (qmax > 0.0) {
+    for (int p = start + tid; p < end; p += kTileThreads) {
+      const double w = ceil(fabs(static_cast<double>(sorted[p].q)) / qmax * 1048576.0);
+      u += w <= 1048576.0 ? static_cast<long long>(w) : 0LL;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
+  if ((tid & 63) == 0) red_u[tid >> 6] = u;
+  __syncthreads();
+  long long usum = 0;
+  for (int w = 0; w < NWAVES; ++w) usum += red_u[w];
+  return qmax * (static_cast<double>(usum) / 1048576.0);
+}
+
+constexpr size_t spread_lane_lds(int real_size, int S, int T) {
+  const size_t TS = T + S - 1, acc = real_size == 4 ? 4 : 8;
+  return acc * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) + 128;
+}
+
+// Gaussian window: the factors are evaluated by the lanes that use them
+// (see the file comment).  Per lane: its x factor g_jx = beta e^{-cg t^2}
+// (t = jx + OFF - dx) directly, and the S factors along y and z with
+// window_axis.
+template <typename R, int S, int T>
+__global__ void __launch_bounds__(kTileThreads)
+k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ meta,
+              const int *__restrict__ offsets, int *__restrict__ counts, WindowConsts wc,
+              double wmax, R *__restrict__ ghost) {
+  using A = typename Acc<R>::T;
+  constexpr int TS = T + S - 1, TS3 = TS * TS * TS;
+  constexpr int GROUPS = 64 / S;
+  constexpr int NWAVES = kTileThreads / 64;
+  constexpr int OFF = Stencil<kGauss, S>::OFF;
+  constexpr double kFix = sizeof(R) == 4 ? 1073741824.0 : 4611686018427387904.0;  // 2^30, 2^62
+  static_assert(2 * NWAVES * 8 <= 128, "reduction slots");
+
+  const int tile = xcd_local(blockIdx.x, gridDim.x);
+  const int start = offsets[tile], end = offsets[tile + 1];
+  const int tid = threadIdx.x;
+  // the binning left this tile's count for its consumer to reset
+  if (tid == 0) counts[tile * kCountStride] = 0;
+  R *out = ghost + static_cast<long long>(tile) * TS3;
+  if (start == end) {  // uniform across the work-group
+    for (int i = tid; i < TS3; i += kTileThreads) out[i] = R(0);
+    return;
+  }
+  A *blk = reinterpret_cast<A *>(g_smem);
+  double *red = reinterpret_cast<double *>(g_smem + sizeof(A) * ((TS3 + 3) & ~3));
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int grp = lane / S, jx = lane - grp * S;
+  const bool active = grp < GROUPS;
+  constexpr int STRIDE = NWAVES * GROUPS;
+  int c = start + wave * GROUPS + grp;
+  // this group's first particle is requested before the block is cleared
+  // and the bound reduced
+  SortedParticle<R> sp{};
+  int packed = 0;
+  if (active && c < end) {
+    sp = sorted[c];
+    packed = meta[c].x;
+  }
+  for (int i = tid; i < TS3; i += kTileThreads) blk[i] = A(0);
+  const double bound = wmax * tile_bound<R, NWAVES>(sorted, start, end, red);
+  const double scale = bound > 0.0 ? kFix / bound : 1.0;
+  const double inv_scale = bound > 0.0 ? bound / kFix : 1.0;  // the barriers of the bound also
+                                                              // order the clearing of blk
+
+  const R cg = static_cast<R>(wc.cg), beta = static_cast<R>(wc.beta);
+  for (; active && c < end; c += STRIDE) {
+    const int cn = c + STRIDE;
+    SortedParticle<R> nsp{};
+    int npacked = 0;
+    if (cn < end) {  // the next particle is requested before this one's atomics
+      nsp = sorted[cn];
+      npacked = meta[cn].x;
+    }
+    R gy[S], gz[S], unused[S];
+    window_axis<R, kGauss, S, false>(sp.dy, wc, gy, unused);
+    window_axis<R, kGauss, S, false>(sp.dz, wc, gz, unused);
+    const R t = static_cast<R>(jx + OFF) - sp.dx;
+    R gx;
+    if constexpr (sizeof(R) == 4)
+      gx = beta * exp2_fast(-wc.cgl2 * t * t);
+    else
+      gx = beta * exp(-cg * t * t);
+    const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
+    A *row = blk + (az * TS + ay) * TS + ax + jx;
+    // the charge in fixed-point units times this lane's x factor
+    const R wq = static_cast<R>(static_cast<double>(sp.q) * scale) * gx;
+#pragma unroll
+    for (int jz = 0; jz < S; ++jz) {
+      const R wz = wq * gz[jz];
+#pragma unroll
+      for (int jy = 0; jy < S; ++jy) {
+        if constexpr (sizeof(R) == 4)
+          atomicAdd(row + (jz * TS + jy) * TS, __float2int_rn(wz * gy[jy]));
+        else  // two's complement: the unsigned add is the signed one
+          atomicAdd(reinterpret_cast<unsigned long long *>(row + (jz * TS + jy) * TS),
+                    static_cast<unsigned long long>(__double2ll_rn(wz * gy[jy])));
+      }
+    }
+    sp = nsp;
+    packed = npacked;
+  }
+  __syncthreads();
+  for (int i = tid; i < TS3; i += kTileThreads)
+    out[i] = static_cast<R>(static_cast<double>(blk[i]) * inv_scale);
+}
+
 // ------------------------------------------------------------------ fold
 // The spread grid is the sum of the tile blocks that cover each point.
 
@@ -297,19 +435,26 @@ k_fold_tiles(const R *__restrict__ ghost, int M, int ntx, R *__restrict__ grid) 
 
 template <typename R, int WIN, int S, int T>
 hipError_t spread_one(se_plan &p) {
-  const size_t lds = SpreadLds<R, S, T>::TOTAL;
+  constexpr bool kLane = WIN == kGauss;
+  const size_t lds = kLane ? spread_lane_lds(sizeof(R), S, T) : SpreadLds<R, S, T>::TOTAL;
   const WindowConsts wc = window_consts(p.cg, p.beta, 0.0);
   const double wmax = (WIN == kGauss) ? p.beta * p.beta * p.beta : 1.0;
+  const void *kern = kLane ? reinterpret_cast<const void *>(&k_spread_lane<R, S, T>)
+                           : reinterpret_cast<const void *>(&k_spread<R, WIN, S, T>);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_spread<R, WIN, S, T>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
   stage_begin(p, SE_STAGE_SPREAD);
-  k_spread<R, WIN, S, T><<<p.ntiles, kTileThreads, lds, p.stream>>>(
-      static_cast<const SortedParticle<R> *>(p.buf.sorted), p.buf.meta, p.buf.offsets,
-      p.buf.counts, wc, wmax, static_cast<R *>(p.buf.ghost));
+  if constexpr (kLane)
+    launch_on(&p, k_spread_lane<R, S, T>, p.ntiles, kTileThreads, lds, p.stream, 
+        static_cast<const SortedParticle<R> *>(p.buf.sorted), p.buf.meta, p.buf.offsets,
+        p.buf.counts, wc, wmax, static_cast<R *>(p.buf.ghost));
+  else
+    launch_on(&p, k_spread<R, WIN, S, T>, p.ntiles, kTileThreads, lds, p.stream, 
+        static_cast<const SortedParticle<R> *>(p.buf.sorted), p.buf.meta, p.buf.offsets,
+        p.buf.counts, wc, wmax, static_cast<R *>(p.buf.ghost));
   stage_end(p, SE_STAGE_SPREAD);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -317,12 +462,12 @@ hipError_t spread_one(se_plan &p) {
   stage_begin(p, SE_STAGE_FOLD);
   if (p.fold_by_tiles) {
     const dim3 fg(p.ntiles, (T * T * T + kThreads - 1) / kThreads);
-    k_fold_tiles<R, WIN, S, T><<<fg, kThreads, 0, p.stream>>>(
+    launch_on(&p, k_fold_tiles<R, WIN, S, T>, fg, kThreads, 0, p.stream, 
         static_cast<const R *>(p.buf.ghost), M, p.ntx, static_cast<R *>(p.buf.grid));
   } else {
     const long long ngrid = static_cast<long long>(M) * M * M;
-    k_fold<R><<<static_cast<unsigned>((ngrid + kThreads - 1) / kThreads), kThreads, 0,
-                p.stream>>>(static_cast<const R *>(p.buf.ghost), p.fold, M,
+    launch_on(&p, k_fold<R>, static_cast<unsigned>((ngrid + kThreads - 1) / kThreads), kThreads, 0,
+                p.stream, static_cast<const R *>(p.buf.ghost), p.fold, M,
                             static_cast<R *>(p.buf.grid));
   }
   stage_end(p, SE_STAGE_FOLD);
@@ -359,7 +504,10 @@ hipError_t spread_dispatch(se_plan &p) {
 
 }  // namespace
 
-size_t spread_lds_bytes(int real_size, int S, int T) { return spread_lds_total(real_size, S, T); }
+size_t spread_lds_bytes(int real_size, int window, int S, int T) {
+  return window == SE_WINDOW_GAUSSIAN ? spread_lane_lds(real_size, S, T)
+                                      : spread_lds_total(real_size, S, T);
+}
 
 hipError_t launch_spread(se_plan &plan) {
   return plan.prm.dtype == SE_FP64 ? spread_dispatch<double>(plan)

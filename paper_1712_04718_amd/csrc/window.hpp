@@ -45,10 +45,16 @@ struct WindowConsts {
   double kap;    // exp(-2 cg), ratio of successive recurrence factors (SE)
   double dcoef;  // SE: 2 a h; SPME: 1/h   (derivative scale)
   float ck[kMaxHalfSupport + 1];  // exp(-cg k^2), k = 0..S/2 (SE, FP32)
+  float cgl2;    // cg log2(e): FP32 factors as beta 2^{-cgl2 t^2} (SE)
 };
 
+// e^{-cg t^2} in FP32 as 2^{-cgl2 t^2} with the hardware base-2 exponential
+// (v_exp_f32, about 1 ulp): the rounding of the argument, which any FP32
+// evaluation shares, dominates its error.
+__device__ inline float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
 inline WindowConsts window_consts(double cg, double beta, double dcoef) {
-  WindowConsts wc{cg, beta, std::exp(-2.0 * cg), dcoef, {}};
+  WindowConsts wc{cg, beta, std::exp(-2.0 * cg), dcoef, {}, static_cast<float>(cg * M_LOG2E)};
   for (int k = 0; k <= kMaxHalfSupport; ++k)
     wc.ck[k] = static_cast<float>(std::exp(-cg * static_cast<double>(k) * k));
   return wc;
@@ -77,8 +83,9 @@ __device__ inline void window_axis(R d, const WindowConsts &wc, R (&g)[S], R (&d
       // k < 0) are built outward from the anchor, where the factors are
       // largest, and gain about one rounding per step.
       constexpr int J0 = -OFF;  // index of the anchor point
-      const R A = beta * expf(-cg * d * d);
-      const R Bu = expf(R(2) * cg * d), Bd = expf(R(-2) * cg * d);
+      const float c2 = wc.cgl2;
+      const R A = beta * exp2_fast(-c2 * d * d);
+      const R Bu = exp2_fast(2.0f * c2 * d), Bd = exp2_fast(-2.0f * c2 * d);
       g[J0] = A;
       R p = A;
 #pragma unroll
