@@ -211,6 +211,26 @@ se_status se_gather(se_plan *plan, void *phi, void *F);
 se_status se_kspace(se_plan *plan, int N, const void *x, const void *q,
                     double *E_dev, void *phi, void *F);
 
+/* se_kspace without a plan and without allocating, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Parameters as for se_plan_create
+ * (prm->flags may hold SE_FLAG_ADD_SELF and SE_FLAG_IK_FORCE; SE_FLAG_TIMING
+ * and SE_FLAG_CALLER_WORKSPACE are SE_ERR_ARG), arrays and outputs as for
+ * se_kspace (device pointers; phi or F may be NULL; N >= 0), enqueued on
+ * hip_stream (a hipStream_t, NULL = the default stream) of the current
+ * device.  The workspace of the evaluation (se_plan_workspace_size(prm, N)
+ * bytes) is carved out of a static array of 64 MiB that the library holds
+ * on each device it runs on until the process ends; an evaluation needing
+ * more is SE_ERR_WORKSPACE (checked on the host, nothing enqueued).  Every
+ * call on a device shares that device's array: the tables and tile
+ * counters are rewritten at the start of each call, and calls that overlap
+ * in time on one device (other streams, other host threads) race.  The
+ * first call on a device resolves the array's address there
+ * (hipGetSymbolAddress; make it outside graph capture).  No hipMalloc,
+ * hipFree or other allocating call is made. */
+se_status se_kspace_noalloc(const se_params *prm, int N, const void *x, const void *q,
+                            double *E_dev, void *phi, void *F, void *hip_stream);
+
 /* Adjoint of se_forward for reverse-mode differentiation, reusing the stored
  * scaled grid (no re-spreading, no FFT):
  *     grad_x = gE * dE/dx = -gE * F,   grad_q = gE * dE/dq = gE * phi,

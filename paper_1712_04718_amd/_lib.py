@@ -33,7 +33,8 @@ EXPORTS = (
     "se_status_string", "se_last_error", "se_params_check", "se_plan_workspace_size",
     "se_plan_create", "se_plan_set_workspace", "se_plan_set_stream", "se_plan_eta",
     "se_plan_destroy",
-    "se_forward", "se_gather", "se_kspace", "se_backward", "se_plan_stage_times",
+    "se_forward", "se_gather", "se_kspace", "se_kspace_noalloc", "se_backward",
+    "se_plan_stage_times",
     "se_plan_reserve_targets", "se_eval_targets",
     "se_rs_plan_create", "se_rs_plan_set_stream", "se_rs_eval", "se_rs_plan_destroy",
     "se_est_real_error", "se_est_fourier_error", "se_est_xi", "se_est_kinf",
@@ -119,6 +120,8 @@ def load() -> ctypes.CDLL:
     lib.se_gather.argtypes = [vp, vp, vp]
     lib.se_kspace.restype = i
     lib.se_kspace.argtypes = [vp, i, vp, vp, vp, vp, vp]
+    lib.se_kspace_noalloc.restype = i
+    lib.se_kspace_noalloc.argtypes = [pp, i, vp, vp, vp, vp, vp, vp]
     lib.se_backward.restype = i
     lib.se_backward.argtypes = [vp, vp, vp, vp]
     lib.se_plan_reserve_targets.restype = i

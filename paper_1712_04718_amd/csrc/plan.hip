@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -405,6 +406,36 @@ se_status check_tiling(const se_plan &pl) {
   return SE_OK;
 }
 
+// ------------------------------------------------ no-allocation entry point
+// se_kspace_noalloc carves the workspace of one evaluation out of this
+// file-scope array instead of allocating: each GPU the library runs on holds
+// its own copy (its address differs per device) until the process ends.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxScratchDevices];  // device address of scratch, per device
+
+// Device address of the current device's scratch, resolved once per device
+// (with that device current) by hipGetSymbolAddress; host code uses only this
+// address, never the array's name.
+hipError_t scratch_address(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 namespace sek {
@@ -673,3 +704,33 @@ se_status se_backward(se_plan *plan, const double *gE_dev, void *grad_x, void *g
 }
 
 }  // extern "C"
+
+extern "C" se_status se_kspace_noalloc(const se_params *prm, int N, const void *x, const void *q,
+                                       double *E_dev, void *phi, void *F, void *hip_stream) {
+  se_status s = check_params(prm, nullptr);
+  if (s != SE_OK) return s;
+  if (prm->flags & (SE_FLAG_TIMING | SE_FLAG_CALLER_WORKSPACE))
+    return fail(SE_ERR_ARG, "se_kspace_noalloc takes neither SE_FLAG_TIMING nor "
+                            "SE_FLAG_CALLER_WORKSPACE");
+  if (N < 0) return fail(SE_ERR_ARG, "N=%d is negative", N);
+  // a plan on the stack: derived parameters and buffer pointers only
+  se_plan pl{};
+  pl.prm = *prm;
+  if (pl.prm.c <= 0.0) pl.prm.c = 0.95;
+  pl.n_max = N > 0 ? N : 1;
+  pl.stream = static_cast<hipStream_t>(hip_stream);
+  pl.last_N = -1;
+  derive(pl);
+  if ((s = check_tiling(pl)) != SE_OK) return s;
+  const Sizes sz = sizes_of(pl.prm, pl.n_max, pl.ntiles, pl.bin_blocks, pl.zfft_blocks, pl.T);
+  if (sz.total > kScratchBytes)
+    return fail(SE_ERR_WORKSPACE,
+                "this evaluation needs %zu bytes of workspace; the static scratch holds %zu",
+                sz.total, kScratchBytes);
+  void *base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return hip_fail(e, "address of the static scratch");
+  if ((e = attach(pl, sz, base)) != hipSuccess) return hip_fail(e, "scratch tables");
+  if ((s = forward_impl(pl, N, x, q, E_dev)) != SE_OK) return s;
+  return gather_impl(pl, phi, F);
+}
