@@ -10,17 +10,18 @@
 // that tile from an atomic add on the tile's counter (one cache line per
 // counter).  Returning global atomics are the cost here, so they are
 // aggregated:
-//   k_bin_count_lds: a work-group takes 256 PPT particles, ranks them per
-//     tile with LDS atomics, then adds each touched tile's count to the
-//     global counter once and hands the returned base to its particles;
-//     PPT = 8 when tiles hold many particles (far fewer global atomics),
-//     PPT = 1 otherwise;
+//   k_bin_count_lds: a work-group takes its particles (256 threads x 1, or
+//     1024 x 8 when tiles hold many particles), ranks them per tile with
+//     LDS atomics, then adds each touched tile's count to the global
+//     counter once and hands the returned base to its particles;
 //   k_bin_count_run: for grids with more tiles than the LDS tables hold,
 //     one atomic per run of equal tiles among neighbouring lanes of a wave
 //     (the atoms of a molecule are usually adjacent in the input).
 // Both also write per-block sums of q^2 (for the self energy).
 // k_bin_scan: one work-group turns the tile counts into offsets (exclusive
-//   scan) and resets the counts for the next call;
+//   scan) and resets the counts for the next call; above 2048 cells
+//   k_bin_scan_sums and k_bin_scan_apply do it over chunks of 2048 cells on
+//   as many work-groups (the real-space cell lists reach 85k cells);
 // k_bin_scatter: write the particles in tile order as (offsets from the
 //   anchor in grid units, q) plus (packed local anchor, original index);
 // k_bin_scatter_scan: the two in one launch when tiles x work-groups is at
@@ -56,36 +57,44 @@ __device__ inline int particle_tile(const R *__restrict__ x, const R *__restrict
   return tile_of(x[3 * n + 0], x[3 * n + 1], x[3 * n + 2], h, M, T, ntx);
 }
 
-// Sum of a per-thread double over the work-group, written by thread 0.
+// Sum of a per-thread double over a work-group of NTHR threads, written by
+// thread 0.
+template <int NTHR = kThreads>
 __device__ inline void block_sum_to(double v, double *out) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  __shared__ double red[kThreads / 64];
+  __shared__ double red[NTHR / 64];
   const int tid = threadIdx.x;
   if ((tid & 63) == 0) red[tid >> 6] = v;
   __syncthreads();
   if (tid == 0) {
     double s = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    for (int w = 0; w < NTHR / 64; ++w) s += red[w];
     *out = s;
   }
 }
 
-template <typename R, int PPT>
-__global__ void __launch_bounds__(kThreads)
+// NTHR threads per work-group, PPT particles per thread: the work-group's
+// NTHR PPT particles are ranked per tile in LDS, then each touched tile's
+// count is added to its global counter once.  Device-scope atomics are the
+// cost (about 20 per ns over the chip), so where tiles hold many particles
+// the work-groups are large (1024 threads x 8: a quarter of the atomics of
+// 256 x 8 with the same loads in flight).
+template <typename R, int PPT, int NTHR>
+__global__ void __launch_bounds__(NTHR)
 k_bin_count_lds(int N, const R *__restrict__ x, const R *__restrict__ q, double h, int M,
                 int T, int ntx, int ntiles, int *__restrict__ counts, int2 *__restrict__ key,
                 double *__restrict__ qsq_part) {
   extern __shared__ int lds_tiles[];
   int *lcnt = lds_tiles, *lbase = lds_tiles + ntiles;
   const int tid = threadIdx.x;
-  const int n0 = blockIdx.x * (kThreads * PPT);
-  for (int t = tid; t < ntiles; t += kThreads) lcnt[t] = 0;
+  const int n0 = blockIdx.x * (NTHR * PPT);
+  for (int t = tid; t < ntiles; t += NTHR) lcnt[t] = 0;
   // all PPT particles are read before the first is used (the index is
   // clamped into [0, N), N >= 1, so the loads need no branch)
   R px[PPT][3], pq[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int nc = min(n0 + k * kThreads + tid, N - 1);  // consecutive threads, consecutive particles
+    const int nc = min(n0 + k * NTHR + tid, N - 1);  // consecutive threads, consecutive particles
     px[k][0] = x[3 * nc + 0];
     px[k][1] = x[3 * nc + 1];
     px[k][2] = x[3 * nc + 2];
@@ -95,7 +104,7 @@ k_bin_count_lds(int N, const R *__restrict__ x, const R *__restrict__ q, double 
   double qq = 0.0;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int n = n0 + k * kThreads + tid;
+    const int n = n0 + k * NTHR + tid;
     tile[k] = -1;
     rank[k] = 0;
     if (n < N) {
@@ -111,29 +120,29 @@ k_bin_count_lds(int N, const R *__restrict__ x, const R *__restrict__ q, double 
   // one global atomic per touched tile; a thread issues a batch of them
   // before it needs any of the returned bases
   constexpr int kAtomicBatch = 8;
-  for (int t0 = tid; t0 < ntiles; t0 += kThreads * kAtomicBatch) {
+  for (int t0 = tid; t0 < ntiles; t0 += NTHR * kAtomicBatch) {
     int c[kAtomicBatch], b[kAtomicBatch];
 #pragma unroll
     for (int k = 0; k < kAtomicBatch; ++k) {
-      const int t = t0 + k * kThreads;
+      const int t = t0 + k * NTHR;
       c[k] = t < ntiles ? lcnt[t] : 0;
     }
 #pragma unroll
     for (int k = 0; k < kAtomicBatch; ++k)
-      b[k] = c[k] > 0 ? atomicAdd(&counts[(t0 + k * kThreads) * kCountStride], c[k]) : 0;
+      b[k] = c[k] > 0 ? atomicAdd(&counts[(t0 + k * NTHR) * kCountStride], c[k]) : 0;
 #pragma unroll
     for (int k = 0; k < kAtomicBatch; ++k) {
-      const int t = t0 + k * kThreads;
+      const int t = t0 + k * NTHR;
       if (t < ntiles) lbase[t] = b[k];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int n = n0 + k * kThreads + tid;
+    const int n = n0 + k * NTHR + tid;
     if (tile[k] >= 0) key[n] = make_int2(tile[k], lbase[tile[k]] + rank[k]);
   }
-  block_sum_to(qq, &qsq_part[blockIdx.x]);
+  block_sum_to<NTHR>(qq, &qsq_part[blockIdx.x]);
 }
 
 template <typename R>
@@ -218,6 +227,73 @@ k_bin_scan(int *__restrict__ counts, int *__restrict__ offsets, int ntiles) {
       if (t0 + k < hi) emit(t0 + k, w[k]);
   }
   if (tid == kScanThreads - 1) offsets[ntiles] = base + incl;
+}
+
+// Two-level exclusive scan of the cell counts for many cells (k_bin_scan is
+// one work-group): k_bin_scan_sums writes the sum of each chunk of
+// kScanChunk counts; k_bin_scan_apply then scans each chunk on its own
+// work-group, starting from the sum of the chunk sums before it, writes the
+// offsets and resets the counts.  Counts are requested kScanChunk/kThreads
+// per thread before any is used.
+constexpr int kScanPerThread = kScanChunk / kThreads;
+static_assert(kScanChunk % kThreads == 0, "whole chunks per work-group");
+
+__device__ inline int block_sum_int(int v, int *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int tid = threadIdx.x;
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  int s = 0;
+  for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+  return s;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_bin_scan_sums(const int *__restrict__ counts, int ncells, int *__restrict__ sums) {
+  __shared__ int red[kThreads / 64];
+  const int lo = blockIdx.x * kScanChunk + threadIdx.x * kScanPerThread;
+  int v = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPerThread; ++k)
+    v += lo + k < ncells ? counts[(lo + k) * kCountStride] : 0;
+  const int s = block_sum_int(v, red);
+  if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_bin_scan_apply(int *__restrict__ counts, int *__restrict__ offsets, int ncells,
+                 const int *__restrict__ sums) {
+  __shared__ int red[kThreads / 64];
+  __shared__ int wsum[kThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lo = blockIdx.x * kScanChunk + tid * kScanPerThread;
+  int v[kScanPerThread];
+#pragma unroll
+  for (int k = 0; k < kScanPerThread; ++k) v[k] = lo + k < ncells ? counts[(lo + k) * kCountStride] : 0;
+  int before = 0;  // the chunk sums of the work-groups before this one
+  for (int b = tid; b < static_cast<int>(blockIdx.x); b += kThreads) before += sums[b];
+  const int base = block_sum_int(before, red);
+  int local = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPerThread; ++k) local += v[k];
+  int incl = local;  // inclusive scan over the lanes of the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int run = base + incl - local;
+  for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+  for (int k = 0; k < kScanPerThread; ++k)
+    if (lo + k < ncells) {
+      offsets[lo + k] = run;
+      run += v[k];
+      counts[(lo + k) * kCountStride] = 0;
+    }
+  if (lo < ncells && lo + kScanPerThread >= ncells) offsets[ncells] = run;  // the last cell's thread
 }
 
 template <typename R>
@@ -327,14 +403,14 @@ hipError_t bin_impl(const BinJob &j, se_plan *timing) {
     if (j.ncells <= kLdsTilesMax) {
       const size_t lds = sizeof(int) * 2 * static_cast<size_t>(j.ncells);
       if (static_cast<long long>(N) >= 256LL * j.ncells) {
-        constexpr int PPT = 8;
-        parts = (N + kThreads * PPT - 1) / (kThreads * PPT);
-        launch_on(timing, k_bin_count_lds<R, PPT>, parts, kThreads, lds, j.stream, 
-            N, xr, qr, j.h, j.M, j.T, j.ntx, j.ncells, j.counts, j.key, j.qsq_part);
+        constexpr int PPT = 8, NTHR = 1024;
+        parts = (N + NTHR * PPT - 1) / (NTHR * PPT);
+        launch_on(timing, k_bin_count_lds<R, PPT, NTHR>, parts, NTHR, lds, j.stream, N, xr, qr,
+                  j.h, j.M, j.T, j.ntx, j.ncells, j.counts, j.key, j.qsq_part);
       } else {
         parts = blocks1;
-        launch_on(timing, k_bin_count_lds<R, 1>, parts, kThreads, lds, j.stream, 
-            N, xr, qr, j.h, j.M, j.T, j.ntx, j.ncells, j.counts, j.key, j.qsq_part);
+        launch_on(timing, k_bin_count_lds<R, 1, kThreads>, parts, kThreads, lds, j.stream, N, xr,
+                  qr, j.h, j.M, j.T, j.ntx, j.ncells, j.counts, j.key, j.qsq_part);
       }
     } else {
       parts = blocks1;
@@ -359,7 +435,15 @@ hipError_t bin_impl(const BinJob &j, se_plan *timing) {
     return hipGetLastError();
   }
   if (timing) stage_begin(*timing, SE_STAGE_BIN_SCAN);
-  launch_on(timing, k_bin_scan, 1, kScanThreads, 0, j.stream, j.counts, j.offsets, j.ncells);
+  if (j.ncells <= kScanOneGroupMax) {
+    launch_on(timing, k_bin_scan, 1, kScanThreads, 0, j.stream, j.counts, j.offsets, j.ncells);
+  } else {
+    const int chunks = scan_chunks(j.ncells);
+    int *sums = j.offsets + j.ncells + 1;
+    launch_on(timing, k_bin_scan_sums, chunks, kThreads, 0, j.stream, j.counts, j.ncells, sums);
+    launch_on(timing, k_bin_scan_apply, chunks, kThreads, 0, j.stream, j.counts, j.offsets,
+              j.ncells, sums);
+  }
   if (timing) stage_end(*timing, SE_STAGE_BIN_SCAN);
   if ((e = hipGetLastError()) != hipSuccess || N == 0) return e;
   if (timing) stage_begin(*timing, SE_STAGE_BIN_SCATTER);

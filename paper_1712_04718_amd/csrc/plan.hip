@@ -173,7 +173,7 @@ Sizes sizes_of(const se_params &p, int n_max, int ntiles, int bin_blocks, int zb
   s.meta = al(n * 8);
   s.key = al(n * 8);
   s.counts = al(static_cast<size_t>(ntiles) * sek::kCountStride * 4);
-  s.offsets = al((ntiles + 1) * 4);
+  s.offsets = al((ntiles + 1 + sek::scan_chunks(ntiles)) * 4);
   s.part = al((bin_blocks + zblocks) * 8);
   s.tw = al(M * 2 * rs);
   s.f = al(M * 8);
@@ -626,7 +626,8 @@ se_status se_plan_reserve_targets(se_plan *plan, int nt_max) {
   const size_t n = static_cast<size_t>(nt_max);
   struct { void **ptr; size_t bytes; } allocs[] = {
       {reinterpret_cast<void **>(&t.counts), static_cast<size_t>(std::max(plan->ntiles, 1)) * sek::kCountStride * 4},
-      {reinterpret_cast<void **>(&t.offsets), static_cast<size_t>(plan->ntiles + 1) * 4},
+      {reinterpret_cast<void **>(&t.offsets),
+       static_cast<size_t>(plan->ntiles + 1 + sek::scan_chunks(plan->ntiles)) * 4},
       {reinterpret_cast<void **>(&t.key), n * 8},
       {reinterpret_cast<void **>(&t.meta), n * 8},
       {&t.sorted, n * 4 * rs},

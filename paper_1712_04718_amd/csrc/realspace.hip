@@ -494,7 +494,8 @@ se_status se_rs_plan_create(double L, double xi, double rc, int dtype, int n_max
   const size_t rs = dtype == SE_FP64 ? 8 : 4;
   struct { void **ptr; size_t n; } allocs[] = {
       {reinterpret_cast<void **>(&p->counts), cells_max * sek::kCountStride * 4},
-      {reinterpret_cast<void **>(&p->offsets), (cells_max + 1) * 4},
+      {reinterpret_cast<void **>(&p->offsets),
+       (cells_max + 1 + static_cast<size_t>(sek::scan_chunks(static_cast<int>(cells_max)))) * 4},
       {reinterpret_cast<void **>(&p->key), static_cast<size_t>(n_max) * 8},
       {reinterpret_cast<void **>(&p->meta), static_cast<size_t>(n_max) * 8},
       {&p->sorted, static_cast<size_t>(n_max) * 4 * rs},

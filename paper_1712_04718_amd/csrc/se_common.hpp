@@ -338,4 +338,11 @@ constexpr int fft_lgb(int M, int real_size, int pass) {
 // same line serialise, on different lines they proceed in parallel.
 constexpr int kCountStride = 32;
 
+// Cells per work-group of the two-level scan of the cell counts (taken above
+// kScanOneGroupMax cells); the offsets array of a binning holds
+// ncells + 1 + scan_chunks(ncells) ints, the chunk sums after the offsets.
+constexpr int kScanChunk = 2048;
+constexpr int kScanOneGroupMax = 2048;
+constexpr int scan_chunks(int ncells) { return (ncells + kScanChunk - 1) / kScanChunk; }
+
 }  // namespace sek
