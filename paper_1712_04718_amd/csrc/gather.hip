@@ -421,10 +421,9 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
     const R tx0 = kj - sp.dx, ty0 = kj - sp.dy, tz0 = kj - sp.dz;
     R gx;
     if constexpr (sizeof(R) == 4) {
-      const float c2 = wc.cgl2;
-      gx = beta * exp2_fast(-c2 * tx0 * tx0);
-      gslot[jx] = beta * exp2_fast(-c2 * ty0 * ty0);
-      gslot[S + jx] = beta * exp2_fast(-c2 * tz0 * tz0);
+      gx = gauss_factor(beta, wc.cgl2, jx + OFF, sp.dx);
+      gslot[jx] = gauss_factor(beta, wc.cgl2, jx + OFF, sp.dy);
+      gslot[S + jx] = gauss_factor(beta, wc.cgl2, jx + OFF, sp.dz);
     } else {
       gx = beta * exp(-cg * tx0 * tx0);
       gslot[jx] = beta * exp(-cg * ty0 * ty0);

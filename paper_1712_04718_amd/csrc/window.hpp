@@ -44,31 +44,39 @@ struct WindowConsts {
   double beta;   // per-axis Gaussian normalisation (SE)
   double kap;    // exp(-2 cg), ratio of successive recurrence factors (SE)
   double dcoef;  // SE: 2 a h; SPME: 1/h   (derivative scale)
-  float ck[kMaxHalfSupport + 1];  // exp(-cg k^2), k = 0..S/2 (SE, FP32)
-  float cgl2;    // cg log2(e): FP32 factors as beta 2^{-cgl2 t^2} (SE)
+  float rk[kMaxHalfSupport + 1];  // exp(-cg (2m + 1)), m = 0..S/2 (SE, FP32)
+  double cgl2;   // cg log2(e): FP32 factors as beta 2^{-cgl2 t^2} (SE)
 };
 
 // e^{-cg t^2} in FP32 as 2^{-cgl2 t^2} with the hardware base-2 exponential
-// (v_exp_f32, about 1 ulp): the rounding of the argument, which any FP32
-// evaluation shares, dominates its error.
+// (v_exp_f32: within 0.8 ulp, mean error -3e-9 relative, over [-12, 4)).
 __device__ inline float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// One FP32 Gaussian factor beta e^{-cg t^2} at t = k - d (k an integer
+// offset, d in [0,1)): t, t^2 and the exponent are formed in FP64 (t exact,
+// two roundings of 1e-16), the exponent is rounded once to FP32, then the
+// hardware exp2.  The error is about one ulp of the factor plus its
+// exponent's rounding, 6e-8 |ln g|, smallest where the factors are largest.
+__device__ inline float gauss_factor(float beta, double cgl2, int k, float d) {
+  const double t = static_cast<double>(k) - static_cast<double>(d);
+  return beta * exp2_fast(static_cast<float>(-cgl2 * t * t));
+}
+
 inline WindowConsts window_consts(double cg, double beta, double dcoef) {
-  WindowConsts wc{cg, beta, std::exp(-2.0 * cg), dcoef, {}, static_cast<float>(cg * M_LOG2E)};
-  for (int k = 0; k <= kMaxHalfSupport; ++k)
-    wc.ck[k] = static_cast<float>(std::exp(-cg * static_cast<double>(k) * k));
+  WindowConsts wc{cg, beta, std::exp(-2.0 * cg), dcoef, {}, cg * M_LOG2E};
+  for (int m = 0; m <= kMaxHalfSupport; ++m)
+    wc.rk[m] = static_cast<float>(std::exp(-cg * (2.0 * m + 1.0)));
   return wc;
 }
 
 // All S factors of one axis (and optionally their derivatives).
 //
-// FP32 writes each Gaussian factor around the anchor point as A B^k C_k
-// (three exponentials per axis, products built outward from the largest
-// factor, so rounding grows only towards the small tail factors): the
-// recurrence of eqs. (4.10)-(4.11) started at the stencil end would pass the
-// relative rounding of its first, smallest factor on to the large central
-// ones.  FP64 uses that recurrence, whose accumulated rounding stays near
-// 1e-15.
+// FP32 evaluates the four central Gaussian factors directly and builds the
+// tail outward from them (six exponentials per axis for any support, and
+// rounding grows only towards the small tail factors): the recurrence of
+// eqs. (4.10)-(4.11) started at the stencil end would pass the relative
+// rounding of its first, smallest factor on to the large central ones.
+// FP64 uses that recurrence, whose accumulated rounding stays near 1e-15.
 template <typename R, int WIN, int S, bool DERIV>
 __device__ inline void window_axis(R d, const WindowConsts &wc, R (&g)[S], R (&dg)[S]) {
   if constexpr (WIN == kGauss) {
@@ -76,28 +84,29 @@ __device__ inline void window_axis(R d, const WindowConsts &wc, R (&g)[S], R (&d
     const R cg = static_cast<R>(wc.cg);
     const R beta = static_cast<R>(wc.beta);
     if constexpr (sizeof(R) == 4) {
-      // With k = j + OFF (k = 0 at the anchor), t_j = k - d and
-      //   g_j = beta e^{-cg (k - d)^2} = A B^k C_k,
-      //   A = beta e^{-cg d^2},  B = e^{2 cg d},  C_k = e^{-cg k^2} (a table),
-      // so an axis needs three exponentials; the powers of B (or of 1/B for
-      // k < 0) are built outward from the anchor, where the factors are
-      // largest, and gain about one rounding per step.
+      // With k = j + OFF (k = 0 at the anchor) and t_k = k - d, the four
+      // factors nearest the centre (k = -1..2), which carry most of the
+      // weight, are evaluated directly by gauss_factor; the rest outward by
+      //   g_{k+1} = g_k B e^{-cg (2k + 1)}   (k >= 2),
+      //   g_{k-1} = g_k B^{-1} e^{-cg (1 - 2k)}   (k <= -1),   B = e^{2 cg d},
+      // two roundings per step on factors below e^{-cg 4}.  Rounding in a
+      // product of separately rounded exponentials (beta e^{-cg d^2} B^k
+      // e^{-cg k^2}) costs about twice the error of the direct form at
+      // k = 1, where that form's intermediate exponents are largest.
       constexpr int J0 = -OFF;  // index of the anchor point
-      const float c2 = wc.cgl2;
-      const R A = beta * exp2_fast(-c2 * d * d);
-      const R Bu = exp2_fast(2.0f * c2 * d), Bd = exp2_fast(-2.0f * c2 * d);
-      g[J0] = A;
-      R p = A;
 #pragma unroll
-      for (int k = 1; J0 + k < S; ++k) {
-        p *= Bu;
-        g[J0 + k] = p * wc.ck[k];
+      for (int k = -1; k <= 2; ++k)
+        if (J0 + k >= 0 && J0 + k < S) g[J0 + k] = gauss_factor(beta, wc.cgl2, k, d);
+      const float eb = static_cast<float>(2.0 * wc.cgl2 * static_cast<double>(d));
+      if constexpr (J0 + 3 < S) {
+        const R Bu = exp2_fast(eb);
+#pragma unroll
+        for (int k = 2; J0 + k + 1 < S; ++k) g[J0 + k + 1] = g[J0 + k] * Bu * wc.rk[k];
       }
-      p = A;
+      if constexpr (J0 - 2 >= 0) {
+        const R Bd = exp2_fast(-eb);
 #pragma unroll
-      for (int k = 1; k <= J0; ++k) {
-        p *= Bd;
-        g[J0 - k] = p * wc.ck[k];
+        for (int m = 1; J0 - m - 1 >= 0; ++m) g[J0 - m - 1] = g[J0 - m] * Bd * wc.rk[m];
       }
       if constexpr (DERIV) {
 #pragma unroll
