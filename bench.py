@@ -251,6 +251,99 @@ def summarize_counters(fetch_dir, write_dir, fetch_log, write_log):
     print("\n".join(md))
 
 
+def _short_name(name):
+    """A kernel's name without its namespace, return type and arguments."""
+    name = name.replace("sek::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    return name.split("(")[0]
+
+
+SQ_PASSES = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS "
+             "SQ_WAIT_INST_LDS SQ_INSTS_VALU SQ_INSTS_LDS",
+             "SQ_WAVES SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE SQ_WAIT_ANY SQ_ACTIVE_INST_ANY "
+             "SQ_INSTS_LDS_ATOMIC SQ_BUSY_CU_CYCLES GRBM_GUI_ACTIVE")
+
+
+def summarize_sq(dir1, dir2, bench_log):
+    """Turn the two rocprofv3 --pmc passes of SQ_PASSES over this script into
+    per-launch means for each k-space stage's FP32 kernels: instruction mix,
+    the shares of the waves' resident cycles spent issuing VALU work or
+    waiting (on LDS issue, on anything), and the share of the LDS pipe's
+    active cycles lost to bank conflicts.  Writes
+    profiles/counters_sq_<workload>_<window>_P<P>_f32.md."""
+    line = _bench_line(bench_log)
+    if line is None:
+        raise SystemExit("no bench.py JSON line in the counter run's log")
+    workload, P, window, M, N = _workload_of(line)
+    rows = _csv_rows(dir1, "counter_collection.csv") + _csv_rows(dir2, "counter_collection.csv")
+
+    def mean(pat, counter):
+        v = [float(r["Counter_Value"]) for r in rows
+             if r["Counter_Name"] == counter and re.search(pat, r["Kernel_Name"])]
+        return sum(v) / len(v) if v else None
+
+    def share(a, b):
+        return f"{a / b:.2f}" if a is not None and b else "-"
+
+    cmd = line.get("command", "python3 bench.py")
+    md = [f"# SQ counters per launch: {workload} (N={N}, M={M}, {window} window, P={P}), FP32\n",
+          "Two `rocprofv3 --pmc` passes over the FP32 bench; means per dispatch of each "
+          "stage's kernels.\n", "```"]
+    md += [f"cd /tmp && rocprofv3 --pmc {ps} -f csv -d <out-dir> -o bench -- {cmd}"
+           for ps in SQ_PASSES]
+    md += ["```\n",
+           "Shares are ratios of counters in the same units: of the waves' resident cycles "
+           "(SQ_WAVE_CYCLES) those issuing VALU work, waiting to issue an LDS instruction, or "
+           "waiting on anything; of the LDS pipe's active cycles (SQ_LDS_IDX_ACTIVE) those lost "
+           "to bank conflicts.\n",
+           "| stage | waves | VALU insts / wave | LDS insts / wave | LDS atomic insts | "
+           "VALU-active share | LDS-wait share | any-wait share | LDS bank-conflict share |",
+           "|---|---|---|---|---|---|---|---|---|"]
+    for st, pat in STAGE_KERNEL_RE.items():
+        c = {k: mean(pat, k) for k in ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_ACTIVE_INST_VALU",
+                                        "SQ_WAIT_INST_LDS", "SQ_INSTS_VALU", "SQ_INSTS_LDS",
+                                        "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE",
+                                        "SQ_WAIT_ANY", "SQ_INSTS_LDS_ATOMIC")}
+        if not c["SQ_WAVES"] or not c["SQ_WAVE_CYCLES"]:
+            continue
+        w, cyc = c["SQ_WAVES"], c["SQ_WAVE_CYCLES"]
+        md.append(f"| {st} | {w:.0f} | {(c['SQ_INSTS_VALU'] or 0) / w:.0f} | "
+                  f"{(c['SQ_INSTS_LDS'] or 0) / w:.0f} | {c['SQ_INSTS_LDS_ATOMIC'] or 0:.0f} | "
+                  f"{share(c['SQ_ACTIVE_INST_VALU'], cyc)} | {share(c['SQ_WAIT_INST_LDS'], cyc)} | "
+                  f"{share(c['SQ_WAIT_ANY'], cyc)} | "
+                  f"{share(c['SQ_LDS_BANK_CONFLICT'], c['SQ_LDS_IDX_ACTIVE'])} |")
+    base = os.path.join(PROFILES, f"counters_sq_{workload}_{window}_P{P}_f32")
+    with open(base + ".md", "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
+def summarize_lds_probe(log_path):
+    """Store the LDS-atomic probe's output (paper_1712_04718_amd/probes/
+    lds_atomic_rate.hip) as profiles/lds_atomic_rate.{json,md}; the JSON is
+    what lds_atomic_peak() reads."""
+    with open(log_path) as f:
+        text = f.read().splitlines()
+    rec = next((json.loads(t) for t in text if t.startswith("{")), None)
+    if rec is None:
+        raise SystemExit("no JSON line in the probe's output")
+    build = ("hipcc --offload-arch=gfx950 -O3 paper_1712_04718_amd/probes/lds_atomic_rate.hip "
+             "-o lds_atomic_rate && ./lds_atomic_rate")
+    rec["command"] = build
+    with open(os.path.join(PROFILES, "lds_atomic_rate.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    md = ["# LDS integer-atomic rate in the spread's access pattern\n",
+          "A 19^3 block of 32-bit integers per 512-thread work-group, each lane adding 64 "
+          "values (8 x 8 rows at a random anchor) with `ds_add_u32`, as the Gaussian spread "
+          "does; plain integers, float products rounded to integers (the spread's fixed-point "
+          "step), and a conflict-free pattern for reference.\n",
+          "```", build, "```\n", "```"] + [t for t in text if not t.startswith("{")] + ["```"]
+    with open(os.path.join(PROFILES, "lds_atomic_rate.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def summarize_trace(trace_dir, bench_log):
     """Turn a rocprofv3 --kernel-trace --stats run of bench.py into mean
     kernel durations per stage (FP32 instantiations, every dispatch of the
@@ -283,7 +376,7 @@ def summarize_trace(trace_dir, bench_log):
             continue
         calls = sum(int(r["Calls"]) for r in rows)
         total_ns = sum(float(r["TotalDurationNs"]) for r in rows)
-        rec["stages"][st] = {"kernels": [r["Name"].split("(")[0] for r in rows], "calls": calls,
+        rec["stages"][st] = {"kernels": [_short_name(r["Name"]) for r in rows], "calls": calls,
                              "mean_us": total_ns / calls / 1e3,
                              "min_us": min(float(r["MinNs"]) for r in rows) / 1e3,
                              "source_sha256_16": hashes.get(st, source_hash(st))}
@@ -291,7 +384,7 @@ def summarize_trace(trace_dir, bench_log):
           "```", f"cd /tmp && {rec['command']}", "```\n",
           "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
-        name = r["Name"].split("(")[0].replace("sek::(anonymous namespace)::", "")
+        name = _short_name(r["Name"])
         md.append(f"| `{name[:100]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                   f"{float(r['Percentage']):.1f} |")
@@ -853,7 +946,18 @@ def main():
     ap.add_argument("--trace-from", nargs=2, metavar=("TRACE_DIR", "LOG"),
                     help="summarize a rocprofv3 --kernel-trace --stats run of this script "
                          "into profiles/ (host only)")
+    ap.add_argument("--sq-from", nargs=3, metavar=("PASS1_DIR", "PASS2_DIR", "LOG"),
+                    help="summarize the two SQ counter passes (SQ_PASSES) of this script into "
+                         "profiles/ (host only)")
+    ap.add_argument("--lds-probe-from", metavar="LOG",
+                    help="store the LDS-atomic probe's output in profiles/ (host only)")
     args = ap.parse_args()
+    if args.sq_from:
+        summarize_sq(*args.sq_from)
+        return
+    if args.lds_probe_from:
+        summarize_lds_probe(args.lds_probe_from)
+        return
     if args.traffic_from:
         summarize_counters(*args.traffic_from)
         return
