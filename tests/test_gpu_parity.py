@@ -121,6 +121,39 @@ def test_dense_cluster(dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("N", [16384, 40001])
+def test_many_particles_per_tile(N, dtype):
+    """Tiles holding 256 particles or more on average (64 tiles at M = 32):
+    the binning then ranks 8192 particles per counting work-group in LDS
+    before one global atomic per touched tile; N = 40001 leaves a ragged
+    last work-group of 7233 particles."""
+    x, q = _rand(N, 10.0, 77 + N)
+    _parity(x, q, 10.0, 1.2, 32, 8, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_coincident_charges(dtype):
+    """Thousands of equal charges on one point, and opposite charges on a
+    point of the same (y, z) anchor column: the partial sums of the tile's
+    fixed-point block can reach the charge bound in any order of the atomics,
+    so a bound that missed a column's charge would overflow here (errors of
+    order one).  FP32 is held to 5e-5: the 1500 identical contributions at a
+    grid point round identically, so their fixed-point and FP32 roundings add
+    up instead of averaging out (a CPU emulation of the 30-bit fixed point
+    alone, with exact factors, gives phi 1.1e-5, F 2.3e-6, E 3.5e-6)."""
+    L, M = 10.0, 32
+    h = L / M
+    p1 = np.array([3.1 * h + 2.0, 5.4 * h + 2.0, 6.7 * h + 2.0])
+    p2 = p1 + np.array([2.3 * h, 0.0, 0.0])
+    p3 = p1 + np.array([0.0, 0.2 * h, -0.3 * h])
+    x = np.concatenate([np.tile(p1, (1500, 1)), np.tile(p2, (1500, 1)), np.tile(p3, (700, 1)),
+                        np.random.default_rng(9).random((300, 3)) * L])
+    q = np.concatenate([np.full(1500, 1.0), np.full(1500, -1.0), np.full(700, 0.5),
+                        np.random.default_rng(10).standard_normal(300)])
+    _parity(x, q, L, 1.2, M, 8, dtype, tol=5e-5 if dtype == torch.float32 else None)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_single_and_non_neutral(dtype):
     """N = 1 and a non-neutral set: k = 0 is dropped, nothing else changes.
     A lone charge feels no k-space force in the exact sum, so its tiny
