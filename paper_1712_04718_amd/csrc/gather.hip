@@ -9,16 +9,16 @@
 // One work-group per tile: the (T+S-1)^3 block of the scaled grid Phi that
 // the tile's particles touch is staged in LDS.  Lane (group, jx) of a wave's
 // 64/S particle groups owns the x-offset jx of one particle and sums over
-// the S^2 (jy, jz) offsets; the S lanes of a particle are then combined
-// (shuffle tree for S = 4, 8, 16; in LDS, compensated, otherwise).
+// the S^2 (jy, jz) offsets, its sums over jy compensated (Kahan); the S
+// lanes of a particle are then combined (shuffle tree for S = 4, 8, 16; in
+// LDS, compensated, otherwise).
 //   Gaussian window (k_gather_lane): the waves take the tile's particles in
 //     a strided loop with no block barrier; each lane evaluates its three
 //     factors (x, y, z at its own offset) and shares the y and z ones with
 //     its group through a per-wave LDS slot.
 //   B-spline window (k_gather): the particles are taken in chunks of one per
 //     thread; phase A computes each particle's factors and derivatives into
-//     LDS (the order-p recursion per axis), phase B sums as above, with the
-//     per-lane sums over y compensated (Kahan).
+//     LDS (the order-p recursion per axis), phase B sums as above.
 // For the Gaussian the derivative sums are rearranged around the stencil
 // centre (see k_gather_lane).
 #include "se_common.hpp"
@@ -447,7 +447,7 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
     const int packed = mt.x;
     const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
     const R *col = blk + (az * TS + ay) * TS + ax + jx;
-    R s0 = R(0), s1 = R(0), s2 = R(0);
+    Kahan<R> k0, k1, k2;
 #pragma unroll
     for (int jy = 0; jy < S; ++jy) {
       R a0 = R(0), b1 = R(0);
@@ -457,10 +457,11 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
         a0 += v * gz[jz];
         b1 += v * cz[jz];
       }
-      s0 += gy[jy] * a0;  // sum g_y g_z Phi
-      s1 += cy[jy] * a0;  // sum c_y g_y g_z Phi
-      s2 += gy[jy] * b1;  // sum g_y c_z g_z Phi
+      k0.add(gy[jy] * a0);  // sum g_y g_z Phi
+      k1.add(cy[jy] * a0);  // sum c_y g_y g_z Phi
+      k2.add(gy[jy] * b1);  // sum g_y c_z g_z Phi
     }
+    const R s0 = k0.value(), s1 = k1.value(), s2 = k2.value();
     const R ey = sp.dy - R(0.5), ez = sp.dz - R(0.5);
     const R dgx = dc * tx0 * gx;
     R t0 = gx * s0, t1 = dgx * s0, t2 = dc * gx * (s1 - ey * s0), t3 = dc * gx * (s2 - ez * s0);
