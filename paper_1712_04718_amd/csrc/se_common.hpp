@@ -314,18 +314,24 @@ constexpr int tile_chunk(long long per_particle, long long fixed_bytes) {
 // Most pencils per FFT work-group, per pass.  Lanes run over the B pencils
 // fastest, so a wave reads 64 / B consecutive elements of each pencil: the
 // y pencils are contiguous and B = 4 gives whole 128-byte lines with many
-// work-groups in flight; x rows and z columns take B = 8.
+// work-groups in flight.  x rows take B = 4 as well (at M = 192 the FP32 x
+// pass took 13.4 instead of 15.9 us, at M = 432 164 instead of 220 us, the
+// inverse x pass 212 instead of 308 us); FP32 z columns take B = 8 (22.5
+// against 24.6 us at M = 192), FP64 ones B = 4 (33.6 against 41.6 us, the
+// LDS per work-group halved).
 enum FftPass { kPassX = 0, kPassY = 1, kPassZ = 2 };
-constexpr int kFftBatchCap[3] = {8, 4, 8};
+constexpr int fft_batch_cap(int pass, int real_size) {
+  return pass == kPassZ && real_size == 4 ? 8 : 4;
+}
 
 // Pencils per FFT work-group of one pass, as log2: B a power of two, at most
-// kFftBatchCap[pass], with M * B <= 16 * kThreads (elements per thread when
+// fft_batch_cap(pass, real_size), with M * B <= 16 * kThreads (elements per thread when
 // loading) and two LDS buffers of M x B complex plus the M twiddles (and,
 // in the z pass, the two FP64 axis tables of the influence function)
 // within 64 KB.
 constexpr int fft_lgb(int M, int real_size, int pass) {
   const int tables = pass == kPassZ ? 2 * 8 * M : 0;
-  int B = kFftBatchCap[pass];
+  int B = fft_batch_cap(pass, real_size);
   while (B > 1 &&
          (M * B > 16 * kThreads || (2 * M * B + M) * 2 * real_size + tables > 65536))
     B >>= 1;
