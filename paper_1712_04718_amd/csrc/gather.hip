@@ -322,12 +322,17 @@ k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ s
 // LDS of the Gaussian gather (k_gather_lane): the tile block, the lane
 // partials (supports that are not a power of two), per-wave factor slots
 // (64/S groups of 2S values each) and the offset tables.
+// LDS of k_gather_lane: the block of Phi, the lane-sum slots (S not a power
+// of two), then one region that holds the staging tables (row and column
+// offsets) until the block barrier and the groups' factor slots after it;
+// sharing it keeps three 16-point-tile work-groups within a CU's LDS.
 constexpr size_t gather_lane_lds(int real_size, int S, int T) {
   const size_t TS = T + S - 1;
+  const size_t wf = static_cast<size_t>(real_size) * (kTileThreads / 64) * (64 / S) * 2 * S;
+  const size_t tables = 4 * (TS * TS + TS);
   return real_size * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) +
          ((S & (S - 1)) ? static_cast<size_t>(real_size) * kTileThreads * 4 : 0) +
-         static_cast<size_t>(real_size) * (kTileThreads / 64) * (64 / S) * 2 * S +
-         4 * (TS * TS + TS);
+         (wf > tables ? wf : tables);
 }
 
 // Gaussian window.  The block of Phi is staged as in k_gather; then each
@@ -350,15 +355,16 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
   constexpr bool POW2 = (S & (S - 1)) == 0;
   constexpr size_t BLK = sizeof(R) * ((TS3 + 3) & ~3);
   constexpr size_t RED = POW2 ? 0 : sizeof(R) * kTileThreads * 4;
-  constexpr size_t WF = sizeof(R) * NWAVES * GROUPS * 2 * S;
 
   const int tile = xcd_local(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   R *blk = reinterpret_cast<R *>(h_smem);
   R *red = reinterpret_cast<R *>(h_smem + BLK);
+  // the staging tables and the factor slots share one region: the tables
+  // are last read before the block barrier, the slots first written after it
   R *wfac = reinterpret_cast<R *>(h_smem + BLK + RED);
-  int *rowtab = reinterpret_cast<int *>(h_smem + BLK + RED + WF), *xtab = rowtab + TS * TS;
+  int *rowtab = reinterpret_cast<int *>(h_smem + BLK + RED), *xtab = rowtab + TS * TS;
 
   // Stage the block (batched loads into registers, then LDS stores; grid
   // offsets from row and column tables), as k_gather does.
