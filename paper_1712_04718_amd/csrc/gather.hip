@@ -12,15 +12,14 @@
 // the S^2 (jy, jz) offsets, its sums over jy compensated (Kahan); the S
 // lanes of a particle are then combined (shuffle tree for S = 4, 8, 16; in
 // LDS, compensated, otherwise).
-//   Gaussian window (k_gather_lane): the waves take the tile's particles in
-//     a strided loop with no block barrier; each lane evaluates its three
-//     factors (x, y, z at its own offset) and shares the y and z ones with
-//     its group through a per-wave LDS slot.
-//   B-spline window (k_gather): the particles are taken in chunks of one per
-//     thread; phase A computes each particle's factors and derivatives into
-//     LDS (the order-p recursion per axis), phase B sums as above.
-// For the Gaussian the derivative sums are rearranged around the stencil
-// centre (see k_gather_lane).
+// After the block barrier the waves take the tile's particles in a strided
+// loop with no further block barrier (k_gather_lane):
+//   Gaussian window: each lane evaluates three factors (x, y, z at its own
+//     offset) and shares the y and z ones with its group through a per-wave
+//     LDS slot; the derivative sums are rearranged around the stencil centre;
+//   B-spline window: lanes 0, 1 and 2 of a group run the order-p recursion
+//     (section 6.1) for x, y and z with its derivatives and share all of
+//     them through the slot.
 #include "se_common.hpp"
 #include "window.hpp"
 
@@ -40,309 +39,30 @@ template <typename R> struct Kahan {
   __device__ inline R value() const { return s - c; }
 };
 
-constexpr int gather_rec(int window, int S) { return window == kGauss ? 3 * S + 4 : 6 * S + 1; }
-// LDS of a gathering work-group besides its factor table and indices: the
-// tile block, the lane partials (supports that are not a power of two) and
-// the offset tables
-constexpr long long gather_fixed_bytes(int real_size, int S, int T) {
-  const long long ts = T + S - 1;
-  return real_size * ((ts * ts * ts + 3) & ~3LL) +
-         ((S & (S - 1)) ? static_cast<long long>(real_size) * kTileThreads * 4 : 0) +
-         4 * (ts * ts + ts);
-}
-// particles per phase-A round (tile_chunk): factors plus two indices each
-constexpr int gather_chunk(int real_size, int window, int S, int T) {
-  return tile_chunk(static_cast<long long>(real_size) * gather_rec(window, S) + 8,
-                    gather_fixed_bytes(real_size, S, T));
-}
-
-// LDS layout: [tile block][lane partials][factors][anchors][original indices]
-template <typename R, int WIN, int S, int T> struct GatherLds {
-  static constexpr int TS = T + S - 1;
-  // SE: g (3S), offsets d (3), q; B-spline: g (3S), dg (3S), q
-  static constexpr int REC = gather_rec(WIN, S);
-  static constexpr int CHUNK = gather_chunk(sizeof(R), WIN, S, T);
-  static constexpr size_t BLK = sizeof(R) * ((TS * TS * TS + 3) & ~3);
-  // lane partials, only for supports that are not a power of two
-  static constexpr size_t RED = (S & (S - 1)) ? sizeof(R) * kTileThreads * 4 : 0;
-  static constexpr size_t FAC = sizeof(R) * CHUNK * REC;
-  static constexpr size_t IDX = 2 * sizeof(int) * CHUNK;
-  // grid offsets of the block's rows (z, y) and wrapped x coordinates
-  static constexpr size_t TAB = sizeof(int) * (TS * TS + TS);
-  static constexpr size_t TOTAL = BLK + RED + FAC + IDX + TAB;
-  static_assert(BLK + RED + TAB == static_cast<size_t>(gather_fixed_bytes(sizeof(R), S, T)),
-                "LDS layout and chunk rule disagree");
-};
-
-template <typename R, int WIN, int S, int T>
-__global__ void __launch_bounds__(kTileThreads)
-k_gather(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ sorted,
-         const int2 *__restrict__ meta, const int *__restrict__ offsets, int M, int ntx,
-         WindowConsts wc, const double *__restrict__ gscale, int mode, R self_coef,
-         R *__restrict__ out_pot, R *__restrict__ out_vec) {
-  using L = GatherLds<R, WIN, S, T>;
-  constexpr int TS = L::TS, REC = L::REC, CHUNK = L::CHUNK;
-  constexpr int GROUPS = 64 / S;
-  constexpr int OFF = Stencil<WIN, S>::OFF;
-  constexpr int NWAVES = kTileThreads / 64;
-  constexpr bool POW2 = (S & (S - 1)) == 0;
-
-  const int tile = xcd_local(blockIdx.x, gridDim.x);
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  R *blk = reinterpret_cast<R *>(h_smem);
-  R *red = reinterpret_cast<R *>(h_smem + L::BLK);
-  R *fac = reinterpret_cast<R *>(h_smem + L::BLK + L::RED);
-  int *anc = reinterpret_cast<int *>(h_smem + L::BLK + L::RED + L::FAC);
-  int *org = anc + CHUNK;
-  int *rowtab = org + CHUNK, *xtab = rowtab + TS * TS;
-
-  // Stage the block: loads are issued in unrolled batches into registers and
-  // only then written to LDS, so a thread has a batch of loads in flight
-  // instead of waiting for each one in turn.  An element's grid offset is
-  // the offset of its (z, y) row plus its wrapped x, both from small tables
-  // built first: one division by TS and two table reads per element instead
-  // of three divisions and three wraps.  The tile's particle range is read
-  // while the tables are built; its first round of particles is read, and
-  // their window factors computed, while the block loads are in flight.
-  const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
-  const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
-  constexpr int TS3 = TS * TS * TS;
-  constexpr int NST = (TS3 + kTileThreads - 1) / kTileThreads;  // elements per thread
-  constexpr int BATCH = sizeof(R) == 4 ? 16 : 8;
-  const int start = offsets[tile], end = offsets[tile + 1];
-  for (int r = tid; r < TS * TS; r += kTileThreads) {
-    const int lz = r / TS, ly = r - lz * TS;
-    rowtab[r] = (wrap_near(bz + lz, M) * M + wrap_near(by + ly, M)) * M;
-  }
-  if (tid < TS) xtab[tid] = wrap_near(bx + tid, M);
-  __syncthreads();
-  const auto load_batch = [&](int k0, R (&v)[BATCH]) {
-#pragma unroll
-    for (int k = 0; k < BATCH; ++k) {
-      const int i = tid + (k0 + k) * kTileThreads;
-      if (k0 + k < NST && i < TS3) {
-        const int r = i / TS, lx = i - r * TS;
-        v[k] = phi_grid[rowtab[r] + xtab[lx]];
-      }
-    }
-  };
-  const auto store_batch = [&](int k0, const R (&v)[BATCH]) {
-#pragma unroll
-    for (int k = 0; k < BATCH; ++k) {
-      const int i = tid + (k0 + k) * kTileThreads;
-      if (k0 + k < NST && i < TS3) blk[i] = v[k];
-    }
-  };
-  // phase A: the window factors of one particle (its own thread) into LDS
-  const auto phase_a = [&](const SortedParticle<R> &sp, const int2 &mt) {
-    R *f = fac + tid * REC;
-    R g[S], dg[S];
-    const R dd[3] = {sp.dx, sp.dy, sp.dz};
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      window_axis<R, WIN, S, WIN == kBspline>(dd[ax], wc, g, dg);
-#pragma unroll
-      for (int j = 0; j < S; ++j) f[ax * S + j] = g[j];
-      if constexpr (WIN == kBspline) {
-#pragma unroll
-        for (int j = 0; j < S; ++j) f[3 * S + ax * S + j] = dg[j];
-      } else {
-        f[3 * S + ax] = dd[ax];
-      }
-    }
-    f[REC - 1] = sp.q;
-    anc[tid] = mt.x;
-    org[tid] = mt.y;
-  };
-  R v0[BATCH];
-  load_batch(0, v0);
-  SortedParticle<R> sp0{};
-  int2 mt0 = make_int2(0, 0);
-  const int nval0 = min(CHUNK, end - start);
-  if (tid < nval0) {
-    sp0 = sorted[start + tid];
-    mt0 = meta[start + tid];
-  }
-  if (start == end) return;  // uniform across the work-group
-  // the first round's factors are computed while the block loads are in flight
-  if (tid < nval0) phase_a(sp0, mt0);
-  store_batch(0, v0);
-#pragma unroll
-  for (int k0 = BATCH; k0 < NST; k0 += BATCH) {
-    R v[BATCH];
-    load_batch(k0, v);
-    store_batch(k0, v);
-  }
-
-  const R scale = gscale ? static_cast<R>(*gscale) : R(1);
-  const int grp = lane / S, jx = lane - grp * S;
-  R *wred = red + wave * 64 * 4;
-  for (int base = start; base < end; base += CHUNK) {
-    const int nval = min(CHUNK, end - base);
-    if (base != start) {
-      __syncthreads();  // previous round done with the factors
-      if (tid < nval) phase_a(sorted[base + tid], meta[base + tid]);
-    }
-    __syncthreads();
-    // phase B: particle groups of S lanes across the work-group
-    if (grp < GROUPS) {
-      for (int c = wave * GROUPS + grp; c < nval; c += NWAVES * GROUPS) {
-        const R *f = fac + c * REC;
-        const int packed = anc[c];
-        const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
-        R t0, t1, t2, t3;  // this lane's parts of phi, and of F / (-q) along x, y, z
-        if constexpr (WIN == kGauss) {
-          // d/dx_m of a Gaussian factor is dc (j + OFF - d) g_j.  With the
-          // centred weights c_j = j + OFF - 1/2 and e = d - 1/2 (|e| <= 1/2):
-          //   sum_j (j + OFF - d) g_j a_j = sum_j c_j g_j a_j - e sum_j g_j a_j,
-          // so the derivative needs one extra weighted sum per axis.
-          const R dc = static_cast<R>(wc.dcoef);
-          const R gx = f[jx];
-          const R ex = f[3 * S + 0] - R(0.5), ey = f[3 * S + 1] - R(0.5), ez = f[3 * S + 2] - R(0.5);
-          R gy[S], gz[S], cy[S], cz[S];
-#pragma unroll
-          for (int j = 0; j < S; ++j) {
-            gy[j] = f[S + j];
-            gz[j] = f[2 * S + j];
-            cy[j] = (static_cast<R>(j + OFF) - R(0.5)) * gy[j];
-            cz[j] = (static_cast<R>(j + OFF) - R(0.5)) * gz[j];
-          }
-          const R *col = blk + (az * TS + ay) * TS + ax + jx;
-          R s0 = R(0), s1 = R(0), s2 = R(0);
-#pragma unroll
-          for (int jy = 0; jy < S; ++jy) {
-            R a0 = R(0), b1 = R(0);
-#pragma unroll
-            for (int jz = 0; jz < S; ++jz) {
-              const R v = col[(jz * TS + jy) * TS];
-              a0 += v * gz[jz];
-              b1 += v * cz[jz];
-            }
-            s0 += gy[jy] * a0;  // sum g_y g_z Phi
-            s1 += cy[jy] * a0;  // sum c_y g_y g_z Phi
-            s2 += gy[jy] * b1;  // sum g_y c_z g_z Phi
-          }
-          const R dgx = dc * (static_cast<R>(jx + OFF) - f[3 * S + 0]) * gx;
-          t0 = gx * s0;
-          t1 = dgx * s0;
-          t2 = dc * gx * (s1 - ey * s0);
-          t3 = dc * gx * (s2 - ez * s0);
-          (void)ex;
-        } else {
-          const R gx = f[jx], dgx = f[3 * S + jx];
-          R gy[S], dgy[S], gz[S], dgz[S];
-#pragma unroll
-          for (int j = 0; j < S; ++j) {
-            gy[j] = f[S + j];
-            gz[j] = f[2 * S + j];
-            dgy[j] = f[4 * S + j];
-            dgz[j] = f[5 * S + j];
-          }
-          const R *col = blk + (az * TS + ay) * TS + ax + jx;
-          Kahan<R> s_pot, s_fy, s_fz;
-#pragma unroll
-          for (int jy = 0; jy < S; ++jy) {
-            R a0 = R(0), a1 = R(0);
-#pragma unroll
-            for (int jz = 0; jz < S; ++jz) {
-              const R v = col[(jz * TS + jy) * TS];
-              a0 += v * gz[jz];
-              a1 += v * dgz[jz];
-            }
-            s_pot.add(gy[jy] * a0);
-            s_fy.add(dgy[jy] * a0);
-            s_fz.add(gy[jy] * a1);
-          }
-          const R sp_v = s_pot.value();
-          t0 = gx * sp_v;
-          t1 = dgx * sp_v;
-          t2 = gx * s_fy.value();
-          t3 = gx * s_fz.value();
-        }
-        if constexpr (POW2) {
-          // pairwise tree over the S lanes of the group
-#pragma unroll
-          for (int o = S / 2; o > 0; o >>= 1) {
-            t0 += __shfl_xor(t0, o);
-            t1 += __shfl_xor(t1, o);
-            t2 += __shfl_xor(t2, o);
-            t3 += __shfl_xor(t3, o);
-          }
-        } else {
-          R *mine = wred + lane * 4;
-          mine[0] = t0;
-          mine[1] = t1;
-          mine[2] = t2;
-          mine[3] = t3;
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          if (jx == 0) {
-            Kahan<R> k0, k1, k2, k3;
-            const R *g = wred + grp * S * 4;
-#pragma unroll
-            for (int l = 0; l < S; ++l) {
-              k0.add(g[4 * l + 0]);
-              k1.add(g[4 * l + 1]);
-              k2.add(g[4 * l + 2]);
-              k3.add(g[4 * l + 3]);
-            }
-            t0 = k0.value();
-            t1 = k1.value();
-            t2 = k2.value();
-            t3 = k3.value();
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-        }
-        if (jx == 0) {
-          const R q = f[REC - 1];
-          const int orig = org[c];
-          if (mode >= kGatherIkX) {
-            // the grid is one component of the field: F_d = q E_d
-            out_vec[3 * orig + (mode - kGatherIkX)] = scale * q * t0;
-          } else {
-            const R pot = t0 + self_coef * q;
-            // potential-force mode: F = -q (t1, t2, t3); adjoint: -gE F = gE q (t1, t2, t3)
-            const R fq = (mode == kGatherPotentialForce) ? -scale * q : scale * q;
-            if (out_pot) out_pot[orig] = scale * pot;
-            if (out_vec) {
-              out_vec[3 * orig + 0] = fq * t1;
-              out_vec[3 * orig + 1] = fq * t2;
-              out_vec[3 * orig + 2] = fq * t3;
-            }
-          }
-        }
-      }
-    }
-  }
-}
-
-// LDS of the Gaussian gather (k_gather_lane): the tile block, the lane
-// partials (supports that are not a power of two), per-wave factor slots
-// (64/S groups of 2S values each) and the offset tables.
 // LDS of k_gather_lane: the block of Phi, the lane-sum slots (S not a power
 // of two), then one region that holds the staging tables (row and column
 // offsets) until the block barrier and the groups' factor slots after it;
 // sharing it keeps three 16-point-tile work-groups within a CU's LDS.
-constexpr size_t gather_lane_lds(int real_size, int S, int T) {
+constexpr int gather_slot(int window, int S) { return window == kGauss ? 2 * S : 6 * S; }
+constexpr size_t gather_lane_lds(int real_size, int window, int S, int T) {
   const size_t TS = T + S - 1;
-  const size_t wf = static_cast<size_t>(real_size) * (kTileThreads / 64) * (64 / S) * 2 * S;
+  const size_t wf =
+      static_cast<size_t>(real_size) * (kTileThreads / 64) * (64 / S) * gather_slot(window, S);
   const size_t tables = 4 * (TS * TS + TS);
   return real_size * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) +
          ((S & (S - 1)) ? static_cast<size_t>(real_size) * kTileThreads * 4 : 0) +
          (wf > tables ? wf : tables);
 }
 
-// Gaussian window.  The block of Phi is staged as in k_gather; then each
-// wave takes particle groups in a strided loop without block barriers: lane
-// (group, jx) evaluates three factors of its particle directly,
-// g = beta e^{-cg t^2} at t = jx + OFF - d along x, y and z, keeps its x
-// factor and shares the y and z ones with the group through the wave's LDS
-// slot, so each lane computes three exponentials per particle (instead of
-// one thread computing all 3S in a phase of its own between barriers).
-template <typename R, int S, int T>
+// The block of Phi is staged first; then each wave takes particle groups in
+// a strided loop without block barriers.  Gaussian: lane (group, jx)
+// evaluates three factors of its particle directly, g = beta e^{-cg t^2} at
+// t = jx + OFF - d along x, y and z, keeps its x factor and shares the y and
+// z ones with the group through the wave's LDS slot, so each lane computes
+// three exponentials per particle (instead of one thread computing all 3S in
+// a phase of its own between barriers).  B-spline: three lanes of the group
+// run the recursion, one axis each, and share factors and derivatives.
+template <typename R, int WIN, int S, int T>
 __global__ void __launch_bounds__(kTileThreads)
 k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ sorted,
               const int2 *__restrict__ meta, const int *__restrict__ offsets, int M, int ntx,
@@ -350,7 +70,8 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
               R *__restrict__ out_pot, R *__restrict__ out_vec) {
   constexpr int TS = T + S - 1, TS3 = TS * TS * TS;
   constexpr int GROUPS = 64 / S;
-  constexpr int OFF = Stencil<kGauss, S>::OFF;
+  constexpr int OFF = Stencil<WIN, S>::OFF;
+  constexpr int SLOT = gather_slot(WIN, S);
   constexpr int NWAVES = kTileThreads / 64;
   constexpr bool POW2 = (S & (S - 1)) == 0;
   constexpr size_t BLK = sizeof(R) * ((TS3 + 3) & ~3);
@@ -367,7 +88,7 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
   int *rowtab = reinterpret_cast<int *>(h_smem + BLK + RED), *xtab = rowtab + TS * TS;
 
   // Stage the block (batched loads into registers, then LDS stores; grid
-  // offsets from row and column tables), as k_gather does.
+  // offsets from row and column tables).
   const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
   const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
   constexpr int NST = (TS3 + kTileThreads - 1) / kTileThreads;  // elements per thread
@@ -413,7 +134,7 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
   const R scale = gscale ? static_cast<R>(*gscale) : R(1);
   const R cg = static_cast<R>(wc.cg), beta = static_cast<R>(wc.beta);
   const R dc = static_cast<R>(wc.dcoef);
-  R *gslot = wfac + (wave * GROUPS + grp) * 2 * S;  // this group's y and z factors
+  R *gslot = wfac + (wave * GROUPS + grp) * SLOT;  // this group's shared factors
   R *wred = red + wave * 64 * 4;
   for (; active && c < end; c += STRIDE) {
     const int cn = c + STRIDE;
@@ -425,8 +146,20 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
     }
     const R kj = static_cast<R>(jx + OFF);
     const R tx0 = kj - sp.dx, ty0 = kj - sp.dy, tz0 = kj - sp.dz;
-    R gx;
-    if constexpr (sizeof(R) == 4) {
+    R gx, dgx = R(0);
+    if constexpr (WIN == kBspline) {
+      // lanes 0, 1, 2 of the group run the recursion for x, y, z and share
+      // the factors and derivatives: slot [g_x | dg_x | g_y | dg_y | g_z | dg_z]
+      if (jx < 3) {
+        R g[S], dg[S];
+        window_axis<R, WIN, S, true>(jx == 0 ? sp.dx : (jx == 1 ? sp.dy : sp.dz), wc, g, dg);
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+          gslot[2 * S * jx + j] = g[j];
+          gslot[2 * S * jx + S + j] = dg[j];
+        }
+      }
+    } else if constexpr (sizeof(R) == 4) {
       gx = gauss_factor(beta, wc.cgl2, jx + OFF, sp.dx);
       gslot[jx] = gauss_factor(beta, wc.cgl2, jx + OFF, sp.dy);
       gslot[S + jx] = gauss_factor(beta, wc.cgl2, jx + OFF, sp.dz);
@@ -438,17 +171,29 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // d/dx_m of a Gaussian factor is dc (j + OFF - d) g_j.  With the centred
-    // weights c_j = j + OFF - 1/2 and e = d - 1/2 (|e| <= 1/2):
+    // Gaussian: d/dx_m of a factor is dc (j + OFF - d) g_j.  With the
+    // centred weights c_j = j + OFF - 1/2 and e = d - 1/2 (|e| <= 1/2):
     //   sum_j (j + OFF - d) g_j a_j = sum_j c_j g_j a_j - e sum_j g_j a_j,
-    // so the derivative needs one extra weighted sum per axis.
+    // so the derivative needs one extra weighted sum per axis.  B-spline:
+    // cy, cz are the derivatives themselves.
     R gy[S], gz[S], cy[S], cz[S];
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-      gy[j] = gslot[j];
-      gz[j] = gslot[S + j];
-      cy[j] = (static_cast<R>(j + OFF) - R(0.5)) * gy[j];
-      cz[j] = (static_cast<R>(j + OFF) - R(0.5)) * gz[j];
+      if constexpr (WIN == kBspline) {
+        gy[j] = gslot[2 * S + j];
+        cy[j] = gslot[3 * S + j];
+        gz[j] = gslot[4 * S + j];
+        cz[j] = gslot[5 * S + j];
+      } else {
+        gy[j] = gslot[j];
+        gz[j] = gslot[S + j];
+        cy[j] = (static_cast<R>(j + OFF) - R(0.5)) * gy[j];
+        cz[j] = (static_cast<R>(j + OFF) - R(0.5)) * gz[j];
+      }
+    }
+    if constexpr (WIN == kBspline) {
+      gx = gslot[jx];
+      dgx = gslot[S + jx];
     }
     const int packed = mt.x;
     const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
@@ -468,9 +213,20 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
       k2.add(gy[jy] * b1);  // sum g_y c_z g_z Phi
     }
     const R s0 = k0.value(), s1 = k1.value(), s2 = k2.value();
-    const R ey = sp.dy - R(0.5), ez = sp.dz - R(0.5);
-    const R dgx = dc * tx0 * gx;
-    R t0 = gx * s0, t1 = dgx * s0, t2 = dc * gx * (s1 - ey * s0), t3 = dc * gx * (s2 - ez * s0);
+    R t0, t1, t2, t3;
+    if constexpr (WIN == kBspline) {
+      t0 = gx * s0;
+      t1 = dgx * s0;
+      t2 = gx * s1;
+      t3 = gx * s2;
+    } else {
+      const R ey = sp.dy - R(0.5), ez = sp.dz - R(0.5);
+      dgx = dc * tx0 * gx;
+      t0 = gx * s0;
+      t1 = dgx * s0;
+      t2 = dc * gx * (s1 - ey * s0);
+      t3 = dc * gx * (s2 - ez * s0);
+    }
     // the group's slot is rewritten only after every lane has read it
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -535,8 +291,7 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
 template <typename R, int WIN, int S, int T>
 hipError_t gather_one(se_plan &p, const void *grid, bool tgt, const double *gscale, int mode,
                       void *pot, void *vec) {
-  constexpr bool kLane = WIN == kGauss;
-  const size_t lds = kLane ? gather_lane_lds(sizeof(R), S, T) : GatherLds<R, WIN, S, T>::TOTAL;
+  const size_t lds = gather_lane_lds(sizeof(R), WIN, S, T);
   const double dcoef = (WIN == kGauss) ? 2.0 * p.a * p.h : 1.0 / p.h;
   const WindowConsts wc = window_consts(p.cg, p.beta, dcoef);
   const double self =
@@ -544,24 +299,17 @@ hipError_t gather_one(se_plan &p, const void *grid, bool tgt, const double *gsca
   const void *sorted = tgt ? p.tgt.sorted : p.buf.sorted;
   const int2 *meta = tgt ? p.tgt.meta : p.buf.meta;
   const int *offsets = tgt ? p.tgt.offsets : p.buf.offsets;
-  const void *kern = kLane ? reinterpret_cast<const void *>(&k_gather_lane<R, S, T>)
-                           : reinterpret_cast<const void *>(&k_gather<R, WIN, S, T>);
+  const void *kern = reinterpret_cast<const void *>(&k_gather_lane<R, WIN, S, T>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
   if (!tgt) stage_begin(p, SE_STAGE_GATHER);
-  if constexpr (kLane)
-    launch_on(&p, k_gather_lane<R, S, T>, p.ntiles, kTileThreads, lds, p.stream, 
-        static_cast<const R *>(grid), static_cast<const SortedParticle<R> *>(sorted), meta,
-        offsets, p.prm.M, p.ntx, wc, gscale, mode, static_cast<R>(self), static_cast<R *>(pot),
-        static_cast<R *>(vec));
-  else
-    launch_on(&p, k_gather<R, WIN, S, T>, p.ntiles, kTileThreads, lds, p.stream, 
-        static_cast<const R *>(grid), static_cast<const SortedParticle<R> *>(sorted), meta,
-        offsets, p.prm.M, p.ntx, wc, gscale, mode, static_cast<R>(self), static_cast<R *>(pot),
-        static_cast<R *>(vec));
+  launch_on(&p, k_gather_lane<R, WIN, S, T>, p.ntiles, kTileThreads, lds, p.stream,
+            static_cast<const R *>(grid), static_cast<const SortedParticle<R> *>(sorted), meta,
+            offsets, p.prm.M, p.ntx, wc, gscale, mode, static_cast<R>(self), static_cast<R *>(pot),
+            static_cast<R *>(vec));
   if (!tgt) stage_end(p, SE_STAGE_GATHER);
   return hipGetLastError();
 }
@@ -611,12 +359,7 @@ hipError_t gather_call(se_plan &p, const GatherCall &g) {
 }  // namespace
 
 size_t gather_lds_bytes(int real_size, int window, int S, int T) {
-  if (window == SE_WINDOW_GAUSSIAN) return gather_lane_lds(real_size, S, T);
-  const int win = kBspline;
-  const size_t rec = gather_rec(win, S);
-  const size_t chunk = gather_chunk(real_size, win, S, T);
-  return static_cast<size_t>(gather_fixed_bytes(real_size, S, T)) + real_size * chunk * rec +
-         2 * 4 * chunk;
+  return gather_lane_lds(real_size, window == SE_WINDOW_GAUSSIAN ? kGauss : kBspline, S, T);
 }
 
 hipError_t launch_gather(se_plan &plan, int N, const double *gscale, int mode, void *out_pot,

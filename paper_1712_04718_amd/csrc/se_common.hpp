@@ -297,20 +297,6 @@ constexpr int kMaxSplineOrder = 8;  // largest SPME order built
 constexpr int kThreads = 256;      // work-group size of the binning, fold and FFT kernels
 constexpr int kTileThreads = 512;  // work-group size of the tile spread and gather kernels
 
-// Particles per phase-A round of the tile kernels (one per thread): the
-// largest power of two up to kTileThreads whose factor table (per_particle
-// bytes each) stays within 32 KB and, when a round of at least 64 particles
-// allows it, keeps the work-group (fixed_bytes besides the table) within
-// 80 KB of LDS, so that two work-groups share a CU.
-constexpr int tile_chunk(long long per_particle, long long fixed_bytes) {
-  long long cap = 32768;
-  const long long room = 80LL * 1024 - fixed_bytes;
-  if (room >= 64 * per_particle && room < cap) cap = room;
-  int c = kTileThreads;
-  while (c > 64 && per_particle * c > cap) c /= 2;
-  return c;
-}
-
 // Most pencils per FFT work-group, per pass.  Lanes run over the B pencils
 // fastest, so a wave reads 64 / B consecutive elements of each pencil: the
 // y pencils are contiguous and B = 4 gives whole 128-byte lines with many

@@ -21,20 +21,14 @@
 // on this chip.)  An FP32 contribution has 24 significant bits while the
 // fixed point spans 30, so exact halves are common: they round to even,
 // which keeps the sum unbiased (rounding halves up would not).
-// Work split, Gaussian window (k_spread_lane): each wave holds 64/S particle
+// Work split (k_spread_lane, both windows): each wave holds 64/S particle
 // groups of S lanes; lane (group, jx) owns the x-offset jx of one particle,
-// evaluates the factors it needs itself (its x factor, all S factors along y
-// and z, each to about one FP32 rounding) and adds its S^2 (jy, jz)
-// products.  The exponentials run in the
-// shadow of the LDS atomics, whose issue rate bounds the kernel, and no
-// factor table or barrier sits between the particles and their atomics.
-// B-spline window (k_spread): the tile's particles are taken in chunks of one
-// per thread;
-//   phase A: each thread computes its particle's 3S window factors and
-//            stores them with its charge in LDS (the first chunk while the
-//            tile's max |q| is being reduced);
-//   phase B: as above, the factors read from LDS (the order-p recursion costs
-//            more than the atomics it would hide behind).
+// evaluates the factors it needs itself (Gaussian: its x factor and all S
+// factors along y and z, each to about one FP32 rounding; B-spline: the
+// order-S recursion of section 6.1 along the three axes) and adds its S^2
+// (jy, jz) products.  The factor arithmetic runs in the shadow of the LDS
+// atomics, whose issue rate bounds the kernel, and no factor table or
+// barrier sits between the particles and their atomics.
 #include "se_common.hpp"
 #include "window.hpp"
 
@@ -46,184 +40,6 @@ extern __shared__ __align__(16) unsigned char g_smem[];
 template <typename R> struct Acc;
 template <> struct Acc<float> { using T = int; };      // fixed point
 template <> struct Acc<double> { using T = long long; };  // fixed point
-
-// particles per phase-A round (tile_chunk): 3S factors, an anchor and a
-// charge each, beside the fixed-point block and the reduction slots
-constexpr int spread_chunk(int real_size, int S, int T) {
-  const long long ts = T + S - 1, acc = real_size == 4 ? 4 : 8;
-  return tile_chunk(static_cast<long long>(real_size) * 3 * S + 4 + real_size,
-                    acc * ((ts * ts * ts + 3) & ~3LL) + 128);
-}
-
-constexpr size_t spread_lds_total(int real_size, int S, int T) {
-  const size_t TS = T + S - 1, acc = real_size == 4 ? 4 : 8;
-  const size_t chunk = spread_chunk(real_size, S, T);
-  return acc * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) + real_size * chunk * 3 * S +
-         4 * chunk + real_size * chunk + 128;
-}
-
-template <typename R, int S, int T> struct SpreadLds {
-  using A = typename Acc<R>::T;
-  static constexpr int TS = T + S - 1;
-  static constexpr int REC = 3 * S;
-  static constexpr int CHUNK = spread_chunk(sizeof(R), S, T);
-  static constexpr size_t BLK = sizeof(A) * ((TS * TS * TS + 3) & ~3);
-  static constexpr size_t FAC = sizeof(R) * CHUNK * REC;
-  static constexpr size_t ANC = sizeof(int) * CHUNK;
-  static constexpr size_t QV = sizeof(R) * CHUNK;
-  static constexpr size_t TOTAL = BLK + FAC + ANC + QV + 128;
-  static_assert(TOTAL == spread_lds_total(sizeof(R), S, T), "LDS size mismatch");
-};
-
-template <typename R, int WIN, int S, int T>
-__global__ void __launch_bounds__(kTileThreads)
-k_spread(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ meta,
-         const int *__restrict__ offsets, int *__restrict__ counts, WindowConsts wc, double wmax,
-         R *__restrict__ ghost) {
-  using L = SpreadLds<R, S, T>;
-  using A = typename Acc<R>::T;
-  constexpr int TS = L::TS, REC = L::REC, TS3 = TS * TS * TS;
-  constexpr int kChunk = L::CHUNK;
-  constexpr int GROUPS = 64 / S;
-  constexpr int NWAVES = kTileThreads / 64;
-  // fixed-point bits of the accumulator
-  constexpr double kFix = sizeof(R) == 4 ? 1073741824.0 : 4611686018427387904.0;  // 2^30, 2^62
-  static_assert(NWAVES * 16 <= 128, "per-wave partials must fit the reduction area");
-  static_assert(kChunk <= kTileThreads, "phase A holds one particle per thread");
-
-  const int tile = xcd_local(blockIdx.x, gridDim.x);
-  const int start = offsets[tile], end = offsets[tile + 1];
-  const int tid = threadIdx.x;
-  // the binning left this tile's count for its consumer to reset
-  if (tid == 0) counts[tile * kCountStride] = 0;
-  R *out = ghost + static_cast<long long>(tile) * TS3;
-  if (start == end) {  // uniform across the work-group
-    for (int i = tid; i < TS3; i += kTileThreads) out[i] = R(0);
-    return;
-  }
-
-  A *blk = reinterpret_cast<A *>(g_smem);
-  R *fac = reinterpret_cast<R *>(g_smem + L::BLK);
-  int *anc = reinterpret_cast<int *>(g_smem + L::BLK + L::FAC);
-  R *qv = reinterpret_cast<R *>(g_smem + L::BLK + L::FAC + L::ANC);
-  double *red = reinterpret_cast<double *>(g_smem + L::BLK + L::FAC + L::ANC + L::QV);
-
-  // The tile's first kChunk particles are read once, into registers; they
-  // serve the charge bound and the first round of phase A.
-  const int n = end - start;
-  SortedParticle<R> mine{};
-  int mine_anchor = 0;
-  if (tid < min(n, kChunk)) {
-    mine = sorted[start + tid];
-    mine_anchor = meta[start + tid].x;
-  }
-  for (int i = tid; i < TS3; i += kTileThreads) blk[i] = A(0);
-
-  // phase A: a particle's 3S window factors and its charge into LDS (the
-  // fixed-point scale is applied in phase B, so this needs no bound)
-  const auto phase_a = [&](const SortedParticle<R> &sp, int a) {
-    R g[S], unused[S];
-    R *f = fac + tid * REC;
-    window_axis<R, WIN, S, false>(sp.dx, wc, g, unused);
-#pragma unroll
-    for (int j = 0; j < S; ++j) f[j] = g[j];
-    window_axis<R, WIN, S, false>(sp.dy, wc, g, unused);
-#pragma unroll
-    for (int j = 0; j < S; ++j) f[S + j] = g[j];
-    window_axis<R, WIN, S, false>(sp.dz, wc, g, unused);
-#pragma unroll
-    for (int j = 0; j < S; ++j) f[2 * S + j] = g[j];
-    qv[tid] = sp.q;
-    anc[tid] = a;
-  };
-
-  // Fixed-point scale of this tile from a bound on sum |q| that does not
-  // depend on the order of the particles (the order inside a tile comes from
-  // atomics): qmax = max |q| is exact, each particle contributes the integer
-  // u = ceil(|q| / qmax * 2^20) >= |q| / qmax * 2^20, and integer sums are
-  // exact, so qmax * sum(u) / 2^20 >= sum |q| is the same on every run.  The
-  // first round's factors are computed while the maximum is reduced; the
-  // two reductions use separate LDS slots, one barrier each.
-  R qa = R(0);  // |q| of particle start + tid
-  if (tid < n) qa = fabs(tid < kChunk ? mine.q : sorted[start + tid].q);
-  double m = static_cast<double>(qa);
-  for (int p = start + kTileThreads + tid; p < end; p += kTileThreads)
-    m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-  double *red_max = red;
-  long long *red_u = reinterpret_cast<long long *>(red + NWAVES);
-  if ((tid & 63) == 0) red_max[tid >> 6] = m;
-  if (tid < min(n, kChunk)) phase_a(mine, mine_anchor);
-  __syncthreads();  // maximum, first factors and zeroed block visible
-  double qmax = 0.0;
-  for (int w = 0; w < NWAVES; ++w) qmax = fmax(qmax, red_max[w]);
-  // (a non-finite charge weighs 0 here: the integer conversion stays defined)
-  const auto weight = [&](double aq) {
-    const double w = ceil(aq / qmax * 1048576.0);
-    return w <= 1048576.0 ? static_cast<long long>(w) : 0LL;
-  };
-  long long u = 0;
-  if (qmax > 0.0) {
-    if (tid < n) u = weight(static_cast<double>(qa));
-    for (int p = start + kTileThreads + tid; p < end; p += kTileThreads)
-      u += weight(fabs(static_cast<double>(sorted[p].q)));
-  }
-  for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
-  if ((tid & 63) == 0) red_u[tid >> 6] = u;
-  __syncthreads();
-  long long usum = 0;
-  for (int w = 0; w < NWAVES; ++w) usum += red_u[w];
-  const double bound = wmax * qmax * (static_cast<double>(usum) / 1048576.0);
-  double scale = 1.0, inv_scale = 1.0;
-  if (bound > 0.0) {
-    scale = kFix / bound;
-    inv_scale = bound / kFix;
-  }
-
-  const int wave = tid >> 6, lane = tid & 63;
-  const int grp = lane / S, jx = lane - grp * S;
-  for (int base = start; base < end; base += kChunk) {
-    const int nval = min(kChunk, end - base);
-    if (base != start) {
-      __syncthreads();  // previous round done with fac / qv / anc
-      if (tid < nval) phase_a(sorted[base + tid], meta[base + tid].x);
-      __syncthreads();
-    }
-    // phase B: lane (group, jx) of 64/S particle groups adds its S^2 products
-    if (grp < GROUPS) {
-      for (int c = wave * GROUPS + grp; c < nval; c += NWAVES * GROUPS) {
-        const R *f = fac + c * REC;
-        const int packed = anc[c];
-        const int ax = packed & 0xff, ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
-        A *row = blk + (az * TS + ay) * TS + ax + jx;
-        // the charge in fixed-point units times this lane's x factor
-        const R wq = static_cast<R>(static_cast<double>(qv[c]) * scale) * f[jx];
-        R gy[S], gz[S];
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-          gy[j] = f[S + j];
-          gz[j] = f[2 * S + j];
-        }
-#pragma unroll
-        for (int jz = 0; jz < S; ++jz) {
-          const R wz = wq * gz[jz];
-#pragma unroll
-          for (int jy = 0; jy < S; ++jy) {
-            if constexpr (sizeof(R) == 4)
-              atomicAdd(row + (jz * TS + jy) * TS, __float2int_rn(wz * gy[jy]));
-            else  // two's complement: the unsigned add is the signed one
-              atomicAdd(reinterpret_cast<unsigned long long *>(row + (jz * TS + jy) * TS),
-                        static_cast<unsigned long long>(__double2ll_rn(wz * gy[jy])));
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-  for (int i = tid; i < TS3; i += kTileThreads) {
-    out[i] = static_cast<R>(static_cast<double>(blk[i]) * inv_scale);
-  }
-}
 
 // FP64 fixed-point scale of a tile (2^62 units leave the rounding far below
 // FP64 rounding, so the simple bound serves): a bound on sum |q| that does not depend
@@ -266,36 +82,34 @@ __device__ inline double tile_bound(const SortedParticle<R> *__restrict__ sorted
 // fixed-point scale, independent of the order of the tile's particles (that
 // order comes from atomics).  A particle with anchor (ax, ay, az) in the tile
 // adds to block point (jx, jy, jz) the value q g_x g_y g_z with
-//   0 <= g_d <= beta k(j_d - a_d),  k(i) = max over d in [0,1) of
-//   e^{-cg (i + OFF - d)^2} = e^{-cg dist(i + OFF, [0,1])^2}  (0 <= i < S),
-// and g_x <= beta, so every partial sum at (jx, jy, jz) is at most
-//   beta^3 sum_n |q_n| k(jy - ay_n) k(jz - az_n),
+//   0 <= g_d <= wmax^(1/3) k(j_d - a_d),  k(i) = the largest value factor i
+//   takes over d in [0, 1) (wc.kt: e^{-cg dist(i + OFF, [0,1])^2} for the
+//   Gaussian, whose factors carry beta = wmax^(1/3); M_S at the point of its
+//   interval nearest S/2 for the B-spline, wmax = 1),
+// and g_x <= wmax^(1/3), so every partial sum at (jx, jy, jz) is at most
+//   wmax sum_n |q_n| k(jy - ay_n) k(jz - az_n),
 // the tile's (y, z) anchor histogram of |q| convolved with k along y and z.
 // To be order-free the histogram holds integers: u = ceil(|q| / qmax 2^20)
 // >= |q| / qmax 2^20 per particle (qmax = max |q| is exact), added with
 // 64-bit integer atomics; the convolutions run in a fixed order (along y in
 // FP64 into an FP32 buffer, then along z in FP64), and the result is raised
-// by 1e-5 for the roundings of the buffer and of the k table.  On the
-// 100k-atom water workload this bound is 11x tighter than wmax sum |q| (the
-// partial sums there stay far below the charge a tile holds), which takes
-// the FP32 fixed-point rounding of the forces from 1.4e-6 to 1.3e-7.
-// LDS: U (T^2 integers), C (TS x T floats), k (S doubles), red (2 NWAVES
-// doubles).  A non-finite charge weighs 0 (the integer conversion stays
-// defined).  Returns the bound divided by beta^3 (0 for a tile without
+// by 1e-5 for the roundings of the buffer, of the k table and of the FP32
+// factors.  On the 100k-atom water workload this bound is 11x tighter than
+// wmax sum |q| (the partial sums there stay far below the charge a tile
+// holds), which takes the FP32 fixed-point rounding of the forces from
+// 1.4e-6 to 1.3e-7.  LDS: U (T^2 integers), C (TS x T floats), red (2
+// NWAVES doubles).  A non-finite charge weighs 0 (the integer conversion
+// stays defined).  Returns the bound divided by wmax (0 for a tile without
 // charge).
 template <typename R, int S, int T, int NWAVES>
 __device__ inline double tile_bound_yz(const SortedParticle<R> *__restrict__ sorted,
                                        const int2 *__restrict__ meta, int start, int end,
-                                       double cg, unsigned long long *U, float *C, double *kt,
+                                       const WindowConsts &wc, unsigned long long *U, float *C,
                                        double *red) {
-  constexpr int TS = T + S - 1, OFF = Stencil<kGauss, S>::OFF;
+  constexpr int TS = T + S - 1;
+  const double *kt = wc.kt;  // k(i), from the host (window_bounds)
   const int tid = threadIdx.x;
   for (int i = tid; i < T * T; i += kTileThreads) U[i] = 0ull;
-  if (tid < S) {
-    const int i = tid + OFF;  // k(tid): the distance of i from [0, 1]
-    const double dist = i < 0 ? -i : (i > 1 ? i - 1 : 0);
-    kt[tid] = exp(-cg * dist * dist);
-  }
   double m = 0.0;
   for (int p = start + tid; p < end; p += kTileThreads)
     m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
@@ -349,12 +163,11 @@ __device__ inline double tile_bound_yz(const SortedParticle<R> *__restrict__ sor
 }
 
 // LDS of k_spread_lane: the fixed-point block, then (FP32) the bound's
-// histogram U (T^2 64-bit integers), C (TS x T floats, rounded up to 8 bytes)
-// and k (S doubles), then 128 bytes of reduction slots.
+// histogram U (T^2 64-bit integers) and C (TS x T floats, rounded up to 8
+// bytes), then 128 bytes of reduction slots.
 constexpr size_t spread_lane_bound_lds(int real_size, int S, int T) {
   return real_size == 4
-             ? 8 * static_cast<size_t>(T * T) + ((4 * static_cast<size_t>((T + S - 1) * T) + 7) & ~size_t(7)) +
-                   8 * static_cast<size_t>(S)
+             ? 8 * static_cast<size_t>(T * T) + ((4 * static_cast<size_t>((T + S - 1) * T) + 7) & ~size_t(7))
              : 0;
 }
 constexpr size_t spread_lane_lds(int real_size, int S, int T) {
@@ -363,11 +176,13 @@ constexpr size_t spread_lane_lds(int real_size, int S, int T) {
          spread_lane_bound_lds(real_size, S, T) + 128;
 }
 
-// Gaussian window: the factors are evaluated by the lanes that use them
-// (see the file comment).  Per lane: its x factor g_jx = beta e^{-cg t^2}
+// The factors are evaluated by the lanes that use them (see the file
+// comment).  Gaussian, per lane: its x factor g_jx = beta e^{-cg t^2}
 // (t = jx + OFF - dx) directly (gauss_factor in FP32), and the S factors
 // along y and z with window_axis (the central ones directly as well).
-template <typename R, int S, int T>
+// B-spline: every lane runs the order-S recursion of window_axis for the
+// three axes of its particle and keeps entry jx along x.
+template <typename R, int WIN, int S, int T>
 __global__ void __launch_bounds__(kTileThreads)
 k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict__ meta,
               const int *__restrict__ offsets, int *__restrict__ counts, WindowConsts wc,
@@ -376,7 +191,7 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
   constexpr int TS = T + S - 1, TS3 = TS * TS * TS;
   constexpr int GROUPS = 64 / S;
   constexpr int NWAVES = kTileThreads / 64;
-  constexpr int OFF = Stencil<kGauss, S>::OFF;
+  constexpr int OFF = Stencil<WIN, S>::OFF;
   constexpr double kFix = sizeof(R) == 4 ? 1073741824.0 : 4611686018427387904.0;  // 2^30, 2^62
   static_assert(2 * NWAVES * 8 <= 128, "reduction slots");
   static_assert(T <= 256, "local anchors are packed in 8 bits");
@@ -395,7 +210,6 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
   unsigned char *bnd = g_smem + sizeof(A) * ((TS3 + 3) & ~3);
   unsigned long long *U = reinterpret_cast<unsigned long long *>(bnd);
   float *C = reinterpret_cast<float *>(bnd + 8 * T * T);
-  double *kt = reinterpret_cast<double *>(bnd + 8 * T * T + ((4 * TS * T + 7) & ~7));
   double *red = reinterpret_cast<double *>(bnd + spread_lane_bound_lds(sizeof(R), S, T));
 
   const int wave = tid >> 6, lane = tid & 63;
@@ -414,7 +228,7 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
   for (int i = tid; i < TS3; i += kTileThreads) blk[i] = A(0);
   double bound;
   if constexpr (sizeof(R) == 4)
-    bound = wmax * tile_bound_yz<R, S, T, NWAVES>(sorted, meta, start, end, wc.cg, U, C, kt, red);
+    bound = wmax * tile_bound_yz<R, S, T, NWAVES>(sorted, meta, start, end, wc, U, C, red);
   else
     bound = wmax * tile_bound<R, NWAVES>(sorted, start, end, red);
   const double scale = bound > 0.0 ? kFix / bound : 1.0;
@@ -431,10 +245,16 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
       npacked = meta[cn].x;
     }
     R gy[S], gz[S], unused[S];
-    window_axis<R, kGauss, S, false>(sp.dy, wc, gy, unused);
-    window_axis<R, kGauss, S, false>(sp.dz, wc, gz, unused);
+    window_axis<R, WIN, S, false>(sp.dy, wc, gy, unused);
+    window_axis<R, WIN, S, false>(sp.dz, wc, gz, unused);
     R gx;
-    if constexpr (sizeof(R) == 4) {
+    if constexpr (WIN == kBspline) {
+      R gxs[S];
+      window_axis<R, WIN, S, false>(sp.dx, wc, gxs, unused);
+      gx = gxs[0];
+#pragma unroll
+      for (int j = 1; j < S; ++j) gx = j == jx ? gxs[j] : gx;
+    } else if constexpr (sizeof(R) == 4) {
       gx = gauss_factor(beta, wc.cgl2, jx + OFF, sp.dx);
     } else {
       const R t = static_cast<R>(jx + OFF) - sp.dx;
@@ -547,26 +367,20 @@ k_fold_tiles(const R *__restrict__ ghost, int M, int ntx, R *__restrict__ grid) 
 
 template <typename R, int WIN, int S, int T>
 hipError_t spread_one(se_plan &p) {
-  constexpr bool kLane = WIN == kGauss;
-  const size_t lds = kLane ? spread_lane_lds(sizeof(R), S, T) : SpreadLds<R, S, T>::TOTAL;
-  const WindowConsts wc = window_consts(p.cg, p.beta, 0.0);
+  const size_t lds = spread_lane_lds(sizeof(R), S, T);
+  WindowConsts wc = window_consts(p.cg, p.beta, 0.0);
+  window_bounds(wc, WIN, S);
   const double wmax = (WIN == kGauss) ? p.beta * p.beta * p.beta : 1.0;
-  const void *kern = kLane ? reinterpret_cast<const void *>(&k_spread_lane<R, S, T>)
-                           : reinterpret_cast<const void *>(&k_spread<R, WIN, S, T>);
+  const void *kern = reinterpret_cast<const void *>(&k_spread_lane<R, WIN, S, T>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
   stage_begin(p, SE_STAGE_SPREAD);
-  if constexpr (kLane)
-    launch_on(&p, k_spread_lane<R, S, T>, p.ntiles, kTileThreads, lds, p.stream, 
-        static_cast<const SortedParticle<R> *>(p.buf.sorted), p.buf.meta, p.buf.offsets,
-        p.buf.counts, wc, wmax, static_cast<R *>(p.buf.ghost));
-  else
-    launch_on(&p, k_spread<R, WIN, S, T>, p.ntiles, kTileThreads, lds, p.stream, 
-        static_cast<const SortedParticle<R> *>(p.buf.sorted), p.buf.meta, p.buf.offsets,
-        p.buf.counts, wc, wmax, static_cast<R *>(p.buf.ghost));
+  launch_on(&p, k_spread_lane<R, WIN, S, T>, p.ntiles, kTileThreads, lds, p.stream,
+            static_cast<const SortedParticle<R> *>(p.buf.sorted), p.buf.meta, p.buf.offsets,
+            p.buf.counts, wc, wmax, static_cast<R *>(p.buf.ghost));
   stage_end(p, SE_STAGE_SPREAD);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -617,8 +431,8 @@ hipError_t spread_dispatch(se_plan &p) {
 }  // namespace
 
 size_t spread_lds_bytes(int real_size, int window, int S, int T) {
-  return window == SE_WINDOW_GAUSSIAN ? spread_lane_lds(real_size, S, T)
-                                      : spread_lds_total(real_size, S, T);
+  (void)window;
+  return spread_lane_lds(real_size, S, T);
 }
 
 hipError_t launch_spread(se_plan &plan) {

@@ -46,6 +46,9 @@ struct WindowConsts {
   double dcoef;  // SE: 2 a h; SPME: 1/h   (derivative scale)
   float rk[kMaxHalfSupport + 1];  // exp(-cg (2m + 1)), m = 0..S/2 (SE, FP32)
   double cgl2;   // cg log2(e): FP32 factors as beta 2^{-cgl2 t^2} (SE)
+  // kt[i]: the largest value factor i of an axis takes over d in [0, 1),
+  // without the Gaussian's beta (the spread's tile bound; window_bounds)
+  double kt[2 * kMaxHalfSupport];
 };
 
 // e^{-cg t^2} in FP32 as 2^{-cgl2 t^2} with the hardware base-2 exponential
@@ -63,10 +66,36 @@ __device__ inline float gauss_factor(float beta, double cgl2, int k, float d) {
 }
 
 inline WindowConsts window_consts(double cg, double beta, double dcoef) {
-  WindowConsts wc{cg, beta, std::exp(-2.0 * cg), dcoef, {}, cg * M_LOG2E};
+  WindowConsts wc{cg, beta, std::exp(-2.0 * cg), dcoef, {}, cg * M_LOG2E, {}};
   for (int m = 0; m <= kMaxHalfSupport; ++m)
     wc.rk[m] = static_cast<float>(std::exp(-cg * (2.0 * m + 1.0)));
   return wc;
+}
+
+// Cardinal B-spline M_n(u) (section 6.1): M_2(u) = 1 - |u - 1| on [0, 2],
+// M_n(u) = (u M_{n-1}(u) + (n - u) M_{n-1}(u - 1)) / (n - 1).
+inline double bspline_value(int n, double u) {
+  if (u <= 0.0 || u >= n) return 0.0;
+  if (n == 2) return 1.0 - std::fabs(u - 1.0);
+  return (u * bspline_value(n - 1, u) + (n - u) * bspline_value(n - 1, u - 1.0)) / (n - 1);
+}
+
+// wc.kt for a support of S points: Gaussian factor i is e^{-cg t^2} at
+// t = i + OFF - d, largest where t is nearest 0 (distance of i + OFF from
+// [0, 1]); B-spline factor i is M_S(d + S - 1 - i), and M_S, symmetric
+// and unimodal about S/2, is largest at the point of [S - 1 - i, S - i]
+// nearest S/2.
+inline void window_bounds(WindowConsts &wc, int window, int S) {
+  for (int i = 0; i < S && i < 2 * kMaxHalfSupport; ++i) {
+    if (window == kGauss) {
+      const int t = i - (S / 2 - 1);
+      const double dist = t < 0 ? -t : (t > 1 ? t - 1 : 0);
+      wc.kt[i] = std::exp(-wc.cg * dist * dist);
+    } else {
+      const double lo = S - 1 - i, hi = S - i, mid = 0.5 * S;
+      wc.kt[i] = bspline_value(S, mid < lo ? lo : (mid > hi ? hi : mid));
+    }
+  }
 }
 
 // All S factors of one axis (and optionally their derivatives).
