@@ -132,7 +132,8 @@ def test_many_particles_per_tile(N, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_coincident_charges(dtype):
+@pytest.mark.parametrize("window,P", [("gaussian", 8), ("bspline", 6)])
+def test_coincident_charges(window, P, dtype):
     """Thousands of equal charges on one point, and opposite charges on a
     point of the same (y, z) anchor column: the partial sums of the tile's
     fixed-point block can reach the charge bound in any order of the atomics,
@@ -150,7 +151,7 @@ def test_coincident_charges(dtype):
                         np.random.default_rng(9).random((300, 3)) * L])
     q = np.concatenate([np.full(1500, 1.0), np.full(1500, -1.0), np.full(700, 0.5),
                         np.random.default_rng(10).standard_normal(300)])
-    _parity(x, q, L, 1.2, M, 8, dtype, tol=5e-5 if dtype == torch.float32 else None)
+    _parity(x, q, L, 1.2, M, P, dtype, window, tol=5e-5 if dtype == torch.float32 else None)
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
