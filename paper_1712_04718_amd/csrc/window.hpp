@@ -1,9 +1,7 @@
-// Per-axis window factors of the two methods, evaluated for one particle.
-//
-// Each particle's factors are computed once, by one lane, into LDS ("phase
-// A" of the spreading and gathering kernels); the accumulation loops then
-// read them.  Grid units: a particle with anchor floor(x/h) = i0 and offset
-// d = x/h - i0 in [0,1) touches the S grid points i0 + OFF + j, j = 0..S-1.
+// Per-axis window factors of the two methods, evaluated for one particle by
+// the lanes of the spreading and gathering kernels that use them.  Grid
+// units: a particle with anchor floor(x/h) = i0 and offset d = x/h - i0 in
+// [0,1) touches the S grid points i0 + OFF + j, j = 0..S-1.
 //
 // SE (section 4): truncated Gaussian, OFF = -(P/2 - 1).  Per axis
 //   g_j = beta exp(-cg t_j^2),  t_j = j + OFF - d   (= (x_j - x)/h),
@@ -12,8 +10,8 @@
 // FP64 factors follow the fast Gaussian gridding recurrence of eqs.
 // (4.10)-(4.11): g_{j+1} = g_j r_j with r_j = exp(-cg (2 t_j + 1)) and
 // r_{j+1} = r_j exp(-2 cg), i.e. two exponentials per axis instead of P.
-// FP32 factors use three exponentials per axis around the anchor (see
-// window_axis).  The derivative
+// FP32 factors are evaluated directly near the centre and by a short
+// recurrence in the tail (see window_axis).  The derivative
 // factor used for forces is the derivative with respect to the particle
 // coordinate, d/dx_m W(x_j - x_m) = 2 a (x_j - x_m) W, i.e. per axis
 // dg_j = 2 a h t_j g_j.
