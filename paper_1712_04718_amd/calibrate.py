@@ -17,7 +17,11 @@ by non-negative least squares on relative residuals.
     python -m paper_1712_04718_amd.calibrate [--dtype f32|f64] [--out file.json]
 
 prints one JSON object: the constants, each measured point and the largest
-relative deviation of the fit.
+relative deviation of the fit;
+
+    python -m paper_1712_04718_amd.calibrate --markdown calib_f32.json calib_f64.json
+
+(host only) writes the two fits as the markdown summary of profiles/.
 """
 from __future__ import annotations
 
@@ -117,12 +121,46 @@ def fit(dtype, kpts, rpts):
     return model, ek, er
 
 
+def markdown(paths):
+    """The fits of calibration runs (JSON files of --out) as markdown."""
+    md = ["# Runtime model of the parameter selection, fitted on one MI355X", "",
+          "Command (run from the repository root on the GPU box, once per precision):", "",
+          "    python -m paper_1712_04718_amd.calibrate --dtype f32 --out <out-dir>/calib_f32.json",
+          "    python -m paper_1712_04718_amd.calibrate --dtype f64 --out <out-dir>/calib_f64.json",
+          "    python -m paper_1712_04718_amd.calibrate --markdown <out-dir>/calib_f32.json "
+          "<out-dir>/calib_f64.json", "",
+          "Each point: mean of 10 calls between HIP events after 3 warm-ups, uniform",
+          "random +-1 charges at 0.1 per A^3.  k space: `se_kspace`, SE window,",
+          "eta = 0.5.  Real space: `se_rs_eval`, xi = 0.3.  The fits are the constants",
+          "`se_cost_model_mi355x` returns (non-negative least squares on relative",
+          "residuals; terms as in `include/sekspace.h`).", ""]
+    for path in paths:
+        with open(path) as f:
+            rec = json.loads(f.readline())
+        md += ["", f"## {rec['dtype'].upper()}", "", "| term | seconds per unit |", "|---|---|"]
+        md += [f"| {k} | {v:.4e} |" for k, v in rec["model"].items()]
+        dev = rec["max_rel_dev"]
+        md += ["", f"Largest relative deviation of the fit: k space {dev['kspace']:.2f}, "
+               f"real space {dev['real']:.2f}.", "", "Real-space points (us):", "",
+               "| N | rc | measured |", "|---|---|---|"]
+        md += [f"| {p['N']} | {p['rc']:g} | {p['t'] * 1e6:.1f} |" for p in rec["real_points"]]
+        md += ["", "k-space points (us):", "", "| N | M | P | measured |", "|---|---|---|---|"]
+        md += [f"| {p['N']} | {p['M']} | {p['P']} | {p['t'] * 1e6:.1f} |"
+               for p in rec["kspace_points"]]
+    return "\n".join(md) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--dtype", choices=("f32", "f64"), default="f32")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--markdown", nargs="+", metavar="JSON",
+                    help="print the fits of earlier runs as markdown (host only)")
     a = ap.parse_args(argv)
+    if a.markdown:
+        print(markdown(a.markdown), end="")
+        return
     kpts, rpts = measure(a.dtype, a.reps)
     model, ek, er = fit(a.dtype, kpts, rpts)
     rec = {"dtype": a.dtype, "gpu": torch.cuda.get_device_name(0), "model": model,

@@ -250,13 +250,13 @@ se_status se_cost_model_mi355x(int dtype, se_cost_model *m) {
   // Non-negative least-squares fits of the model to se_kspace and se_rs_eval
   // times on an MI355X (calibrate.py of this package; 60 k-space and 15
   // real-space configurations per precision).
-  // Largest relative deviation of the fit: 29% (FP32), 25% (FP64).
+  // Largest relative deviation of the fit: 28% (FP32), 19% (FP64).
   if (dtype == SE_FP32) {
-    *m = se_cost_model{2.2373e-05, 8.7386e-12, 1.1716e-12, 7.8036e-09, 8.0868e-13,
-                       3.5440e-05, 9.9003e-11, 3.2998e-13, 2.2721e-12, 1.4419e-11, 0.0};
+    *m = se_cost_model{2.7460e-05, 4.3858e-11, 1.4148e-12, 4.5958e-09, 7.3412e-13,
+                       3.8216e-05, 9.8504e-11, 3.1094e-13, 2.9073e-12, 1.1430e-11, 0.0};
   } else if (dtype == SE_FP64) {
-    *m = se_cost_model{2.6680e-05, 0.0, 6.6887e-12, 1.7401e-08, 2.1290e-12,
-                       3.6009e-05, 1.4799e-10, 6.0737e-13, 6.8980e-12, 0.0, 1.9966e-12};
+    *m = se_cost_model{3.4173e-05, 0.0, 7.4489e-12, 1.4449e-08, 2.1344e-12,
+                       3.6777e-05, 1.3219e-10, 5.8826e-13, 6.5268e-12, 0.0, 1.8870e-12};
   } else {
     return bad("unknown dtype");
   }
