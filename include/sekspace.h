@@ -112,8 +112,8 @@ enum {
     SE_STAGE_GATHER,         /* step 6 (se_gather or se_backward)            */
     SE_STAGE_FFT_XY,         /* step 3, x and y in one pass per z plane: in
                                 place of FFT_X + FFT_Y where an M x (M/2+1)
-                                plane fits in LDS twice (FP32 M <= 128, FP64
-                                M <= 96, compiled sizes)                     */
+                                plane fits in LDS (FP32 M <= 192, FP64
+                                M <= 128, compiled sizes)                    */
     SE_STAGE_IFFT_YX,        /* step 5, the same in place of IFFT_Y + IFFT_X */
     SE_NUM_STAGES
 };

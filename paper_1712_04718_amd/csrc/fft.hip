@@ -3,10 +3,11 @@
 //
 // Passes over a half spectrum stored as C[z][kx][y], kx = 0..M/2
 // (K = M/2 + 1 values), y contiguous, all built on one batched Stockham FFT
-// held in LDS.  Where a z plane fits in LDS twice (compiled M, FP32 M <= 128,
-// FP64 M <= 96) the x and y passes of each direction run as one plane pass
-// (k_fft_xy_r2c, k_fft_yx_c2r, below), so the sequence is xy, z, yx; other
-// sizes run the five passes:
+// held in LDS.  Where a z plane fits in LDS (compiled M: twice, ping-pong
+// stages, FP32 M <= 128 and FP64 M <= 96; once, in-place stages, FP32
+// M = 144..192 and FP64 M = 120, 128) the x and y passes of each direction
+// run as one plane pass (k_fft_xy_r2c, k_fft_yx_c2r, below), so the sequence
+// is xy, z, yx; other sizes run the five passes:
 //   x_r2c : pairs of real rows packed as one complex row, transformed, and
 //           split into two half spectra, written as runs along y;
 //   y_fwd : FFT of B contiguous y pencils (consecutive (z, kx));
@@ -239,6 +240,60 @@ __device__ inline cplx_t<R> *fft_batch_ct(cplx_t<R> *in, cplx_t<R> *out, const c
   }
 }
 
+// The same stages in one buffer: each thread reads its butterflies into
+// registers, the work-group waits, and the results go back to the same LDS
+// (the Stockham permutation of the stage), for plane buffers that fit in LDS
+// only once.
+template <typename R, int M, int B, int PB, int NT, int RAD, int NS>
+__device__ inline void stockham_stage_inplace(cplx_t<R> *buf, const cplx_t<R> *tw) {
+  using C = cplx_t<R>;
+  constexpr int NB = M / RAD, TOTAL = NB * B, TSTEP = M / (NS * RAD);
+  constexpr int NIT = (TOTAL + NT - 1) / NT;
+  C v[NIT][RAD];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int t = it * NT + static_cast<int>(threadIdx.x);
+    if (TOTAL % NT == 0 || t < TOTAL) {
+      const int j = t / B, b = t - j * B;
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[it][r] = buf[(j + r * NB) * PB + b];
+      if (NS > 1 && k != 0) {
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) v[it][r] = cmul(v[it][r], tw[r * k * TSTEP]);
+      }
+      if constexpr (RAD == 2) dft2<R, C>(v[it]);
+      if constexpr (RAD == 3) dft3<R, C>(v[it]);
+      if constexpr (RAD == 4) dft4<R, C>(v[it]);
+      if constexpr (RAD == 5) dft5<R, C>(v[it]);
+      if constexpr (RAD == 8) dft8<R, C>(v[it]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int t = it * NT + static_cast<int>(threadIdx.x);
+    if (TOTAL % NT == 0 || t < TOTAL) {
+      const int j = t / B, b = t - j * B;
+      const int q = j / NS, k = j - q * NS;
+      const int dst = q * NS * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf[(dst + r * NS) * PB + b] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, int M, int B, int PB, int NT, int STAGE, int NS>
+__device__ inline void fft_batch_inplace(cplx_t<R> *buf, const cplx_t<R> *tw) {
+  constexpr RadixList L = radix_list(M);
+  if constexpr (STAGE < L.n) {
+    constexpr int RAD = L.r[STAGE];
+    stockham_stage_inplace<R, M, B, PB, NT, RAD, NS>(buf, tw);
+    fft_batch_inplace<R, M, B, PB, NT, STAGE + 1, NS * RAD>(buf, tw);
+  }
+}
+
 // Forward FFT of the B pencils in buf0, compile-time (MC > 0) or run-time plan.
 template <typename R, int MC, int LGBC>
 __device__ inline cplx_t<R> *fft_any(cplx_t<R> *buf0, cplx_t<R> *buf1, int lgB, const FftPlan &pl,
@@ -452,7 +507,7 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
 
 // ------------------------------------------------- fused x-y plane passes
 //
-// When two M x (M/2 + 1) complex buffers fit in LDS, work-groups that each
+// When an M x (M/2 + 1) complex buffer fits in LDS, work-groups that each
 // hold a whole z plane do both in-plane transforms, so that the 3D FFT and
 // its inverse take three launches (xy, z with scaling, yx) instead of five:
 //   k_fft_xy_r2c: the plane's real rows in pairs as complex rows (x-major),
@@ -478,6 +533,10 @@ constexpr int kPlaneSplitFwd = 2, kPlaneSplitInv = 2;
 template <typename R, int M> constexpr size_t plane_lds_bytes() {
   return sizeof(cplx_t<R>) * (2 * PlaneGeom<M, 1>::BUF + M);
 }
+// one plane buffer (in-place stages), one work-group per plane
+template <typename R, int M> constexpr size_t plane1_lds_bytes() {
+  return sizeof(cplx_t<R>) * (PlaneGeom<M, 1>::BUF + M);
+}
 // threads per plane work-group: about four complex values per thread, 64..1024
 constexpr int plane_threads(int M) {
   int nt = 64;
@@ -487,15 +546,23 @@ constexpr int plane_threads(int M) {
 template <typename R, int M> constexpr bool plane_fits() {
   return plane_lds_bytes<R, M>() <= kMaxLds && M % 4 == 0 && (M / 2) % kPlaneSplitInv == 0;
 }
+template <typename R, int M> constexpr bool plane1_fits() {
+  return plane1_lds_bytes<R, M>() <= kMaxLds && M % 4 == 0;
+}
 
-template <typename R, int M, int NT, int NS>
+// ONE: a single plane buffer and in-place stages (NS = 1): the x FFT, the
+// split into the two half spectra (every thread first reads the values it
+// needs, then all write) and the y FFT all work in the one M x PB buffer.
+template <typename R, int M, int NT, int NS, bool ONE>
 __global__ void __launch_bounds__(NT)
 k_fft_xy_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec,
              const cplx_t<R> *__restrict__ tw_g) {
   using C = cplx_t<R>;
   using G = PlaneGeom<M, NS>;
   constexpr int H = G::H, K = G::K, PB = G::PB, KP = G::KP;
-  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + G::BUF, *twl = b1 + G::BUF;
+  static_assert(!ONE || NS == 1, "one plane buffer serves one work-group per plane");
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + G::BUF;
+  C *twl = ONE ? b1 : b1 + G::BUF;
   for (int i = threadIdx.x; i < M; i += NT) twl[i] = tw_g[i];
   const long long z = blockIdx.x / NS;
   const int k0 = static_cast<int>(blockIdx.x % NS) * KP;  // first kx pencil of this work-group
@@ -525,14 +592,19 @@ k_fft_xy_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec,
     }
   }
   __syncthreads();
-  C *X = fft_batch_ct<R, M, H, PB, NT, 0, 1>(b0, b1, twl);
-  C *Y = (X == b0) ? b1 : b0;
+  C *X, *Y;
+  if constexpr (ONE) {
+    fft_batch_inplace<R, M, H, PB, NT, 0, 1>(b0, twl);
+    X = Y = b0;
+  } else {
+    X = fft_batch_ct<R, M, H, PB, NT, 0, 1>(b0, b1, twl);
+    Y = (X == b0) ? b1 : b0;
+  }
   // Z = FFT(r1 + i r2): R1[k] = (Z[k] + conj Z[M-k]) / 2 (row 2b),
   // R2[k] = (Z[k] - conj Z[M-k]) / 2i (row 2b + 1); element y of this
   // work-group's pencil kx = k0 + kk (zero past the last one)
-  for (int i = threadIdx.x; i < H * KP; i += NT) {
-    const int b = i / KP, kk = i - b * KP, k = k0 + kk;
-    C r1, r2;
+  const auto split = [&](int b, int kk, C &r1, C &r2) {
+    const int k = k0 + kk;
     if (k < K) {
       const C zk = X[k * PB + b];
       const C zm = X[(k == 0 ? 0 : M - k) * PB + b];
@@ -543,11 +615,40 @@ k_fft_xy_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec,
     } else {
       r1.x = r1.y = r2.x = r2.y = R(0);
     }
-    Y[(2 * b) * PB + kk] = r1;
-    Y[(2 * b + 1) * PB + kk] = r2;
+  };
+  const C *S;
+  if constexpr (ONE) {
+    constexpr int NSP = H * KP, PS = (NSP + NT - 1) / NT;
+    C r1v[PS], r2v[PS];
+#pragma unroll
+    for (int it = 0; it < PS; ++it) {
+      const int i = threadIdx.x + it * NT;
+      if (NSP % NT == 0 || i < NSP) split(i / KP, i % KP, r1v[it], r2v[it]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < PS; ++it) {
+      const int i = threadIdx.x + it * NT;
+      if (NSP % NT == 0 || i < NSP) {
+        const int b = i / KP, kk = i - b * KP;
+        Y[(2 * b) * PB + kk] = r1v[it];
+        Y[(2 * b + 1) * PB + kk] = r2v[it];
+      }
+    }
+    __syncthreads();
+    fft_batch_inplace<R, M, KP, PB, NT, 0, 1>(Y, twl);
+    S = Y;
+  } else {
+    for (int i = threadIdx.x; i < H * KP; i += NT) {
+      const int b = i / KP, kk = i - b * KP;
+      C r1, r2;
+      split(b, kk, r1, r2);
+      Y[(2 * b) * PB + kk] = r1;
+      Y[(2 * b + 1) * PB + kk] = r2;
+    }
+    __syncthreads();
+    S = fft_batch_ct<R, M, KP, PB, NT, 0, 1>(Y, X, twl);
   }
-  __syncthreads();
-  const C *S = fft_batch_ct<R, M, KP, PB, NT, 0, 1>(Y, X, twl);
   C *out = spec + (z * K + k0) * M;
   const int nk = min(KP, K - k0);
   for (int i = threadIdx.x; i < nk * M; i += NT) {
@@ -556,14 +657,16 @@ k_fft_xy_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec,
   }
 }
 
-template <typename R, int M, int NT, int NS>
+template <typename R, int M, int NT, int NS, bool ONE>
 __global__ void __launch_bounds__(NT)
 k_fft_yx_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid,
              const cplx_t<R> *__restrict__ tw_g, EnergyOut eo) {
   using C = cplx_t<R>;
   using G = PlaneGeom<M, NS>;
   constexpr int K = G::K, PB = G::PB, HP = G::HP;
-  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + G::BUF, *twl = b1 + G::BUF;
+  static_assert(!ONE || NS == 1, "one plane buffer serves one work-group per plane");
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + G::BUF;
+  C *twl = ONE ? b1 : b1 + G::BUF;
   for (int i = threadIdx.x; i < M; i += NT) twl[i] = tw_g[i];
   const long long z = blockIdx.x / NS;
   const int p0 = static_cast<int>(blockIdx.x % NS) * HP;  // first row pair of this work-group
@@ -585,29 +688,60 @@ k_fft_yx_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid,
     }
   }
   __syncthreads();
-  C *Y = fft_batch_ct<R, M, K, PB, NT, 0, 1>(b0, b1, twl);  // conj of the inverse along y
-  C *X = (Y == b0) ? b1 : b0;
+  C *X, *Y;
+  if constexpr (ONE) {
+    fft_batch_inplace<R, M, K, PB, NT, 0, 1>(b0, twl);  // conj of the inverse along y
+    X = Y = b0;
+  } else {
+    Y = fft_batch_ct<R, M, K, PB, NT, 0, 1>(b0, b1, twl);  // conj of the inverse along y
+    X = (Y == b0) ? b1 : b0;
+  }
   // row pair b = p0 + bb (rows 2b, 2b + 1) with half spectra R1, R2 (the
   // conjugates of Y's): Z[k] = R1[k] + i R2[k] on 0..M/2 and
   // conj(R1[M-k]) + i conj(R2[M-k]) above, stored conjugated for the
   // inverse along x
-  for (int i = threadIdx.x; i < HP * K; i += NT) {
-    const int bb = i / K, k = i - bb * K, b = p0 + bb;
+  const auto rebuild = [&](int bb, int k, C &zz, C &zc) {
+    const int b = p0 + bb;
     const C r1 = cconj(Y[(2 * b) * PB + k]);
     const C r2 = cconj(Y[(2 * b + 1) * PB + k]);
-    C zz;
     zz.x = r1.x - r2.y;
     zz.y = -(r1.y + r2.x);
-    X[k * PB + bb] = zz;
-    if (k > 0 && k < M - k) {
-      C zc;
-      zc.x = r1.x + r2.y;
-      zc.y = -(r2.x - r1.y);
-      X[(M - k) * PB + bb] = zc;
+    zc.x = r1.x + r2.y;
+    zc.y = -(r2.x - r1.y);
+  };
+  const C *Zr;
+  if constexpr (ONE) {
+    constexpr int NRB = HP * K, PS = (NRB + NT - 1) / NT;
+    C zzv[PS], zcv[PS];
+#pragma unroll
+    for (int it = 0; it < PS; ++it) {
+      const int i = threadIdx.x + it * NT;
+      if (NRB % NT == 0 || i < NRB) rebuild(i / K, i % K, zzv[it], zcv[it]);
     }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < PS; ++it) {
+      const int i = threadIdx.x + it * NT;
+      if (NRB % NT == 0 || i < NRB) {
+        const int bb = i / K, k = i - bb * K;
+        X[k * PB + bb] = zzv[it];
+        if (k > 0 && k < M - k) X[(M - k) * PB + bb] = zcv[it];
+      }
+    }
+    __syncthreads();
+    fft_batch_inplace<R, M, HP, PB, NT, 0, 1>(X, twl);
+    Zr = X;
+  } else {
+    for (int i = threadIdx.x; i < HP * K; i += NT) {
+      const int bb = i / K, k = i - bb * K;
+      C zz, zc;
+      rebuild(bb, k, zz, zc);
+      X[k * PB + bb] = zz;
+      if (k > 0 && k < M - k) X[(M - k) * PB + bb] = zc;
+    }
+    __syncthreads();
+    Zr = fft_batch_ct<R, M, HP, PB, NT, 0, 1>(X, Y, twl);
   }
-  __syncthreads();
-  const C *Zr = fft_batch_ct<R, M, HP, PB, NT, 0, 1>(X, Y, twl);
   R *out = grid + z * M * M;
   for (int i = threadIdx.x; i < HP * M; i += NT) {
     const int bb = i / M, x = i - bb * M, b = p0 + bb;
@@ -726,25 +860,27 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
 }
 
 // The three-launch sequence with the fused plane passes (compile-time M
-// whose plane buffers fit in LDS).
-template <typename R, int MC>
+// whose plane buffers fit in LDS: twice with NSF and NSI work-groups per
+// plane, or, ONE, once with one work-group per plane).
+template <typename R, int MC, bool ONE>
 hipError_t fft_run_planes(se_plan &p, double *E_dev) {
   using C = cplx_t<R>;
   constexpr int LZ = fft_lgb(MC, sizeof(R), kPassZ);
   constexpr int NT = plane_threads(MC);
-  constexpr size_t lds = plane_lds_bytes<R, MC>();
-  constexpr unsigned nfwd = MC * kPlaneSplitFwd, ninv = MC * kPlaneSplitInv;
+  constexpr int NSF = ONE ? 1 : kPlaneSplitFwd, NSI = ONE ? 1 : kPlaneSplitInv;
+  constexpr size_t lds = ONE ? plane1_lds_bytes<R, MC>() : plane_lds_bytes<R, MC>();
+  constexpr unsigned nfwd = MC * NSF, ninv = MC * NSI;
   if (MC != p.prm.M || LZ != p.fft_lgb[kPassZ] || p.fft_threads != kThreads)
     return hipErrorInvalidValue;
   hipError_t e;
   if (lds > 65536) {
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(
-                                     &k_fft_xy_r2c<R, MC, NT, kPlaneSplitFwd>),
+                                     &k_fft_xy_r2c<R, MC, NT, NSF, ONE>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  static_cast<int>(lds))) != hipSuccess)
       return e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(
-                                     &k_fft_yx_c2r<R, MC, NT, kPlaneSplitInv>),
+                                     &k_fft_yx_c2r<R, MC, NT, NSI, ONE>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  static_cast<int>(lds))) != hipSuccess)
       return e;
@@ -753,7 +889,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
   C *spec = static_cast<C *>(p.buf.spec);
   const C *tw = static_cast<const C *>(p.buf.twiddle);
   stage_begin(p, SE_STAGE_FFT_XY);
-  launch_on(&p, k_fft_xy_r2c<R, MC, NT, kPlaneSplitFwd>, nfwd, NT, lds, p.stream, static_cast<const R *>(p.buf.grid), spec, tw);
+  launch_on(&p, k_fft_xy_r2c<R, MC, NT, NSF, ONE>, nfwd, NT, lds, p.stream, static_cast<const R *>(p.buf.grid), spec, tw);
   stage_end(p, SE_STAGE_FFT_XY);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double tpl = 2.0 * M_PI / p.prm.L;
@@ -766,7 +902,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
       launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, p.fft_threads, lds_z, p.stream, 
           spec, spec2, p.fft, LZ, tw, static_cast<const double *>(p.buf.axis_f),
           static_cast<const double *>(p.buf.axis_k2), p.wscale, nullptr, d, tpl);
-      launch_on(&p, k_fft_yx_c2r<R, MC, NT, kPlaneSplitInv>, ninv, NT, lds, p.stream, 
+      launch_on(&p, k_fft_yx_c2r<R, MC, NT, NSI, ONE>, ninv, NT, lds, p.stream, 
           spec2, static_cast<R *>(p.buf.field) + static_cast<long long>(d) * MC * MC * MC, tw,
           none);
       if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -782,14 +918,16 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
   const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.part, p.bin_parts, self_coef,
                      E_dev};
   stage_begin(p, SE_STAGE_IFFT_YX);
-  launch_on(&p, k_fft_yx_c2r<R, MC, NT, kPlaneSplitInv>, ninv, NT, lds, p.stream, spec, static_cast<R *>(p.buf.grid), tw, eo);
+  launch_on(&p, k_fft_yx_c2r<R, MC, NT, NSI, ONE>, ninv, NT, lds, p.stream, spec, static_cast<R *>(p.buf.grid), tw, eo);
   stage_end(p, SE_STAGE_IFFT_YX);
   return hipGetLastError();
 }
 
 template <typename R, int MC>
 hipError_t fft_run(se_plan &p, double *E_dev) {
-  if constexpr (MC > 0 && plane_fits<R, MC>()) return fft_run_planes<R, MC>(p, E_dev);
+  if constexpr (MC > 0 && plane_fits<R, MC>()) return fft_run_planes<R, MC, false>(p, E_dev);
+  if constexpr (MC > 0 && !plane_fits<R, MC>() && plane1_fits<R, MC>())
+    return fft_run_planes<R, MC, true>(p, E_dev);
   // compiled pencils per work-group of each pass (ignored for MC = 0)
   constexpr int LX = MC > 0 ? fft_lgb(MC, sizeof(R), kPassX) : 0;
   constexpr int LY = MC > 0 ? fft_lgb(MC, sizeof(R), kPassY) : 0;

@@ -15,9 +15,11 @@ FIVE_PASSES = {"fft_x", "fft_y", "ifft_y", "ifft_x"}
 PLANE_PASSES = {"fft_xy", "ifft_yx"}
 
 
-# M = 40: the plane fits in LDS, so x and y run as one pass each way;
-# M = 144 in FP32 does not fit and runs the five separate passes
-@pytest.mark.parametrize("M,fft_stages", [(40, PLANE_PASSES), (144, FIVE_PASSES)])
+# M = 40 and M = 192: the plane fits in LDS (twice, or once with in-place
+# stages), so x and y run as one pass each way; M = 216 in FP32 does not
+# fit and runs the five separate passes
+@pytest.mark.parametrize("M,fft_stages", [(40, PLANE_PASSES), (192, PLANE_PASSES),
+                                          (216, FIVE_PASSES)])
 def test_stage_means_cover_every_launch_and_reset(M, fft_stages):
     print(f"[timing] N=3000 L=20 M={M} P=8 fp32, 40 steps", flush=True)
     rng = np.random.default_rng(11)
