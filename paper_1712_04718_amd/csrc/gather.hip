@@ -10,8 +10,8 @@
 // the tile's particles touch is staged in LDS.  Lane (group, jx) of a wave's
 // 64/S particle groups owns the x-offset jx of one particle and sums over
 // the S^2 (jy, jz) offsets, its sums over jy compensated (Kahan); the S
-// lanes of a particle are then combined (shuffle tree for S = 4, 8, 16; in
-// LDS, compensated, otherwise).
+// lanes of a particle are then combined (for S = 4, 8, 16 by a tree of DPP
+// row moves, without the LDS; otherwise in LDS, compensated).
 // After the block barrier the waves take the tile's particles in a strided
 // loop with no further block barrier (k_gather_lane):
 //   Gaussian window: each lane evaluates three factors (x, y, z at its own
@@ -62,6 +62,30 @@ constexpr size_t gather_lane_lds(int real_size, int window, int S, int T) {
 // three exponentials per particle (instead of one thread computing all 3S in
 // a phase of its own between barriers).  B-spline: three lanes of the group
 // run the recursion, one axis each, and share factors and derivatives.
+// One lane's value from another lane of its 16-lane row (DPP row move; the
+// source lane is fixed by CTRL), 0 where the source lies outside the row.
+template <int CTRL> __device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL> __device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+// Sum of the S lanes of a group (S = 2..16, a power of two; groups start at
+// multiples of S) in the group's first lane: partial sums at lane distances
+// S/2, ..., 2, 1, each lane adding the value of the lane that distance above
+// it (row shifts by 8 and 4, then quad permutations that swap pairs and
+// neighbours).
+template <int S, typename R> __device__ inline R group_sum_first(R v) {
+  static_assert(S >= 2 && S <= 16 && (S & (S - 1)) == 0, "a power-of-two group within a row");
+  if constexpr (S >= 16) v += dpp_move<0x108>(v);  // row_shl:8, lane i + 8
+  if constexpr (S >= 8) v += dpp_move<0x104>(v);   // row_shl:4, lane i + 4
+  if constexpr (S >= 4) v += dpp_move<0x4e>(v);    // quad_perm [2,3,0,1], lane i ^ 2
+  v += dpp_move<0xb1>(v);                          // quad_perm [1,0,3,2], lane i ^ 1
+  return v;
+}
+
 template <typename R, int WIN, int S, int T>
 __global__ void __launch_bounds__(kTileThreads)
 k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ sorted,
@@ -120,7 +144,9 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
       const int i = tid + (k0 + k) * kTileThreads;
       if (k0 + k < NST && i < TS3) {
         const int r = i / TS, lx = i - r * TS;
-        v[k] = phi_grid[rowtab[r] + xtab[lx]];
+        // byte offset from the grid's base in 32 bits (grids stay below 4 GB)
+        const unsigned off = static_cast<unsigned>(rowtab[r] + xtab[lx]) * sizeof(R);
+        v[k] = *reinterpret_cast<const R *>(reinterpret_cast<const char *>(phi_grid) + off);
       }
     }
 #pragma unroll
@@ -231,13 +257,10 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     if constexpr (POW2) {
-#pragma unroll
-      for (int o = S / 2; o > 0; o >>= 1) {
-        t0 += __shfl_xor(t0, o);
-        t1 += __shfl_xor(t1, o);
-        t2 += __shfl_xor(t2, o);
-        t3 += __shfl_xor(t3, o);
-      }
+      t0 = group_sum_first<S>(t0);
+      t1 = group_sum_first<S>(t1);
+      t2 = group_sum_first<S>(t2);
+      t3 = group_sum_first<S>(t3);
     } else {
       R *mine = wred + lane * 4;
       mine[0] = t0;
