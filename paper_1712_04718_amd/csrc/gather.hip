@@ -10,8 +10,9 @@
 // the tile's particles touch is staged in LDS.  Lane (group, jx) of a wave's
 // 64/S particle groups owns the x-offset jx of one particle and sums over
 // the S^2 (jy, jz) offsets, its sums over jy compensated (Kahan); the S
-// lanes of a particle are then combined (for S = 4, 8, 16 by a tree of DPP
-// row moves, without the LDS; otherwise in LDS, compensated).
+// lanes of a particle are then combined with DPP lane moves, without the
+// LDS (for S = 4, 8, 16 a tree of row moves; otherwise the group's first
+// lane adds the S values in lane order, compensated).
 // After the block barrier the waves take the tile's particles in a strided
 // loop with no further block barrier (k_gather_lane):
 //   Gaussian window: each lane evaluates three factors (x, y, z at its own
@@ -39,9 +40,9 @@ template <typename R> struct Kahan {
   __device__ inline R value() const { return s - c; }
 };
 
-// LDS of k_gather_lane: the block of Phi, the lane-sum slots (S not a power
-// of two), then one region that holds the staging tables (row and column
-// offsets) until the block barrier and the groups' factor slots after it;
+// LDS of k_gather_lane: the block of Phi, then one region that holds the
+// staging tables (row and column offsets) until the block barrier and the
+// groups' factor slots after it;
 // sharing it keeps three 16-point-tile work-groups within a CU's LDS.
 constexpr int gather_slot(int window, int S) { return window == kGauss ? 2 * S : 6 * S; }
 constexpr size_t gather_lane_lds(int real_size, int window, int S, int T) {
@@ -50,7 +51,6 @@ constexpr size_t gather_lane_lds(int real_size, int window, int S, int T) {
       static_cast<size_t>(real_size) * (kTileThreads / 64) * (64 / S) * gather_slot(window, S);
   const size_t tables = 4 * (TS * TS + TS);
   return real_size * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) +
-         ((S & (S - 1)) ? static_cast<size_t>(real_size) * kTileThreads * 4 : 0) +
          (wf > tables ? wf : tables);
 }
 
@@ -99,17 +99,15 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
   constexpr int NWAVES = kTileThreads / 64;
   constexpr bool POW2 = (S & (S - 1)) == 0;
   constexpr size_t BLK = sizeof(R) * ((TS3 + 3) & ~3);
-  constexpr size_t RED = POW2 ? 0 : sizeof(R) * kTileThreads * 4;
 
   const int tile = xcd_local(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   R *blk = reinterpret_cast<R *>(h_smem);
-  R *red = reinterpret_cast<R *>(h_smem + BLK);
   // the staging tables and the factor slots share one region: the tables
   // are last read before the block barrier, the slots first written after it
-  R *wfac = reinterpret_cast<R *>(h_smem + BLK + RED);
-  int *rowtab = reinterpret_cast<int *>(h_smem + BLK + RED), *xtab = rowtab + TS * TS;
+  R *wfac = reinterpret_cast<R *>(h_smem + BLK);
+  int *rowtab = reinterpret_cast<int *>(h_smem + BLK), *xtab = rowtab + TS * TS;
 
   // Stage the block (batched loads into registers, then LDS stores; grid
   // offsets from row and column tables).
@@ -161,7 +159,6 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
   const R cg = static_cast<R>(wc.cg), beta = static_cast<R>(wc.beta);
   const R dc = static_cast<R>(wc.dcoef);
   R *gslot = wfac + (wave * GROUPS + grp) * SLOT;  // this group's shared factors
-  R *wred = red + wave * 64 * 4;
   for (; active && c < end; c += STRIDE) {
     const int cn = c + STRIDE;
     SortedParticle<R> nsp{};
@@ -262,31 +259,28 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
       t2 = group_sum_first<S>(t2);
       t3 = group_sum_first<S>(t3);
     } else {
-      R *mine = wred + lane * 4;
-      mine[0] = t0;
-      mine[1] = t1;
-      mine[2] = t2;
-      mine[3] = t3;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (jx == 0) {
-        Kahan<R> k0, k1, k2, k3;
-        const R *g = wred + grp * S * 4;
+      // the group's first lane adds the S lane values in lane order,
+      // compensated, the values moving down one lane per step
+      Kahan<R> k0, k1, k2, k3;
+      k0.add(t0);
+      k1.add(t1);
+      k2.add(t2);
+      k3.add(t3);
 #pragma unroll
-        for (int l = 0; l < S; ++l) {
-          k0.add(g[4 * l + 0]);
-          k1.add(g[4 * l + 1]);
-          k2.add(g[4 * l + 2]);
-          k3.add(g[4 * l + 3]);
-        }
-        t0 = k0.value();
-        t1 = k1.value();
-        t2 = k2.value();
-        t3 = k3.value();
+      for (int l = 1; l < S; ++l) {
+        t0 = dpp_move<0x130>(t0);  // wave_shl:1, lane i + 1
+        t1 = dpp_move<0x130>(t1);
+        t2 = dpp_move<0x130>(t2);
+        t3 = dpp_move<0x130>(t3);
+        k0.add(t0);
+        k1.add(t1);
+        k2.add(t2);
+        k3.add(t3);
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+      t0 = k0.value();
+      t1 = k1.value();
+      t2 = k2.value();
+      t3 = k3.value();
     }
     if (jx == 0) {
       const R q = sp.q;
