@@ -62,16 +62,6 @@ constexpr size_t gather_lane_lds(int real_size, int window, int S, int T) {
 // three exponentials per particle (instead of one thread computing all 3S in
 // a phase of its own between barriers).  B-spline: three lanes of the group
 // run the recursion, one axis each, and share factors and derivatives.
-// One lane's value from another lane of its 16-lane row (DPP row move; the
-// source lane is fixed by CTRL), 0 where the source lies outside the row.
-template <int CTRL> __device__ inline float dpp_move(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
-}
-template <int CTRL> __device__ inline double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
-  return __hiloint2double(hi, lo);
-}
 // Sum of the S lanes of a group (S = 2..16, a power of two; groups start at
 // multiples of S) in the group's first lane: partial sums at lane distances
 // S/2, ..., 2, 1, each lane adding the value of the lane that distance above

@@ -51,6 +51,45 @@ __device__ inline int xcd_local(int b, int G) {
   return b < q * kXcds ? (b % kXcds) * q + b / kXcds : b;
 }
 
+// The value v of the lane that the DPP control CTRL selects (a row move
+// stays within the lane's row of 16 lanes, a wave shift moves by one lane),
+// 0 where that lane does not exist.
+template <int CTRL> __device__ inline int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL> __device__ inline float dpp_move(float v) {
+  return __int_as_float(dpp_move<CTRL>(__float_as_int(v)));
+}
+template <int CTRL> __device__ inline double dpp_move(double v) {
+  return __hiloint2double(dpp_move<CTRL>(__double2hiint(v)), dpp_move<CTRL>(__double2loint(v)));
+}
+template <int CTRL> __device__ inline long long dpp_move(long long v) {
+  const int lo = dpp_move<CTRL>(static_cast<int>(v & 0xffffffffLL));
+  const int hi = dpp_move<CTRL>(static_cast<int>(v >> 32));
+  return (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo);
+}
+// v of lane L (a wave-uniform value)
+template <int L> __device__ inline double read_lane(double v) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), L),
+                          __builtin_amdgcn_readlane(__double2loint(v), L));
+}
+template <int L> __device__ inline long long read_lane(long long v) {
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(v & 0xffffffffLL), L);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), L);
+  return (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo);
+}
+// v combined by op (associative and commutative, with 0 as a neutral value
+// for the lanes' values: a sum, or a maximum of non-negative values) over
+// the 64 lanes of the wave, valid in lane 0: DPP row moves reduce each row
+// of 16 lanes into its first lane, which lane 0 then reads.
+template <typename T, typename Op> __device__ inline T wave_reduce0(T v, Op op) {
+  v = op(v, dpp_move<0x108>(v));  // row_shl:8, lane i + 8
+  v = op(v, dpp_move<0x104>(v));  // row_shl:4, lane i + 4
+  v = op(v, dpp_move<0x4e>(v));   // quad_perm [2,3,0,1], lane i ^ 2
+  v = op(v, dpp_move<0xb1>(v));   // quad_perm [1,0,3,2], lane i ^ 1
+  return op(op(v, read_lane<16>(v)), op(read_lane<32>(v), read_lane<48>(v)));
+}
+
 // Anchor of a coordinate u in grid units: floor(u) reduced mod M into
 // [0, M), and the offset u - floor(u).  A non-finite u (or one beyond the
 // integer range) takes anchor 0 while its offset stays NaN, so the outputs

@@ -56,7 +56,7 @@ __device__ inline double tile_bound(const SortedParticle<R> *__restrict__ sorted
   double m = 0.0;
   for (int p = start + tid; p < end; p += kTileThreads)
     m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  m = wave_reduce0(m, [](double a, double b) { return fmax(a, b); });
   double *red_max = red;
   long long *red_u = reinterpret_cast<long long *>(red + NWAVES);
   if ((tid & 63) == 0) red_max[tid >> 6] = m;
@@ -70,7 +70,7 @@ __device__ inline double tile_bound(const SortedParticle<R> *__restrict__ sorted
       u += w <= 1048576.0 ? static_cast<long long>(w) : 0LL;
     }
   }
-  for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
+  u = wave_reduce0(u, [](long long a, long long b) { return a + b; });
   if ((tid & 63) == 0) red_u[tid >> 6] = u;
   __syncthreads();
   long long usum = 0;
@@ -113,7 +113,7 @@ __device__ inline double tile_bound_yz(const SortedParticle<R> *__restrict__ sor
   double m = 0.0;
   for (int p = start + tid; p < end; p += kTileThreads)
     m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  m = wave_reduce0(m, [](double a, double b) { return fmax(a, b); });
   if ((tid & 63) == 0) red[tid >> 6] = m;
   __syncthreads();
   double qmax = 0.0;
@@ -154,7 +154,7 @@ __device__ inline double tile_bound_yz(const SortedParticle<R> *__restrict__ sor
     }
     bmax = fmax(bmax, b);
   }
-  for (int o = 32; o > 0; o >>= 1) bmax = fmax(bmax, __shfl_xor(bmax, o));
+  bmax = wave_reduce0(bmax, [](double a, double b) { return fmax(a, b); });
   if ((tid & 63) == 0) red[NWAVES + (tid >> 6)] = bmax;
   __syncthreads();
   double bm = 0.0;
