@@ -61,7 +61,7 @@ __device__ inline int particle_tile(const R *__restrict__ x, const R *__restrict
 // thread 0.
 template <int NTHR = kThreads>
 __device__ inline void block_sum_to(double v, double *out) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v = wave_reduce0(v, [](double a, double b) { return a + b; });
   __shared__ double red[NTHR / 64];
   const int tid = threadIdx.x;
   if ((tid & 63) == 0) red[tid >> 6] = v;
@@ -198,12 +198,7 @@ k_bin_scan(int *__restrict__ counts, int *__restrict__ offsets, int ntiles) {
     for (int k = 0; k < kScanPer; ++k) local += w[k];
   }
   const int lane = tid & 63, wave = tid >> 6;
-  int incl = local;  // inclusive scan over the lanes of the wave
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int u = __shfl_up(incl, o);
-    if (lane >= o) incl += u;
-  }
+  const int incl = wave_inclusive_scan(local);  // over the lanes of the wave
   __shared__ int wsum[kScanThreads / 64];
   if (lane == 63) wsum[wave] = incl;
   __syncthreads();
@@ -239,7 +234,7 @@ constexpr int kScanPerThread = kScanChunk / kThreads;
 static_assert(kScanChunk % kThreads == 0, "whole chunks per work-group");
 
 __device__ inline int block_sum_int(int v, int *red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v = wave_reduce0(v, [](int a, int b) { return a + b; });
   const int tid = threadIdx.x;
   if ((tid & 63) == 0) red[tid >> 6] = v;
   __syncthreads();
@@ -276,12 +271,7 @@ k_bin_scan_apply(int *__restrict__ counts, int *__restrict__ offsets, int ncells
   int local = 0;
 #pragma unroll
   for (int k = 0; k < kScanPerThread; ++k) local += v[k];
-  int incl = local;  // inclusive scan over the lanes of the wave
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int u = __shfl_up(incl, o);
-    if (lane >= o) incl += u;
-  }
+  const int incl = wave_inclusive_scan(local);  // over the lanes of the wave
   if (lane == 63) wsum[wave] = incl;
   __syncthreads();
   int run = base + incl - local;
@@ -353,12 +343,7 @@ k_bin_scatter_scan(int N, const R *__restrict__ x, const R *__restrict__ q, doub
 #pragma unroll
   for (int k = 0; k < kPer; ++k) local += v[k];
   const int lane = tid & 63, wave = tid >> 6;
-  int incl = local;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int u = __shfl_up(incl, o);
-    if (lane >= o) incl += u;
-  }
+  const int incl = wave_inclusive_scan(local);  // over the lanes of the wave
   __shared__ int wsum[kThreads / 64];
   if (lane == 63) wsum[wave] = incl;
   __syncthreads();

@@ -439,10 +439,9 @@ __device__ inline void write_energy(const EnergyOut &eo) {
   for (int b = threadIdx.x; b < eo.nparts; b += NT) se += eo.part[b];
   if (eo.self_coef != 0.0)
     for (int b = threadIdx.x; b < eo.nq; b += NT) sq += eo.qsq_part[b];
-  for (int o = 32; o > 0; o >>= 1) {
-    se += __shfl_xor(se, o);
-    sq += __shfl_xor(sq, o);
-  }
+  const auto add = [](double a, double b) { return a + b; };
+  se = wave_reduce0(se, add);
+  sq = wave_reduce0(sq, add);
   if ((threadIdx.x & 63) == 0) {
     wred[0][threadIdx.x >> 6] = se;
     wred[1][threadIdx.x >> 6] = sq;
@@ -848,7 +847,7 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
 
   // energy: one partial per block (a fixed tree over the lanes of each wave,
   // then the waves in order), added in a fixed order by the next pass
-  for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
+  e = wave_reduce0(e, [](double a, double b) { return a + b; });
   __shared__ double wred[kThreads / 64];
   if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = e;
   __syncthreads();

@@ -69,6 +69,7 @@ template <int CTRL> __device__ inline long long dpp_move(long long v) {
   return (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo);
 }
 // v of lane L (a wave-uniform value)
+template <int L> __device__ inline int read_lane(int v) { return __builtin_amdgcn_readlane(v, L); }
 template <int L> __device__ inline double read_lane(double v) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), L),
                           __builtin_amdgcn_readlane(__double2loint(v), L));
@@ -88,6 +89,20 @@ template <typename T, typename Op> __device__ inline T wave_reduce0(T v, Op op) 
   v = op(v, dpp_move<0x4e>(v));   // quad_perm [2,3,0,1], lane i ^ 2
   v = op(v, dpp_move<0xb1>(v));   // quad_perm [1,0,3,2], lane i ^ 1
   return op(op(v, read_lane<16>(v)), op(read_lane<32>(v), read_lane<48>(v)));
+}
+
+// Inclusive prefix sum of v over the 64 lanes of the wave (exact integer
+// arithmetic, so its order does not matter): DPP row shifts by 1, 2, 4, 8
+// scan each row of 16 lanes, then each row adds the totals of the rows
+// before it, read from their last lanes.
+__device__ inline int wave_inclusive_scan(int v) {
+  v += dpp_move<0x111>(v);  // row_shr:1, lane i - 1
+  v += dpp_move<0x112>(v);  // row_shr:2
+  v += dpp_move<0x114>(v);  // row_shr:4
+  v += dpp_move<0x118>(v);  // row_shr:8
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const int r0 = read_lane<15>(v), r1 = read_lane<31>(v), r2 = read_lane<47>(v);
+  return v + (lane >= 16 ? r0 : 0) + (lane >= 32 ? r1 : 0) + (lane >= 48 ? r2 : 0);
 }
 
 // Anchor of a coordinate u in grid units: floor(u) reduced mod M into
