@@ -188,11 +188,7 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
     // inclusive prefix sum of the counts nb_pre[1..NB], two per lane
     const int i1 = 2 * tid + 1, i2 = 2 * tid + 2;
     const int a = i1 <= NB ? nb_pre[i1] : 0, b = i2 <= NB ? nb_pre[i2] : 0;
-    int v = a + b;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int u = __shfl_up(v, o);
-      if (tid >= o) v += u;
-    }
+    const int v = wave_inclusive_scan(a + b);
     const int before = v - a - b;
     if (i1 <= NB) nb_pre[i1] = before + a;
     if (i2 <= NB) nb_pre[i2] = v;
@@ -324,7 +320,7 @@ k_rs_pairs(const SortedParticle<R> *__restrict__ sorted, const int2 *__restrict_
     }
   }
   // energy partial of this cell (fixed order)
-  for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
+  e = wave_reduce0(e, [](double a, double b) { return a + b; });
   if ((tid & 63) == 0) ered[tid >> 6] = e;
   __syncthreads();
   if (tid == 0) {
@@ -352,7 +348,7 @@ k_rs_energy(const double *__restrict__ epart, int n, double *__restrict__ E) {
 #pragma unroll
     for (int u = 0; u < U; ++u) s += v[u];
   }
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  s = wave_reduce0(s, [](double a, double b) { return a + b; });
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
