@@ -411,11 +411,14 @@ def test_wide_support_reaches_the_exact_sum():
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("window,M,P", [("gaussian", 30, 8), ("gaussian", 48, 12),
-                                        ("bspline", 32, 5), ("bspline", 30, 6)])
+                                        ("bspline", 32, 5), ("bspline", 30, 6),
+                                        ("gaussian", 144, 8), ("bspline", 128, 6)])
 def test_ik_forces(window, M, P, dtype):
     """SE_FLAG_IK_FORCE: forces by ik differentiation (section 3.1) against the
     oracle's; E and phi are those of the analytic plan; the field at points
-    and the adjoint (analytic, the exact gradient of E) are unchanged."""
+    and the adjoint (analytic, the exact gradient of E) are unchanged.  M = 144
+    (FP32) and M = 128 (FP64) take the plane passes with one LDS buffer, the
+    three field components included."""
     L, xi = 10.0, 1.2
     x, q = _rand(1100, L, 41)
     print(f"[ik] {window} M={M} P={P} {dtype}", flush=True)
