@@ -174,7 +174,7 @@ k_bin_count_run(int N, const R *__restrict__ x, const R *__restrict__ q, double 
 // One work-group: exclusive scan of the tile counts into offsets, and the
 // counts reset for the next call.  Each thread takes a contiguous chunk of
 // tiles and requests all its counts before using any; the chunk sums are
-// scanned within each wave by shuffles and across the waves through LDS
+// scanned within each wave by DPP row moves and across the waves through LDS
 // (one barrier).
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 32;  // counts per thread held in registers
@@ -310,9 +310,10 @@ k_bin_scatter(int N, const R *__restrict__ x, const R *__restrict__ q, double h,
 }
 
 // k_bin_scatter with the scan folded in: every work-group scans the tile
-// counts into LDS itself (a chunk of counts per thread, shuffles within the
-// waves, one barrier across them), work-group 0 also publishes the offsets,
-// and the counts are left for the consumer of the tiles to reset.  Saves the
+// counts into LDS itself (a chunk of counts per thread, DPP prefix sums
+// within the waves, one barrier across them), work-group 0 also publishes
+// the offsets, and the counts are left for the consumer of the tiles to
+// reset.  Saves the
 // one-work-group scan launch between counting and scattering.
 template <typename R>
 __global__ void __launch_bounds__(kThreads)
