@@ -9,18 +9,19 @@
 //
 // LDS accumulation in fixed point, with a per-tile scale 2^B / bound, where
 // bound is at least every partial sum the tile's block can hold: B = 30 in
-// 32-bit integers (FP32) and B = 62 in 64-bit integers (FP64).  The bound is
-// wmax * sum_tile |q| (wmax bounds every window value: beta^3 for the
-// Gaussian, 1 for B-splines), except for the FP32 Gaussian, whose 30-bit
-// quantum would otherwise dominate its rounding: there it is the tile's
-// charge histogram over (y, z) anchors convolved with the window's largest
-// values (tile_bound_yz), about ten times tighter on a water-like system.
-// No partial sum can leave (-2^(B+1), 2^(B+1)), each contribution is rounded
-// once, and the result does not depend on the order of the additions, so
-// both precisions are bitwise reproducible.  (Integer LDS atomics run far faster than floating-point ones
-// on this chip.)  An FP32 contribution has 24 significant bits while the
-// fixed point spans 30, so exact halves are common: they round to even,
-// which keeps the sum unbiased (rounding halves up would not).
+// 32-bit integers (FP32) and B = 50 in 64-bit integers (FP64, where every
+// contribution then lies below 2^51 and rounds to an integer with one FP64
+// add, round_to_int64).  The bound is the tile's charge histogram over
+// (y, z) anchors convolved with the window's largest values (tile_bound_yz),
+// about ten times tighter than wmax * sum_tile |q| on a water-like system,
+// so the fixed-point quantum stays below the rest of each precision's
+// rounding.  No partial sum can leave (-2^(B+1), 2^(B+1)), each contribution
+// is rounded once, and the result does not depend on the order of the
+// additions, so both precisions are bitwise reproducible.  (Integer LDS
+// atomics run far faster than floating-point ones on this chip.)  An FP32
+// contribution has 24 significant bits while the fixed point spans 30, so
+// exact halves are common: they round to even, which keeps the sum unbiased
+// (rounding halves up would not).
 // Work split (k_spread_lane, both windows): each wave holds 64/S particle
 // groups of S lanes; lane (group, jx) owns the x-offset jx of one particle,
 // evaluates the factors it needs itself (Gaussian: its x factor and all S
@@ -37,48 +38,21 @@ namespace {
 
 extern __shared__ __align__(16) unsigned char g_smem[];
 
+// v rounded to the nearest integer, ties to even, as a 64-bit two's
+// complement value, for |v| < 2^51: adding 1.5 2^52 leaves v's rounded
+// integer in the low bits of a double in [2^52, 2^53), whose bit pattern
+// grows by one per unit there.
+__device__ inline unsigned long long round_to_int64(double v) {
+  constexpr double kMagic = 6755399441055744.0;  // 1.5 2^52
+  return static_cast<unsigned long long>(__double_as_longlong(v + kMagic)) -
+         static_cast<unsigned long long>(__double_as_longlong(kMagic));
+}
+
 template <typename R> struct Acc;
 template <> struct Acc<float> { using T = int; };      // fixed point
 template <> struct Acc<double> { using T = long long; };  // fixed point
 
-// FP64 fixed-point scale of a tile (2^62 units leave the rounding far below
-// FP64 rounding, so the simple bound serves): a bound on sum |q| that does not depend
-// on the order of its particles (that order comes from atomics): qmax =
-// max |q| is exact, each particle contributes the integer
-// u = ceil(|q| / qmax * 2^20) >= |q| / qmax * 2^20, and integer sums are
-// exact, so qmax * sum(u) / 2^20 >= sum |q| is the same on every run.  Two
-// block reductions, one barrier each; red holds 2 NWAVES doubles.  A
-// non-finite charge weighs 0 here (the integer conversion stays defined).
-template <typename R, int NWAVES>
-__device__ inline double tile_bound(const SortedParticle<R> *__restrict__ sorted, int start,
-                                    int end, double *red) {
-  const int tid = threadIdx.x;
-  double m = 0.0;
-  for (int p = start + tid; p < end; p += kTileThreads)
-    m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
-  m = wave_reduce0(m, [](double a, double b) { return fmax(a, b); });
-  double *red_max = red;
-  long long *red_u = reinterpret_cast<long long *>(red + NWAVES);
-  if ((tid & 63) == 0) red_max[tid >> 6] = m;
-  __syncthreads();
-  double qmax = 0.0;
-  for (int w = 0; w < NWAVES; ++w) qmax = fmax(qmax, red_max[w]);
-  long long u = 0;
-  if (qmax > 0.0) {
-    for (int p = start + tid; p < end; p += kTileThreads) {
-      const double w = ceil(fabs(static_cast<double>(sorted[p].q)) / qmax * 1048576.0);
-      u += w <= 1048576.0 ? static_cast<long long>(w) : 0LL;
-    }
-  }
-  u = wave_reduce0(u, [](long long a, long long b) { return a + b; });
-  if ((tid & 63) == 0) red_u[tid >> 6] = u;
-  __syncthreads();
-  long long usum = 0;
-  for (int w = 0; w < NWAVES; ++w) usum += red_u[w];
-  return qmax * (static_cast<double>(usum) / 1048576.0);
-}
-
-// Bound on every partial sum the tile's block can hold, for the FP32
+// Bound on every partial sum the tile's block can hold, for the
 // fixed-point scale, independent of the order of the tile's particles (that
 // order comes from atomics).  A particle with anchor (ax, ay, az) in the tile
 // adds to block point (jx, jy, jz) the value q g_x g_y g_z with
@@ -97,7 +71,7 @@ __device__ inline double tile_bound(const SortedParticle<R> *__restrict__ sorted
 // factors.  On the 100k-atom water workload this bound is 11x tighter than
 // wmax sum |q| (the partial sums there stay far below the charge a tile
 // holds), which takes the FP32 fixed-point rounding of the forces from
-// 1.4e-6 to 1.3e-7.  LDS: U (T^2 integers), C (TS x T floats), red (2
+// 1.4e-6 to 1.3e-7 (and keeps the 50-bit FP64 quantum near 1e-13).  LDS: U (T^2 integers), C (TS x T floats), red (2
 // NWAVES doubles).  A non-finite charge weighs 0 (the integer conversion
 // stays defined).  Returns the bound divided by wmax (0 for a tile without
 // charge).
@@ -162,18 +136,16 @@ __device__ inline double tile_bound_yz(const SortedParticle<R> *__restrict__ sor
   return qmax * (bm / 1048576.0) * (1.0 + 1e-5);
 }
 
-// LDS of k_spread_lane: the fixed-point block, then (FP32) the bound's
-// histogram U (T^2 64-bit integers) and C (TS x T floats, rounded up to 8
-// bytes), then 128 bytes of reduction slots.
-constexpr size_t spread_lane_bound_lds(int real_size, int S, int T) {
-  return real_size == 4
-             ? 8 * static_cast<size_t>(T * T) + ((4 * static_cast<size_t>((T + S - 1) * T) + 7) & ~size_t(7))
-             : 0;
+// LDS of k_spread_lane: the fixed-point block, then the bound's histogram U
+// (T^2 64-bit integers) and C (TS x T floats, rounded up to 8 bytes), then
+// 128 bytes of reduction slots.
+constexpr size_t spread_lane_bound_lds(int S, int T) {
+  return 8 * static_cast<size_t>(T * T) + ((4 * static_cast<size_t>((T + S - 1) * T) + 7) & ~size_t(7));
 }
 constexpr size_t spread_lane_lds(int real_size, int S, int T) {
   const size_t TS = T + S - 1, acc = real_size == 4 ? 4 : 8;
   return acc * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) +
-         spread_lane_bound_lds(real_size, S, T) + 128;
+         spread_lane_bound_lds(S, T) + 128;
 }
 
 // The factors are evaluated by the lanes that use them (see the file
@@ -192,7 +164,7 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
   constexpr int GROUPS = 64 / S;
   constexpr int NWAVES = kTileThreads / 64;
   constexpr int OFF = Stencil<WIN, S>::OFF;
-  constexpr double kFix = sizeof(R) == 4 ? 1073741824.0 : 4611686018427387904.0;  // 2^30, 2^62
+  constexpr double kFix = sizeof(R) == 4 ? 1073741824.0 : 1125899906842624.0;  // 2^30, 2^50
   static_assert(2 * NWAVES * 8 <= 128, "reduction slots");
   static_assert(T <= 256, "local anchors are packed in 8 bits");
 
@@ -210,7 +182,7 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
   unsigned char *bnd = g_smem + sizeof(A) * ((TS3 + 3) & ~3);
   unsigned long long *U = reinterpret_cast<unsigned long long *>(bnd);
   float *C = reinterpret_cast<float *>(bnd + 8 * T * T);
-  double *red = reinterpret_cast<double *>(bnd + spread_lane_bound_lds(sizeof(R), S, T));
+  double *red = reinterpret_cast<double *>(bnd + spread_lane_bound_lds(S, T));
 
   const int wave = tid >> 6, lane = tid & 63;
   const int grp = lane / S, jx = lane - grp * S;
@@ -227,10 +199,7 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
   }
   for (int i = tid; i < TS3; i += kTileThreads) blk[i] = A(0);
   double bound;
-  if constexpr (sizeof(R) == 4)
-    bound = wmax * tile_bound_yz<R, S, T, NWAVES>(sorted, meta, start, end, wc, U, C, red);
-  else
-    bound = wmax * tile_bound<R, NWAVES>(sorted, start, end, red);
+  bound = wmax * tile_bound_yz<R, S, T, NWAVES>(sorted, meta, start, end, wc, U, C, red);
   const double scale = bound > 0.0 ? kFix / bound : 1.0;
   const double inv_scale = bound > 0.0 ? bound / kFix : 1.0;  // the barriers of the bound also
                                                               // order the clearing of blk
@@ -273,7 +242,7 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
           atomicAdd(row + (jz * TS + jy) * TS, __float2int_rn(wz * gy[jy]));
         else  // two's complement: the unsigned add is the signed one
           atomicAdd(reinterpret_cast<unsigned long long *>(row + (jz * TS + jy) * TS),
-                    static_cast<unsigned long long>(__double2ll_rn(wz * gy[jy])));
+                    round_to_int64(wz * gy[jy]));
       }
     }
     sp = nsp;
