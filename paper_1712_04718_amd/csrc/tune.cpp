@@ -250,13 +250,13 @@ se_status se_cost_model_mi355x(int dtype, se_cost_model *m) {
   // Non-negative least-squares fits of the model to se_kspace and se_rs_eval
   // times on an MI355X (calibrate.py of this package; 60 k-space and 15
   // real-space configurations per precision).
-  // Largest relative deviation of the fit: 28% (FP32), 19% (FP64).
+  // Largest relative deviation of the fit: 28% (FP32), 23% (FP64).
   if (dtype == SE_FP32) {
-    *m = se_cost_model{2.7460e-05, 4.3858e-11, 1.4148e-12, 4.5958e-09, 7.3412e-13,
-                       3.8216e-05, 9.8504e-11, 3.1094e-13, 2.9073e-12, 1.1430e-11, 0.0};
+    *m = se_cost_model{2.6235e-05, 4.4756e-11, 1.4806e-12, 4.1938e-09, 7.3363e-13,
+                       3.7230e-05, 9.7986e-11, 3.0431e-13, 2.8861e-12, 0.0, 1.2697e-12};
   } else if (dtype == SE_FP64) {
-    *m = se_cost_model{3.4173e-05, 0.0, 7.4489e-12, 1.4449e-08, 2.1344e-12,
-                       3.6777e-05, 1.3219e-10, 5.8826e-13, 6.5268e-12, 0.0, 1.8870e-12};
+    *m = se_cost_model{3.2834e-05, 0.0, 7.6880e-12, 1.3704e-08, 2.1280e-12,
+                       3.5091e-05, 1.4049e-10, 4.4957e-13, 6.4146e-12, 0.0, 2.0063e-12};
   } else {
     return bad("unknown dtype");
   }
