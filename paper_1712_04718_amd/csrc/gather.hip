@@ -42,8 +42,8 @@ template <typename R> struct Kahan {
 
 // LDS of k_gather_lane: the block of Phi, then one region that holds the
 // staging tables (row and column offsets) until the block barrier and the
-// groups' factor slots after it;
-// sharing it keeps three 16-point-tile work-groups within a CU's LDS.
+// groups' factor slots after it; sharing it keeps three 16-point-tile
+// work-groups within a CU's LDS.
 constexpr int gather_slot(int window, int S) { return window == kGauss ? 2 * S : 6 * S; }
 constexpr size_t gather_lane_lds(int real_size, int window, int S, int T) {
   const size_t TS = T + S - 1;
@@ -54,14 +54,6 @@ constexpr size_t gather_lane_lds(int real_size, int window, int S, int T) {
          (wf > tables ? wf : tables);
 }
 
-// The block of Phi is staged first; then each wave takes particle groups in
-// a strided loop without block barriers.  Gaussian: lane (group, jx)
-// evaluates three factors of its particle directly, g = beta e^{-cg t^2} at
-// t = jx + OFF - d along x, y and z, keeps its x factor and shares the y and
-// z ones with the group through the wave's LDS slot, so each lane computes
-// three exponentials per particle (instead of one thread computing all 3S in
-// a phase of its own between barriers).  B-spline: three lanes of the group
-// run the recursion, one axis each, and share factors and derivatives.
 // Sum of the S lanes of a group (S = 2..16, a power of two; groups start at
 // multiples of S) in the group's first lane: partial sums at lane distances
 // S/2, ..., 2, 1, each lane adding the value of the lane that distance above
@@ -76,6 +68,14 @@ template <int S, typename R> __device__ inline R group_sum_first(R v) {
   return v;
 }
 
+// The block of Phi is staged first; then each wave takes particle groups in
+// a strided loop without block barriers.  Gaussian: lane (group, jx)
+// evaluates three factors of its particle directly, g = beta e^{-cg t^2} at
+// t = jx + OFF - d along x, y and z, keeps its x factor and shares the y and
+// z ones with the group through the wave's LDS slot, so each lane computes
+// three exponentials per particle (instead of one thread computing all 3S in
+// a phase of its own between barriers).  B-spline: three lanes of the group
+// run the recursion, one axis each, and share factors and derivatives.
 template <typename R, int WIN, int S, int T>
 __global__ void __launch_bounds__(kTileThreads)
 k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ sorted,
@@ -133,7 +133,8 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
       if (k0 + k < NST && i < TS3) {
         const int r = i / TS, lx = i - r * TS;
         // byte offset from the grid's base in 32 bits (grids stay below 4 GB)
-        const unsigned off = static_cast<unsigned>(rowtab[r] + xtab[lx]) * sizeof(R);
+        const unsigned off =
+            static_cast<unsigned>(rowtab[r] + xtab[lx]) * static_cast<unsigned>(sizeof(R));
         v[k] = *reinterpret_cast<const R *>(reinterpret_cast<const char *>(phi_grid) + off);
       }
     }

@@ -82,7 +82,8 @@ template <int L> __device__ inline long long read_lane(long long v) {
 // v combined by op (associative and commutative, with 0 as a neutral value
 // for the lanes' values: a sum, or a maximum of non-negative values) over
 // the 64 lanes of the wave, valid in lane 0: DPP row moves reduce each row
-// of 16 lanes into its first lane, which lane 0 then reads.
+// of 16 lanes into its first lane, which lane 0 then reads.  Every lane of
+// the wave must be active.
 template <typename T, typename Op> __device__ inline T wave_reduce0(T v, Op op) {
   v = op(v, dpp_move<0x108>(v));  // row_shl:8, lane i + 8
   v = op(v, dpp_move<0x104>(v));  // row_shl:4, lane i + 4
@@ -94,7 +95,8 @@ template <typename T, typename Op> __device__ inline T wave_reduce0(T v, Op op) 
 // Inclusive prefix sum of v over the 64 lanes of the wave (exact integer
 // arithmetic, so its order does not matter): DPP row shifts by 1, 2, 4, 8
 // scan each row of 16 lanes, then each row adds the totals of the rows
-// before it, read from their last lanes.
+// before it, read from their last lanes.  Every lane of the wave must be
+// active.
 __device__ inline int wave_inclusive_scan(int v) {
   v += dpp_move<0x111>(v);  // row_shr:1, lane i - 1
   v += dpp_move<0x112>(v);  // row_shr:2

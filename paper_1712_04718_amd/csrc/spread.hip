@@ -71,10 +71,10 @@ template <> struct Acc<double> { using T = long long; };  // fixed point
 // factors.  On the 100k-atom water workload this bound is 11x tighter than
 // wmax sum |q| (the partial sums there stay far below the charge a tile
 // holds), which takes the FP32 fixed-point rounding of the forces from
-// 1.4e-6 to 1.3e-7 (and keeps the 50-bit FP64 quantum near 1e-13).  LDS: U (T^2 integers), C (TS x T floats), red (2
-// NWAVES doubles).  A non-finite charge weighs 0 (the integer conversion
-// stays defined).  Returns the bound divided by wmax (0 for a tile without
-// charge).
+// 1.4e-6 to 1.3e-7 (and keeps the 50-bit FP64 quantum near 1e-13).  LDS: U
+// (T^2 integers), C (TS x T floats), red (2 NWAVES doubles).  A non-finite
+// charge weighs 0 (the integer conversion stays defined).  Returns the bound
+// divided by wmax (0 for a tile without charge).
 template <typename R, int S, int T, int NWAVES>
 __device__ inline double tile_bound_yz(const SortedParticle<R> *__restrict__ sorted,
                                        const int2 *__restrict__ meta, int start, int end,
@@ -198,8 +198,8 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
     packed = meta[c].x;
   }
   for (int i = tid; i < TS3; i += kTileThreads) blk[i] = A(0);
-  double bound;
-  bound = wmax * tile_bound_yz<R, S, T, NWAVES>(sorted, meta, start, end, wc, U, C, red);
+  const double bound =
+      wmax * tile_bound_yz<R, S, T, NWAVES>(sorted, meta, start, end, wc, U, C, red);
   const double scale = bound > 0.0 ? kFix / bound : 1.0;
   const double inv_scale = bound > 0.0 ? bound / kFix : 1.0;  // the barriers of the bound also
                                                               // order the clearing of blk
