@@ -162,7 +162,7 @@ Sizes sizes_of(const se_params &p, int n_max, int ntiles, int bin_blocks, int zb
   auto al = [](size_t b) { return ((b ? b : 1) + 255) & ~static_cast<size_t>(255); };
   const size_t TS = T + p.P - 1;
   s.grid = al(M * M * M * rs);
-  s.ghost = al(T > 0 ? static_cast<size_t>(ntiles) * TS * TS * TS * rs : 0);
+  s.ghost = al(T > 0 ? static_cast<size_t>(ntiles) * sek::ghost_stride(static_cast<int>(TS)) * rs : 0);
   s.cover = al(T > 0 ? M * max_cover(p, T) * 4 : 0);
   s.cover_count = al(M * 4);
   s.spec = al(M * M * K * 2 * rs);

@@ -194,7 +194,7 @@ struct TargetBuffers {
 
 struct DeviceBuffers {
   void *grid = nullptr;       // M^3 real: the scaled grid Phi (input of gathering)
-  void *ghost = nullptr;      // ntiles * (T+S-1)^3 real: spread tile blocks
+  void *ghost = nullptr;      // ntiles * ghost_stride(T+S-1) real: spread tile blocks
   int *cover = nullptr;       // fold tables (FoldTables)
   int *cover_count = nullptr;
   void *spec = nullptr;       // M*M*(M/2+1) complex half spectrum
@@ -342,6 +342,11 @@ inline void launch_on(se_plan *tp, void (*kernel)(KArgs...), dim3 grid, dim3 blo
 size_t spread_lds_bytes(int real_size, int window, int S, int T);
 size_t gather_lds_bytes(int real_size, int window, int S, int T);
 constexpr size_t kMaxLds = 160 * 1024;
+
+// Values per tile block in the ghost array: the (T+S-1)^3 block rounded up
+// to a multiple of four, so that every block starts on 16 bytes and the
+// spread stores it 16 bytes per lane.
+__host__ __device__ constexpr int ghost_stride(int TS) { return (TS * TS * TS + 3) & ~3; }
 
 // gather modes
 constexpr int kGatherPotentialForce = 0;  // out_pot = phi, out_vec = F

@@ -3,9 +3,10 @@
 //
 // One work-group per tile of T^3 anchor points.  The particles anchored in
 // the tile touch a (T+S-1)^3 block of the grid, accumulated in LDS and then
-// stored, with plain coalesced stores, as the tile's own block of a "ghost"
-// array; a fold kernel then adds the overlapping blocks that cover each grid
-// point, so no grid zeroing and no global atomics are needed.
+// stored, with plain coalesced 16-byte stores, as the tile's own block of a
+// "ghost" array (blocks ghost_stride values apart); a fold kernel then adds
+// the overlapping blocks that cover each grid point, so no grid zeroing and
+// no global atomics are needed.
 //
 // LDS accumulation in fixed point, with a per-tile scale 2^B / bound, where
 // bound is at least every partial sum the tile's block can hold: B = 30 in
@@ -136,16 +137,15 @@ __device__ inline double tile_bound_yz(const SortedParticle<R> *__restrict__ sor
   return qmax * (bm / 1048576.0) * (1.0 + 1e-5);
 }
 
-// LDS of k_spread_lane: the fixed-point block, then the bound's histogram U
-// (T^2 64-bit integers) and C (TS x T floats, rounded up to 8 bytes), then
-// 128 bytes of reduction slots.
+// LDS of k_spread_lane: the fixed-point block (ghost_stride values), then
+// the bound's histogram U (T^2 64-bit integers) and C (TS x T floats,
+// rounded up to 8 bytes), then 128 bytes of reduction slots.
 constexpr size_t spread_lane_bound_lds(int S, int T) {
   return 8 * static_cast<size_t>(T * T) + ((4 * static_cast<size_t>((T + S - 1) * T) + 7) & ~size_t(7));
 }
 constexpr size_t spread_lane_lds(int real_size, int S, int T) {
-  const size_t TS = T + S - 1, acc = real_size == 4 ? 4 : 8;
-  return acc * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) +
-         spread_lane_bound_lds(S, T) + 128;
+  const size_t acc = real_size == 4 ? 4 : 8;
+  return acc * static_cast<size_t>(ghost_stride(T + S - 1)) + spread_lane_bound_lds(S, T) + 128;
 }
 
 // The factors are evaluated by the lanes that use them (see the file
@@ -160,10 +160,15 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
               const int *__restrict__ offsets, int *__restrict__ counts, WindowConsts wc,
               double wmax, R *__restrict__ ghost) {
   using A = typename Acc<R>::T;
-  constexpr int TS = T + S - 1, TS3 = TS * TS * TS;
+  constexpr int TS = T + S - 1, TSB = ghost_stride(TS);
   constexpr int GROUPS = 64 / S;
   constexpr int NWAVES = kTileThreads / 64;
   constexpr int OFF = Stencil<WIN, S>::OFF;
+  // the block is cleared and stored 16 bytes per lane
+  constexpr int NV = 16 / sizeof(R);
+  using VA = A __attribute__((ext_vector_type(NV)));
+  using VR = R __attribute__((ext_vector_type(NV)));
+  static_assert(TSB % NV == 0, "whole 16-byte vectors per block");
   constexpr double kFix = sizeof(R) == 4 ? 1073741824.0 : 1125899906842624.0;  // 2^30, 2^50
   static_assert(2 * NWAVES * 8 <= 128, "reduction slots");
   static_assert(T <= 256, "local anchors are packed in 8 bits");
@@ -173,13 +178,13 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
   const int tid = threadIdx.x;
   // the binning left this tile's count for its consumer to reset
   if (tid == 0) counts[tile * kCountStride] = 0;
-  R *out = ghost + static_cast<long long>(tile) * TS3;
+  R *out = ghost + static_cast<long long>(tile) * TSB;
   if (start == end) {  // uniform across the work-group
-    for (int i = tid; i < TS3; i += kTileThreads) out[i] = R(0);
+    for (int i = tid; i < TSB / NV; i += kTileThreads) reinterpret_cast<VR *>(out)[i] = VR(0);
     return;
   }
   A *blk = reinterpret_cast<A *>(g_smem);
-  unsigned char *bnd = g_smem + sizeof(A) * ((TS3 + 3) & ~3);
+  unsigned char *bnd = g_smem + sizeof(A) * TSB;
   unsigned long long *U = reinterpret_cast<unsigned long long *>(bnd);
   float *C = reinterpret_cast<float *>(bnd + 8 * T * T);
   double *red = reinterpret_cast<double *>(bnd + spread_lane_bound_lds(S, T));
@@ -197,7 +202,7 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
     sp = sorted[c];
     packed = meta[c].x;
   }
-  for (int i = tid; i < TS3; i += kTileThreads) blk[i] = A(0);
+  for (int i = tid; i < TSB / NV; i += kTileThreads) reinterpret_cast<VA *>(blk)[i] = VA(0);
   const double bound =
       wmax * tile_bound_yz<R, S, T, NWAVES>(sorted, meta, start, end, wc, U, C, red);
   const double scale = bound > 0.0 ? kFix / bound : 1.0;
@@ -249,8 +254,14 @@ k_spread_lane(const SortedParticle<R> *__restrict__ sorted, const int2 *__restri
     packed = npacked;
   }
   __syncthreads();
-  for (int i = tid; i < TS3; i += kTileThreads)
-    out[i] = static_cast<R>(static_cast<double>(blk[i]) * inv_scale);
+  // (the block's last TSB - TS^3 values are zeros that no fold reads)
+  for (int i = tid; i < TSB / NV; i += kTileThreads) {
+    const VA a = reinterpret_cast<const VA *>(blk)[i];
+    VR o;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) o[k] = static_cast<R>(static_cast<double>(a[k]) * inv_scale);
+    reinterpret_cast<VR *>(out)[i] = o;
+  }
 }
 
 // ------------------------------------------------------------------ fold
@@ -267,7 +278,7 @@ k_fold(const R *__restrict__ ghost, FoldTables ft, int M, R *__restrict__ grid) 
   const int x = static_cast<int>(i % M);
   const long long zy = i / M;
   const int y = static_cast<int>(zy % M), z = static_cast<int>(zy / M);
-  const int TS = ft.TS, TS3 = TS * TS * TS, KC = ft.KC;
+  const int TS = ft.TS, TSB = ghost_stride(TS), KC = ft.KC;
   R s = R(0);
   const int nz = ft.count[z], ny = ft.count[y], nx = ft.count[x];
   for (int iz = 0; iz < nz; ++iz) {
@@ -275,11 +286,11 @@ k_fold(const R *__restrict__ ghost, FoldTables ft, int M, R *__restrict__ grid) 
     for (int iy = 0; iy < ny; ++iy) {
       const int cy = ft.cover[y * KC + iy];
       const long long base =
-          static_cast<long long>(((cz >> 6) * ft.ntx + (cy >> 6)) * ft.ntx) * TS3 +
+          static_cast<long long>(((cz >> 6) * ft.ntx + (cy >> 6)) * ft.ntx) * TSB +
           ((cz & 63) * TS + (cy & 63)) * TS;
       for (int ix = 0; ix < nx; ++ix) {
         const int cx = ft.cover[x * KC + ix];
-        s += ghost[base + static_cast<long long>(cx >> 6) * TS3 + (cx & 63)];
+        s += ghost[base + static_cast<long long>(cx >> 6) * TSB + (cx & 63)];
       }
     }
   }
@@ -296,7 +307,7 @@ k_fold(const R *__restrict__ ghost, FoldTables ft, int M, R *__restrict__ grid) 
 template <typename R, int WIN, int S, int T>
 __global__ void __launch_bounds__(kThreads)
 k_fold_tiles(const R *__restrict__ ghost, int M, int ntx, R *__restrict__ grid) {
-  constexpr int TS = T + S - 1, TS3 = TS * TS * TS, T3 = T * T * T;
+  constexpr int TS = T + S - 1, TSB = ghost_stride(TS), T3 = T * T * T;
   constexpr int MAXK = (TS + T - 1) / T;
   constexpr int OFF = Stencil<WIN, S>::OFF;
   const int i = static_cast<int>(blockIdx.y) * kThreads + static_cast<int>(threadIdx.x);
@@ -316,7 +327,7 @@ k_fold_tiles(const R *__restrict__ ghost, int M, int ntx, R *__restrict__ grid) 
         if (cz < TS && cy < TS && cx < TS) {
           const int sz = tz - kz + (tz < kz ? ntx : 0), sy = ty - ky + (ty < ky ? ntx : 0);
           const int sx = tx - kx + (tx < kx ? ntx : 0);
-          v[kz][ky][kx] = ghost[static_cast<long long>((sz * ntx + sy) * ntx + sx) * TS3 +
+          v[kz][ky][kx] = ghost[static_cast<long long>((sz * ntx + sy) * ntx + sx) * TSB +
                                 (cz * TS + cy) * TS + cx];
         }
       }
