@@ -40,15 +40,21 @@ template <typename R> struct Kahan {
   __device__ inline R value() const { return s - c; }
 };
 
+// Work-group size of k_gather_lane: 12 waves in FP32, so that the two
+// work-groups a CU holds at the 12-point tiles of a 96^3 grid give each SIMD
+// six waves (what the kernel's registers allow) to hide the latency of its
+// LDS reads; 8 waves in FP64, whose registers allow five.
+constexpr int gather_threads(int real_size) { return real_size == 4 ? 768 : 512; }
+
 // LDS of k_gather_lane: the block of Phi, then one region that holds the
 // staging tables (row and column offsets) until the block barrier and the
-// groups' factor slots after it; sharing it keeps three 16-point-tile
-// work-groups within a CU's LDS.
+// groups' factor slots after it (sharing it keeps two FP32 work-groups at
+// 16-point tiles within a CU's LDS).
 constexpr int gather_slot(int window, int S) { return window == kGauss ? 2 * S : 6 * S; }
 constexpr size_t gather_lane_lds(int real_size, int window, int S, int T) {
   const size_t TS = T + S - 1;
-  const size_t wf =
-      static_cast<size_t>(real_size) * (kTileThreads / 64) * (64 / S) * gather_slot(window, S);
+  const size_t wf = static_cast<size_t>(real_size) * (gather_threads(real_size) / 64) * (64 / S) *
+                    gather_slot(window, S);
   const size_t tables = 4 * (TS * TS + TS);
   return real_size * ((TS * TS * TS + 3) & ~static_cast<size_t>(3)) +
          (wf > tables ? wf : tables);
@@ -77,7 +83,7 @@ template <int S, typename R> __device__ inline R group_sum_first(R v) {
 // a phase of its own between barriers).  B-spline: three lanes of the group
 // run the recursion, one axis each, and share factors and derivatives.
 template <typename R, int WIN, int S, int T>
-__global__ void __launch_bounds__(kTileThreads)
+__global__ void __launch_bounds__(gather_threads(sizeof(R)))
 k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restrict__ sorted,
               const int2 *__restrict__ meta, const int *__restrict__ offsets, int M, int ntx,
               WindowConsts wc, const double *__restrict__ gscale, int mode, R self_coef,
@@ -86,7 +92,8 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
   constexpr int GROUPS = 64 / S;
   constexpr int OFF = Stencil<WIN, S>::OFF;
   constexpr int SLOT = gather_slot(WIN, S);
-  constexpr int NWAVES = kTileThreads / 64;
+  constexpr int GTH = gather_threads(sizeof(R));
+  constexpr int NWAVES = GTH / 64;
   constexpr bool POW2 = (S & (S - 1)) == 0;
   constexpr size_t BLK = sizeof(R) * ((TS3 + 3) & ~3);
 
@@ -103,11 +110,11 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
   // offsets from row and column tables).
   const int tz = tile / (ntx * ntx), ty = (tile / ntx) % ntx, tx = tile % ntx;
   const int bz = tz * T + OFF, by = ty * T + OFF, bx = tx * T + OFF;
-  constexpr int NST = (TS3 + kTileThreads - 1) / kTileThreads;  // elements per thread
+  constexpr int NST = (TS3 + GTH - 1) / GTH;  // elements per thread
   constexpr int BATCH = sizeof(R) == 4 ? 16 : 8;
   const int start = offsets[tile], end = offsets[tile + 1];
   if (start == end) return;  // uniform across the work-group
-  for (int r = tid; r < TS * TS; r += kTileThreads) {
+  for (int r = tid; r < TS * TS; r += GTH) {
     const int lz = r / TS, ly = r - lz * TS;
     rowtab[r] = (wrap_near(bz + lz, M) * M + wrap_near(by + ly, M)) * M;
   }
@@ -129,7 +136,7 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
     R v[BATCH];
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
-      const int i = tid + (k0 + k) * kTileThreads;
+      const int i = tid + (k0 + k) * GTH;
       if (k0 + k < NST && i < TS3) {
         const int r = i / TS, lx = i - r * TS;
         // byte offset from the grid's base in 32 bits (grids stay below 4 GB)
@@ -140,7 +147,7 @@ k_gather_lane(const R *__restrict__ phi_grid, const SortedParticle<R> *__restric
     }
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
-      const int i = tid + (k0 + k) * kTileThreads;
+      const int i = tid + (k0 + k) * GTH;
       if (k0 + k < NST && i < TS3) blk[i] = v[k];
     }
   }
@@ -314,7 +321,7 @@ hipError_t gather_one(se_plan &p, const void *grid, bool tgt, const double *gsca
     if (e != hipSuccess) return e;
   }
   if (!tgt) stage_begin(p, SE_STAGE_GATHER);
-  launch_on(&p, k_gather_lane<R, WIN, S, T>, p.ntiles, kTileThreads, lds, p.stream,
+  launch_on(&p, k_gather_lane<R, WIN, S, T>, p.ntiles, gather_threads(sizeof(R)), lds, p.stream,
             static_cast<const R *>(grid), static_cast<const SortedParticle<R> *>(sorted), meta,
             offsets, p.prm.M, p.ntx, wc, gscale, mode, static_cast<R>(self), static_cast<R *>(pot),
             static_cast<R *>(vec));

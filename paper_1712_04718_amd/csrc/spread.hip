@@ -84,9 +84,26 @@ __device__ inline double tile_bound_yz(const SortedParticle<R> *__restrict__ sor
   constexpr int TS = T + S - 1;
   const double *kt = wc.kt;  // k(i), from the host (window_bounds)
   const int tid = threadIdx.x;
+  // the first KB particles of each thread stay in registers for the
+  // histogram pass (one read of them instead of two)
+  constexpr int KB = 4;
+  R qv[KB];
+  int pv[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int p = start + tid + k * kTileThreads;
+    qv[k] = R(0);
+    pv[k] = 0;
+    if (p < end) {
+      qv[k] = sorted[p].q;
+      pv[k] = meta[p].x;
+    }
+  }
   for (int i = tid; i < T * T; i += kTileThreads) U[i] = 0ull;
   double m = 0.0;
-  for (int p = start + tid; p < end; p += kTileThreads)
+#pragma unroll
+  for (int k = 0; k < KB; ++k) m = fmax(m, fabs(static_cast<double>(qv[k])));
+  for (int p = start + tid + KB * kTileThreads; p < end; p += kTileThreads)
     m = fmax(m, fabs(static_cast<double>(sorted[p].q)));
   m = wave_reduce0(m, [](double a, double b) { return fmax(a, b); });
   if ((tid & 63) == 0) red[tid >> 6] = m;
@@ -97,13 +114,17 @@ __device__ inline double tile_bound_yz(const SortedParticle<R> *__restrict__ sor
   // |q| 2^20 / qmax through a reciprocal: u falls short of it by at most
   // two FP64 roundings (4e-16 relative), far inside the margin below
   const double inv = 1048576.0 / qmax;
-  for (int p = start + tid; p < end; p += kTileThreads) {
-    const double aq = fabs(static_cast<double>(sorted[p].q));
+  const auto add = [&](R q, int packed) {
+    const double aq = fabs(static_cast<double>(q));
     const double w = fmin(ceil(aq * inv), 1048576.0);
-    const int packed = meta[p].x;
     const int ay = (packed >> 8) & 0xff, az = (packed >> 16) & 0xff;
     if (aq <= qmax) atomicAdd(&U[ay * T + az], static_cast<unsigned long long>(w));
-  }
+  };
+#pragma unroll
+  for (int k = 0; k < KB; ++k)
+    if (start + tid + k * kTileThreads < end) add(qv[k], pv[k]);
+  for (int p = start + tid + KB * kTileThreads; p < end; p += kTileThreads)
+    add(sorted[p].q, meta[p].x);
   __syncthreads();
   // C(jy, az) = sum_ay U(ay, az) k(jy - ay)
   for (int i = tid; i < TS * T; i += kTileThreads) {
