@@ -7,7 +7,9 @@
 // stages, FP32 M <= 128 and FP64 M <= 96; once, in-place stages, FP32
 // M = 144..192 and FP64 M = 120, 128) the x and y passes of each direction
 // run as one plane pass (k_fft_xy_r2c, k_fft_yx_c2r, below), so the sequence
-// is xy, z, yx; other sizes run the five passes:
+// is xy, z, yx; other sizes run the five passes (for compiled M with one
+// LDS buffer of pencils and in-place stages, which leaves room for more
+// work-groups per CU; the run-time plan's kernels ping-pong between two):
 //   x_r2c : pairs of real rows packed as one complex row, transformed, and
 //           split into two half spectra, written as runs along y;
 //   y_fwd : FFT of B contiguous y pencils (consecutive (z, kx));
@@ -294,14 +296,18 @@ __device__ inline void fft_batch_inplace(cplx_t<R> *buf, const cplx_t<R> *tw) {
   }
 }
 
-// Forward FFT of the B pencils in buf0, compile-time (MC > 0) or run-time plan.
+// Forward FFT of the B pencils in buf0 for the five-pass kernels: compiled
+// M in place in buf0 (buf1 is not used), the run-time plan ping-ponging
+// between buf0 and buf1; returns the buffer holding the result.
 template <typename R, int MC, int LGBC>
-__device__ inline cplx_t<R> *fft_any(cplx_t<R> *buf0, cplx_t<R> *buf1, int lgB, const FftPlan &pl,
-                                     const cplx_t<R> *tw) {
-  if constexpr (MC > 0)
-    return fft_batch_ct<R, MC, 1 << LGBC, 1 << LGBC, kThreads, 0, 1>(buf0, buf1, tw);
-  else
+__device__ inline cplx_t<R> *fft_pencils(cplx_t<R> *buf0, cplx_t<R> *buf1, int lgB,
+                                         const FftPlan &pl, const cplx_t<R> *tw) {
+  if constexpr (MC > 0) {
+    fft_batch_inplace<R, MC, 1 << LGBC, 1 << LGBC, kThreads, 0, 1>(buf0, tw);
+    return buf0;
+  } else {
     return fft_batch<R>(buf0, buf1, lgB, pl, tw);
+  }
 }
 
 // i / M: a constant divisor when M is known at compile time, else the
@@ -322,7 +328,7 @@ k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl
   const int M = CT ? MC : pl.M;
   const int lgb = CT ? LGBC : lgB;
   const int K = M / 2 + 1, B = 1 << lgb;
-  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = CT ? b0 : b0 + M * B;  // compiled M: one buffer
   C *twl = b1 + M * B;  // twiddles staged in LDS
   for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
   const long long nrows = static_cast<long long>(M) * M;
@@ -345,7 +351,7 @@ k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl
     }
   }
   __syncthreads();
-  const C *Z = fft_any<R, MC, LGBC>(b0, b1, lgb, pl, twl);
+  const C *Z = fft_pencils<R, MC, LGBC>(b0, b1, lgb, pl, twl);
   // Z = FFT(r1 + i r2): R1[k] = (Z[k] + conj Z[M-k]) / 2, R2[k] = (Z[k] - conj Z[M-k]) / 2i.
   // Rows 2b and 2b+1 are (z, y) and (z, y+1) with y even (M is even), so the
   // two half spectra land side by side in C[z][k][y]: one 2-element store.
@@ -374,7 +380,7 @@ k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl
   const int M = CT ? MC : pl.M;
   const int lgb = CT ? LGBC : lgB;
   const int K = M / 2 + 1, B = 1 << lgb;
-  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = CT ? b0 : b0 + M * B;  // compiled M: one buffer
   C *twl = b1 + M * B;  // twiddles staged in LDS
   for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
   const long long nrows = static_cast<long long>(M) * M;
@@ -406,7 +412,7 @@ k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl
     }
   }
   __syncthreads();
-  const C *Z = fft_any<R, MC, LGBC>(b0, b1, lgb, pl, twl);
+  const C *Z = fft_pencils<R, MC, LGBC>(b0, b1, lgb, pl, twl);
   for (int i = threadIdx.x; i < 2 * B * M; i += kThreads) {
     const int r = div_M<MC>(i, pl), xk = i - r * M;
     const long long gr = row0 + r;
@@ -466,7 +472,7 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
   const int M = CT ? MC : pl.M;
   const int lgb = CT ? LGBC : lgB;
   const int K = M / 2 + 1, B = 1 << lgb;
-  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = CT ? b0 : b0 + M * B;  // compiled M: one buffer
   C *twl = b1 + M * B;  // twiddles staged in LDS
   for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
   // B consecutive (z, kx) pencils, each M contiguous values along y
@@ -492,7 +498,7 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
     }
   }
   __syncthreads();
-  const C *Z = fft_any<R, MC, LGBC>(b0, b1, lgb, pl, twl);
+  const C *Z = fft_pencils<R, MC, LGBC>(b0, b1, lgb, pl, twl);
   for (int i = threadIdx.x; i < M * B; i += kThreads) {
     const int y = i >> lgb, b = i & (B - 1);
     if (c0 + b < npen) {
@@ -770,7 +776,7 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
   const int lgb = CT ? LGBC : lgB;
   const int K = M / 2 + 1, B = 1 << lgb;
   const int npen = M * K;
-  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = b0 + M * B;
+  C *b0 = reinterpret_cast<C *>(f_smem), *b1 = CT ? b0 : b0 + M * B;  // compiled M: one buffer
   C *twl = b1 + M * B;  // twiddles staged in LDS
   // the per-axis tables of the influence function too, so that the scaling
   // step between the two transforms needs no global memory round trip
@@ -801,8 +807,8 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
     }
   }
   __syncthreads();
-  C *Z = fft_any<R, MC, LGBC>(b0, b1, lgb, pl, twl);
-  C *other = (Z == b0) ? b1 : b0;
+  C *Z = fft_pencils<R, MC, LGBC>(b0, b1, lgb, pl, twl);
+  C *other = (Z == b0) ? b1 : b0;  // Z itself for compiled M
   // signed wave number of an axis index (0 on the Nyquist plane)
   const auto signed_k = [&](int n) {
     return 2 * n == M ? 0.0 : two_pi_over_L * static_cast<double>(2 * n < M ? n : n - M);
@@ -838,7 +844,7 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
     Z[i] = v;  // holds conj(w * G^)
   }
   __syncthreads();
-  const C *Y = fft_any<R, MC, LGBC>(Z, other, lgb, pl, twl);
+  const C *Y = fft_pencils<R, MC, LGBC>(Z, other, lgb, pl, twl);
   for (int i = threadIdx.x; i < M * B; i += kThreads) {
     const int z = i >> lgb, b = i & (B - 1);
     if (c0 + b < npen) out[z * zs + c0 + b] = cconj(Y[i]);
@@ -884,7 +890,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
                                  static_cast<int>(lds))) != hipSuccess)
       return e;
   }
-  const size_t lds_z = sizeof(C) * (2 * MC * (1 << LZ) + MC) + 2 * sizeof(double) * MC;
+  const size_t lds_z = sizeof(C) * (MC * (1 << LZ) + MC) + 2 * sizeof(double) * MC;
   C *spec = static_cast<C *>(p.buf.spec);
   const C *tw = static_cast<const C *>(p.buf.twiddle);
   stage_begin(p, SE_STAGE_FFT_XY);
@@ -924,6 +930,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
 
 template <typename R, int MC>
 hipError_t fft_run(se_plan &p, double *E_dev) {
+  static_assert(MC == 0 || fft_compiled(MC), "every compiled grid size is in kCompiledM");
   if constexpr (MC > 0 && plane_fits<R, MC>()) return fft_run_planes<R, MC, false>(p, E_dev);
   if constexpr (MC > 0 && !plane_fits<R, MC>() && plane1_fits<R, MC>())
     return fft_run_planes<R, MC, true>(p, E_dev);
@@ -938,8 +945,11 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
   // are sized from the plan's.
   if (MC > 0 && (MC != M || LX != lx || LY != ly || LZ != lz || p.fft_threads != kThreads))
     return hipErrorInvalidValue;
+  // the plan sized the batches for one buffer exactly when M is compiled
+  if (MC == 0 && fft_compiled(M)) return hipErrorInvalidValue;
   const int Bx = 1 << lx, By = 1 << ly;
-  const auto lds_of = [M](int lg) { return sizeof(C) * (2 * M * (1 << lg) + M); };
+  // pencil buffers: one for compiled M, two for the run-time plan
+  const auto lds_of = [M](int lg) { return sizeof(C) * ((MC > 0 ? 1 : 2) * M * (1 << lg) + M); };
   const auto lds_zof = [M, lds_of](int lg) { return lds_of(lg) + 2 * sizeof(double) * M; };
   C *spec = static_cast<C *>(p.buf.spec);
   const C *tw = static_cast<const C *>(p.buf.twiddle);

@@ -371,16 +371,28 @@ constexpr int fft_batch_cap(int pass, int real_size) {
   return pass == kPassZ && real_size == 4 ? 8 : 4;
 }
 
+// Grid sizes whose FFT kernels are compiled for their M (the others run
+// the run-time plan's kernels).
+constexpr int kCompiledM[] = {16,  24,  32,  40,  48,  64,  80,  96,  120, 128, 144,
+                              160, 192, 216, 240, 256, 288, 320, 384, 432, 480, 512};
+constexpr bool fft_compiled(int M) {
+  for (int m : kCompiledM)
+    if (m == M) return true;
+  return false;
+}
+
 // Pencils per FFT work-group of one pass, as log2: B a power of two, at most
 // fft_batch_cap(pass, real_size), with M * B <= 16 * kThreads (elements per thread when
-// loading) and two LDS buffers of M x B complex plus the M twiddles (and,
-// in the z pass, the two FP64 axis tables of the influence function)
-// within 64 KB.
+// loading) and the LDS buffers of M x B complex (one for the compiled
+// kernels, whose radix stages run in place; two for the run-time plan's,
+// which ping-pong) plus the M twiddles (and, in the z pass, the two FP64
+// axis tables of the influence function) within 64 KB.
 constexpr int fft_lgb(int M, int real_size, int pass) {
   const int tables = pass == kPassZ ? 2 * 8 * M : 0;
+  const int nbuf = fft_compiled(M) ? 1 : 2;
   int B = fft_batch_cap(pass, real_size);
   while (B > 1 &&
-         (M * B > 16 * kThreads || (2 * M * B + M) * 2 * real_size + tables > 65536))
+         (M * B > 16 * kThreads || (nbuf * M * B + M) * 2 * real_size + tables > 65536))
     B >>= 1;
   int lg = 0;
   while ((1 << lg) < B) ++lg;

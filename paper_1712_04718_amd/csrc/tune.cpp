@@ -250,13 +250,13 @@ se_status se_cost_model_mi355x(int dtype, se_cost_model *m) {
   // Non-negative least-squares fits of the model to se_kspace and se_rs_eval
   // times on an MI355X (calibrate.py of this package; 60 k-space and 15
   // real-space configurations per precision).
-  // Largest relative deviation of the fit: 28% (FP32), 23% (FP64).
+  // Largest relative deviation of the fit: 27% (FP32), 23% (FP64).
   if (dtype == SE_FP32) {
-    *m = se_cost_model{2.6235e-05, 4.4756e-11, 1.4806e-12, 4.1938e-09, 7.3363e-13,
-                       3.7230e-05, 9.7986e-11, 3.0431e-13, 2.8861e-12, 0.0, 1.2697e-12};
+    *m = se_cost_model{2.6945e-05, 3.2147e-11, 1.2664e-12, 4.2873e-09, 7.6776e-13,
+                       3.8105e-05, 9.0256e-11, 3.0490e-13, 2.4347e-12, 0.0, 1.4182e-12};
   } else if (dtype == SE_FP64) {
-    *m = se_cost_model{3.2834e-05, 0.0, 7.6880e-12, 1.3704e-08, 2.1280e-12,
-                       3.5091e-05, 1.4049e-10, 4.4957e-13, 6.4146e-12, 0.0, 2.0063e-12};
+    *m = se_cost_model{3.3205e-05, 0.0, 7.5893e-12, 1.3672e-08, 2.1569e-12,
+                       3.6594e-05, 1.3720e-10, 4.4701e-13, 6.3684e-12, 0.0, 1.9237e-12};
   } else {
     return bad("unknown dtype");
   }
