@@ -41,6 +41,20 @@ extern __shared__ __align__(16) unsigned char f_smem[];
 // (M * B <= 16 * threads for every plan, see fft_lgb).
 constexpr int kMaxPerThread = 16;
 
+// Work-group size of the z pass: 512 threads for compiled M >= 384, whose
+// work-groups each hold 1700-3500 values through the twenty-odd in-place
+// stages of the pass (measured: 242 -> 209 us at M = 432, 149 -> 129 us at
+// M = 384, FP32), else kThreads (at M = 192-288 the wider work-groups were
+// no faster or slower).
+constexpr int zpass_threads(int MC) { return MC >= 384 ? 512 : kThreads; }
+
+// Work-group size of the five-pass x and y kernels: 512 threads for FP64 at
+// compiled M >= 384 (M = 432: inverse y 331 -> 254 us, inverse x 293 -> 258
+// us), else kThreads (FP32 lost 5-15% with 512 at M = 384 and 432).
+template <typename R> constexpr int xy_threads(int MC) {
+  return sizeof(R) == 8 && MC >= 384 ? 512 : kThreads;
+}
+
 template <typename C> __device__ inline C cmul(C a, C b) {
   C r;
   r.x = a.x * b.x - a.y * b.y;
@@ -299,11 +313,11 @@ __device__ inline void fft_batch_inplace(cplx_t<R> *buf, const cplx_t<R> *tw) {
 // Forward FFT of the B pencils in buf0 for the five-pass kernels: compiled
 // M in place in buf0 (buf1 is not used), the run-time plan ping-ponging
 // between buf0 and buf1; returns the buffer holding the result.
-template <typename R, int MC, int LGBC>
+template <typename R, int MC, int LGBC, int NT = kThreads>
 __device__ inline cplx_t<R> *fft_pencils(cplx_t<R> *buf0, cplx_t<R> *buf1, int lgB,
                                          const FftPlan &pl, const cplx_t<R> *tw) {
   if constexpr (MC > 0) {
-    fft_batch_inplace<R, MC, 1 << LGBC, 1 << LGBC, kThreads, 0, 1>(buf0, tw);
+    fft_batch_inplace<R, MC, 1 << LGBC, 1 << LGBC, NT, 0, 1>(buf0, tw);
     return buf0;
   } else {
     return fft_batch<R>(buf0, buf1, lgB, pl, tw);
@@ -320,42 +334,43 @@ template <int MC> __device__ inline int div_M(int i, const FftPlan &pl) {
 // ---------------------------------------------------------------- x passes
 
 template <typename R, int MC, int LGBC>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(xy_threads<R>(MC))
 k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB,
             const cplx_t<R> *__restrict__ tw_g) {
   using C = cplx_t<R>;
+  constexpr int NT = xy_threads<R>(MC), NPT = 16 * kThreads / NT;
   constexpr bool CT = MC > 0;
   const int M = CT ? MC : pl.M;
   const int lgb = CT ? LGBC : lgB;
   const int K = M / 2 + 1, B = 1 << lgb;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = CT ? b0 : b0 + M * B;  // compiled M: one buffer
   C *twl = b1 + M * B;  // twiddles staged in LDS
-  for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
+  for (int i = threadIdx.x; i < M; i += NT) twl[i] = tw_g[i];
   const long long nrows = static_cast<long long>(M) * M;
   const long long row0 = static_cast<long long>(xcd_local(blockIdx.x, gridDim.x)) * 2 * B;
   // row r of the batch goes to pencil r/2, real part for even r, imag for odd;
   // all loads are issued before the first LDS store
-  R v[2 * kMaxPerThread];
+  R v[2 * NPT];
 #pragma unroll
-  for (int k = 0; k < 2 * kMaxPerThread; ++k) {
-    const int i = threadIdx.x + k * kThreads;
+  for (int k = 0; k < 2 * NPT; ++k) {
+    const int i = threadIdx.x + k * NT;
     const long long gr = row0 + div_M<MC>(i, pl);
     v[k] = (i < 2 * B * M && gr < nrows) ? grid[row0 * M + i] : R(0);
   }
 #pragma unroll
-  for (int k = 0; k < 2 * kMaxPerThread; ++k) {
-    const int i = threadIdx.x + k * kThreads;
+  for (int k = 0; k < 2 * NPT; ++k) {
+    const int i = threadIdx.x + k * NT;
     if (i < 2 * B * M) {
       const int r = div_M<MC>(i, pl), xk = i - r * M;
       reinterpret_cast<R *>(&b0[xk * B + (r >> 1)])[r & 1] = v[k];
     }
   }
   __syncthreads();
-  const C *Z = fft_pencils<R, MC, LGBC>(b0, b1, lgb, pl, twl);
+  const C *Z = fft_pencils<R, MC, LGBC, NT>(b0, b1, lgb, pl, twl);
   // Z = FFT(r1 + i r2): R1[k] = (Z[k] + conj Z[M-k]) / 2, R2[k] = (Z[k] - conj Z[M-k]) / 2i.
   // Rows 2b and 2b+1 are (z, y) and (z, y+1) with y even (M is even), so the
   // two half spectra land side by side in C[z][k][y]: one 2-element store.
-  for (int i = threadIdx.x; i < B * K; i += kThreads) {
+  for (int i = threadIdx.x; i < B * K; i += NT) {
     const int k = i >> lgb, b = i & (B - 1);
     const long long gr = row0 + 2 * b;
     if (gr >= nrows) continue;
@@ -372,22 +387,23 @@ k_fft_x_r2c(const R *__restrict__ grid, cplx_t<R> *__restrict__ spec, FftPlan pl
 }
 
 template <typename R, int MC, int LGBC>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(xy_threads<R>(MC))
 k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl, int lgB,
             const cplx_t<R> *__restrict__ tw_g) {
   using C = cplx_t<R>;
+  constexpr int NT = xy_threads<R>(MC), NPT = 16 * kThreads / NT;
   constexpr bool CT = MC > 0;
   const int M = CT ? MC : pl.M;
   const int lgb = CT ? LGBC : lgB;
   const int K = M / 2 + 1, B = 1 << lgb;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = CT ? b0 : b0 + M * B;  // compiled M: one buffer
   C *twl = b1 + M * B;  // twiddles staged in LDS
-  for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
+  for (int i = threadIdx.x; i < M; i += NT) twl[i] = tw_g[i];
   const long long nrows = static_cast<long long>(M) * M;
   const long long row0 = static_cast<long long>(xcd_local(blockIdx.x, gridDim.x)) * 2 * B;
   // Z[k] = R1[k] + i R2[k] on 0..M/2 and conj(R1[M-k]) + i conj(R2[M-k]) above;
   // stored conjugated for the inverse transform.
-  for (int i = threadIdx.x; i < B * K; i += kThreads) {
+  for (int i = threadIdx.x; i < B * K; i += NT) {
     const int k = i >> lgb, b = i & (B - 1);
     const long long gr = row0 + 2 * b;
     C r1, r2;
@@ -412,8 +428,8 @@ k_fft_x_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid, FftPlan pl
     }
   }
   __syncthreads();
-  const C *Z = fft_pencils<R, MC, LGBC>(b0, b1, lgb, pl, twl);
-  for (int i = threadIdx.x; i < 2 * B * M; i += kThreads) {
+  const C *Z = fft_pencils<R, MC, LGBC, NT>(b0, b1, lgb, pl, twl);
+  for (int i = threadIdx.x; i < 2 * B * M; i += NT) {
     const int r = div_M<MC>(i, pl), xk = i - r * M;
     const long long gr = row0 + r;
     if (gr >= nrows) continue;
@@ -464,25 +480,26 @@ __device__ inline void write_energy(const EnergyOut &eo) {
 }
 
 template <typename R, int MC, int LGBC, bool INV>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(xy_threads<R>(MC))
 k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__restrict__ tw_g,
         EnergyOut eo) {
   using C = cplx_t<R>;
+  constexpr int NT = xy_threads<R>(MC), NPT = 16 * kThreads / NT;
   constexpr bool CT = MC > 0;
   const int M = CT ? MC : pl.M;
   const int lgb = CT ? LGBC : lgB;
   const int K = M / 2 + 1, B = 1 << lgb;
   C *b0 = reinterpret_cast<C *>(f_smem), *b1 = CT ? b0 : b0 + M * B;  // compiled M: one buffer
   C *twl = b1 + M * B;  // twiddles staged in LDS
-  for (int i = threadIdx.x; i < M; i += kThreads) twl[i] = tw_g[i];
+  for (int i = threadIdx.x; i < M; i += NT) twl[i] = tw_g[i];
   // B consecutive (z, kx) pencils, each M contiguous values along y
   const int npen = M * K;
   const int c0 = xcd_local(blockIdx.x, gridDim.x) * B;
   {
-    C v[kMaxPerThread];
+    C v[NPT];
 #pragma unroll
-    for (int k = 0; k < kMaxPerThread; ++k) {
-      const int i = threadIdx.x + k * kThreads;
+    for (int k = 0; k < NPT; ++k) {
+      const int i = threadIdx.x + k * NT;
       const int y = i >> lgb, b = i & (B - 1);
       if (i < M * B && c0 + b < npen) {
         v[k] = spec[static_cast<long long>(c0 + b) * M + y];
@@ -492,14 +509,14 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
       }
     }
 #pragma unroll
-    for (int k = 0; k < kMaxPerThread; ++k) {
-      const int i = threadIdx.x + k * kThreads;
+    for (int k = 0; k < NPT; ++k) {
+      const int i = threadIdx.x + k * NT;
       if (i < M * B) b0[i] = v[k];
     }
   }
   __syncthreads();
-  const C *Z = fft_pencils<R, MC, LGBC>(b0, b1, lgb, pl, twl);
-  for (int i = threadIdx.x; i < M * B; i += kThreads) {
+  const C *Z = fft_pencils<R, MC, LGBC, NT>(b0, b1, lgb, pl, twl);
+  for (int i = threadIdx.x; i < M * B; i += NT) {
     const int y = i >> lgb, b = i & (B - 1);
     if (c0 + b < npen) {
       C v = Z[i];
@@ -507,7 +524,7 @@ k_fft_y(cplx_t<R> *__restrict__ spec, FftPlan pl, int lgB, const cplx_t<R> *__re
       spec[static_cast<long long>(c0 + b) * M + y] = v;
     }
   }
-  if (INV && blockIdx.x == 0 && eo.E) write_energy<kThreads>(eo);
+  if (INV && blockIdx.x == 0 && eo.E) write_energy<NT>(eo);
 }
 
 // ------------------------------------------------- fused x-y plane passes
@@ -765,12 +782,13 @@ k_fft_yx_c2r(const cplx_t<R> *__restrict__ spec, R *__restrict__ grid,
 // is zero (its derivative is not defined on the grid).  Otherwise out = in
 // and the energy partials go to epart.
 template <typename R, int MC, int LGBC>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(zpass_threads(MC))
 k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
               const cplx_t<R> *__restrict__ tw_g, const double *__restrict__ axis_f,
               const double *__restrict__ axis_k2, double wscale, double *__restrict__ epart,
               int ik, double two_pi_over_L) {
   using C = cplx_t<R>;
+  constexpr int ZT = zpass_threads(MC), ZPT = 16 * kThreads / ZT;
   constexpr bool CT = MC > 0;
   const int M = CT ? MC : pl.M;
   const int lgb = CT ? LGBC : lgB;
@@ -781,7 +799,7 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
   // the per-axis tables of the influence function too, so that the scaling
   // step between the two transforms needs no global memory round trip
   double *af = reinterpret_cast<double *>(twl + M), *ak2 = af + M;
-  for (int i = threadIdx.x; i < M; i += kThreads) {
+  for (int i = threadIdx.x; i < M; i += ZT) {
     twl[i] = tw_g[i];
     af[i] = axis_f[i];
     ak2[i] = axis_k2[i];
@@ -789,10 +807,10 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
   const int c0 = xcd_local(blockIdx.x, gridDim.x) * B;  // pencils c = kx M + ky, contiguous in a z plane
   const long long zs = static_cast<long long>(M) * K;
   {
-    C v[kMaxPerThread];
+    C v[ZPT];
 #pragma unroll
-    for (int k = 0; k < kMaxPerThread; ++k) {
-      const int i = threadIdx.x + k * kThreads;
+    for (int k = 0; k < ZPT; ++k) {
+      const int i = threadIdx.x + k * ZT;
       const int z = i >> lgb, b = i & (B - 1);
       if (i < M * B && c0 + b < npen) {
         v[k] = in[z * zs + c0 + b];
@@ -801,13 +819,13 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
       }
     }
 #pragma unroll
-    for (int k = 0; k < kMaxPerThread; ++k) {
-      const int i = threadIdx.x + k * kThreads;
+    for (int k = 0; k < ZPT; ++k) {
+      const int i = threadIdx.x + k * ZT;
       if (i < M * B) b0[i] = v[k];
     }
   }
   __syncthreads();
-  C *Z = fft_pencils<R, MC, LGBC>(b0, b1, lgb, pl, twl);
+  C *Z = fft_pencils<R, MC, LGBC, ZT>(b0, b1, lgb, pl, twl);
   C *other = (Z == b0) ? b1 : b0;  // Z itself for compiled M
   // signed wave number of an axis index (0 on the Nyquist plane)
   const auto signed_k = [&](int n) {
@@ -815,7 +833,7 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
   };
 
   double e = 0.0;
-  for (int i = threadIdx.x; i < M * B; i += kThreads) {
+  for (int i = threadIdx.x; i < M * B; i += ZT) {
     const int kz = i >> lgb, b = i & (B - 1);
     const int c = c0 + b;
     C v = Z[i];
@@ -844,8 +862,8 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
     Z[i] = v;  // holds conj(w * G^)
   }
   __syncthreads();
-  const C *Y = fft_pencils<R, MC, LGBC>(Z, other, lgb, pl, twl);
-  for (int i = threadIdx.x; i < M * B; i += kThreads) {
+  const C *Y = fft_pencils<R, MC, LGBC, ZT>(Z, other, lgb, pl, twl);
+  for (int i = threadIdx.x; i < M * B; i += ZT) {
     const int z = i >> lgb, b = i & (B - 1);
     if (c0 + b < npen) out[z * zs + c0 + b] = cconj(Y[i]);
   }
@@ -854,12 +872,12 @@ k_fft_z_scale(const cplx_t<R> *in, cplx_t<R> *out, FftPlan pl, int lgB,
   // energy: one partial per block (a fixed tree over the lanes of each wave,
   // then the waves in order), added in a fixed order by the next pass
   e = wave_reduce0(e, [](double a, double b) { return a + b; });
-  __shared__ double wred[kThreads / 64];
+  __shared__ double wred[ZT / 64];
   if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = e;
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) s += wred[w];
+    for (int w = 0; w < ZT / 64; ++w) s += wred[w];
     epart[blockIdx.x] = s;
   }
 }
@@ -904,7 +922,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
     // which the potential's z pass then overwrites); not timed
     C *spec2 = static_cast<C *>(p.buf.spec2);
     for (int d = 0; d < 3; ++d) {
-      launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, p.fft_threads, lds_z, p.stream, 
+      launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, zpass_threads(MC), lds_z, p.stream, 
           spec, spec2, p.fft, LZ, tw, static_cast<const double *>(p.buf.axis_f),
           static_cast<const double *>(p.buf.axis_k2), p.wscale, nullptr, d, tpl);
       launch_on(&p, k_fft_yx_c2r<R, MC, NT, NSI, ONE>, ninv, NT, lds, p.stream, 
@@ -914,7 +932,7 @@ hipError_t fft_run_planes(se_plan &p, double *E_dev) {
     }
   }
   stage_begin(p, SE_STAGE_FFT_Z_SCALE);
-  launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, p.fft_threads, lds_z, p.stream, 
+  launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, zpass_threads(MC), lds_z, p.stream, 
       spec, spec, p.fft, LZ, tw, static_cast<const double *>(p.buf.axis_f),
       static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks, -1, tpl);
   stage_end(p, SE_STAGE_FFT_Z_SCALE);
@@ -956,14 +974,14 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
   const int xblocks = (M * M + 2 * Bx - 1) / (2 * Bx);
   hipError_t e = hipSuccess;
   stage_begin(p, SE_STAGE_FFT_X);
-  launch_on(&p, k_fft_x_r2c<R, MC, LX>, xblocks, p.fft_threads, lds_of(lx), p.stream, 
+  launch_on(&p, k_fft_x_r2c<R, MC, LX>, xblocks, xy_threads<R>(MC), lds_of(lx), p.stream, 
       static_cast<const R *>(p.buf.grid), spec, p.fft, lx, tw);
   stage_end(p, SE_STAGE_FFT_X);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const unsigned yg = static_cast<unsigned>((M * K + By - 1) / By);
   const EnergyOut none{nullptr, 0, nullptr, 0, 0.0, nullptr};
   stage_begin(p, SE_STAGE_FFT_Y);
-  launch_on(&p, k_fft_y<R, MC, LY, false>, yg, p.fft_threads, lds_of(ly), p.stream, spec, p.fft, ly, tw, none);
+  launch_on(&p, k_fft_y<R, MC, LY, false>, yg, xy_threads<R>(MC), lds_of(ly), p.stream, spec, p.fft, ly, tw, none);
   stage_end(p, SE_STAGE_FFT_Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double tpl = 2.0 * M_PI / p.prm.L;
@@ -972,19 +990,19 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
     // which the potential's z pass then overwrites); not timed
     C *spec2 = static_cast<C *>(p.buf.spec2);
     for (int d = 0; d < 3; ++d) {
-      launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, p.fft_threads, lds_zof(lz), p.stream, 
+      launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, zpass_threads(MC), lds_zof(lz), p.stream, 
           spec, spec2, p.fft, lz, tw, static_cast<const double *>(p.buf.axis_f),
           static_cast<const double *>(p.buf.axis_k2), p.wscale, nullptr, d, tpl);
-      launch_on(&p, k_fft_y<R, MC, LY, true>, yg, p.fft_threads, lds_of(ly), p.stream, spec2, p.fft, ly, tw,
+      launch_on(&p, k_fft_y<R, MC, LY, true>, yg, xy_threads<R>(MC), lds_of(ly), p.stream, spec2, p.fft, ly, tw,
                                                                            none);
-      launch_on(&p, k_fft_x_c2r<R, MC, LX>, xblocks, p.fft_threads, lds_of(lx), p.stream, 
+      launch_on(&p, k_fft_x_c2r<R, MC, LX>, xblocks, xy_threads<R>(MC), lds_of(lx), p.stream, 
           spec2, static_cast<R *>(p.buf.field) + static_cast<long long>(d) * M * M * M, p.fft, lx,
           tw);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
   stage_begin(p, SE_STAGE_FFT_Z_SCALE);
-  launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, p.fft_threads, lds_zof(lz), p.stream, 
+  launch_on(&p, k_fft_z_scale<R, MC, LZ>, p.zfft_blocks, zpass_threads(MC), lds_zof(lz), p.stream, 
       spec, spec, p.fft, lz, tw, static_cast<const double *>(p.buf.axis_f),
       static_cast<const double *>(p.buf.axis_k2), p.wscale, p.buf.part + p.bin_blocks, -1, tpl);
   stage_end(p, SE_STAGE_FFT_Z_SCALE);
@@ -993,11 +1011,11 @@ hipError_t fft_run(se_plan &p, double *E_dev) {
   const EnergyOut eo{p.buf.part + p.bin_blocks, p.zfft_blocks, p.buf.part, p.bin_parts, self_coef,
                      E_dev};
   stage_begin(p, SE_STAGE_IFFT_Y);
-  launch_on(&p, k_fft_y<R, MC, LY, true>, yg, p.fft_threads, lds_of(ly), p.stream, spec, p.fft, ly, tw, eo);
+  launch_on(&p, k_fft_y<R, MC, LY, true>, yg, xy_threads<R>(MC), lds_of(ly), p.stream, spec, p.fft, ly, tw, eo);
   stage_end(p, SE_STAGE_IFFT_Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   stage_begin(p, SE_STAGE_IFFT_X);
-  launch_on(&p, k_fft_x_c2r<R, MC, LX>, xblocks, p.fft_threads, lds_of(lx), p.stream, 
+  launch_on(&p, k_fft_x_c2r<R, MC, LX>, xblocks, xy_threads<R>(MC), lds_of(lx), p.stream, 
       spec, static_cast<R *>(p.buf.grid), p.fft, lx, tw);
   stage_end(p, SE_STAGE_IFFT_X);
   return hipGetLastError();
