@@ -355,8 +355,10 @@ constexpr int kGatherTargets = 2;         // points of plan.tgt: phi (no self te
 constexpr int kGatherIkX = 3;             // +d (d = 0, 1, 2): out_vec[3 n + d] = scale q * (field d at n)
 
 constexpr int kMaxSplineOrder = 8;  // largest SPME order built
-constexpr int kThreads = 256;      // work-group size of the binning, fold and FFT kernels
-constexpr int kTileThreads = 512;  // work-group size of the tile spread and gather kernels
+constexpr int kThreads = 256;      // work-group size of the binning, fold and FFT kernels (the
+                                   // five-pass FFT at M >= 384 widens some passes to 512)
+constexpr int kTileThreads = 512;  // work-group size of the tile spread kernel (the gather's
+                                   // depends on the precision)
 
 // Most pencils per FFT work-group, per pass.  Lanes run over the B pencils
 // fastest, so a wave reads 64 / B consecutive elements of each pencil: the
@@ -365,7 +367,8 @@ constexpr int kTileThreads = 512;  // work-group size of the tile spread and gat
 // pass took 13.4 instead of 15.9 us, at M = 432 164 instead of 220 us, the
 // inverse x pass 212 instead of 308 us); FP32 z columns take B = 8 (22.5
 // against 24.6 us at M = 192), FP64 ones B = 4 (33.6 against 41.6 us, the
-// LDS per work-group halved).
+// LDS per work-group halved).  (Measured with two pencil buffers; with the
+// one buffer of the compiled sizes, 16 FP32 z columns were slower again.)
 enum FftPass { kPassX = 0, kPassY = 1, kPassZ = 2 };
 constexpr int fft_batch_cap(int pass, int real_size) {
   return pass == kPassZ && real_size == 4 ? 8 : 4;

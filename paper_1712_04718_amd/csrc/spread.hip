@@ -333,7 +333,9 @@ k_fold_tiles(const R *__restrict__ ghost, int M, int ntx, R *__restrict__ grid) 
   constexpr int TS = T + S - 1, TSB = ghost_stride(TS);
   constexpr int MAXK = (TS + T - 1) / T;
   constexpr int OFF = Stencil<WIN, S>::OFF;
-  constexpr int ZU = 4;  // z planes whose loads are issued together
+  // z planes whose loads are issued together (at M = 432, 16-point tiles:
+  // 244 us with two, 253 with four; at 12-point tiles four beat two)
+  constexpr int ZU = T >= 16 ? 2 : 4;
   static_assert(T * T <= kThreads, "one thread per (x, y) column of a tile");
   const int i = static_cast<int>(threadIdx.x);
   if (i >= T * T) return;
