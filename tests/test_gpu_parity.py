@@ -19,6 +19,11 @@ from paper_1712_04718_amd import SEPlan
 pytestmark = pytest.mark.gpu
 
 DTYPES = [torch.float32, torch.float64]
+# Relative rms difference allowed between ik and analytic forces at P = 6,
+# xi = M / 4L, 0.07 (M/4)^3 charges in L = 10: the FP64 oracle gives
+# 4.5e-3 to 5.4e-3 for this recipe at M = 48, 64 and 96, the library 7.4e-3
+# at M = 384; a wrong component, sign or scale of the field gives order one.
+IK_VS_ANALYTIC = 2e-2
 
 
 def _rand(N, L, seed, neutral=True):
@@ -96,6 +101,43 @@ def test_large_grid_sizes(M):
     print(f"[parity] large grid M={M} errors {errs}", flush=True)
     for dtype, e in errs.items():
         assert max(e) < TOL[dtype], (M, dtype, e)
+
+
+@pytest.mark.timeout(300)
+def test_ik_forces_wide_passes():
+    """At M = 384 the z pass (both precisions) and, in FP64, the x and y
+    passes run 512-thread work-groups, for the three field components of the
+    ik forces as well.  An oracle at this size would take minutes, so the
+    check needs none: ik forces against the analytic forces of the same
+    parameters (the two differentiations differ by the method's error,
+    IK_VS_ANALYTIC), and FP32 against FP64."""
+    L, M, P = 10.0, 384, 6
+    xi = M / (4 * L)
+    N = int(0.07 * (M / 4) ** 3)
+    x, q = _rand(N, L, 1384)
+    x = x.astype(np.float32).astype(np.float64)
+    q = q.astype(np.float32).astype(np.float64)
+    print(f"[ik] wide passes N={N} M={M} P={P}", flush=True)
+    forces = {}
+    for dtype in DTYPES:
+        xs, qs = to_dev(x, q, dtype)
+        plan = SEPlan(M, P, L, xi, dtype=dtype, n_max=N, ik_force=True)
+        ref = SEPlan(M, P, L, xi, dtype=dtype, n_max=N)
+        _, _, F = plan.kspace(xs, qs)
+        _, _, Fa = ref.kspace(xs, qs)
+        torch.cuda.synchronize()
+        forces[dtype] = (F.double().cpu().numpy(), Fa.double().cpu().numpy())
+        plan.close()
+        ref.close()
+        torch.cuda.empty_cache()
+    F64, Fa64 = forces[torch.float64]
+    F32, Fa32 = forces[torch.float32]
+    d_method = O.rel_rms(F64, Fa64)
+    e32 = array_errors(F32, F64)
+    print(f"[ik] wide passes: ik vs analytic {d_method:.3e}, FP32 vs FP64 {e32}", flush=True)
+    assert d_method < IK_VS_ANALYTIC, d_method
+    assert max(e32) < TOL[torch.float32], e32
+    assert max(array_errors(Fa32, Fa64)) < TOL[torch.float32]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
